@@ -1,0 +1,77 @@
+"""Assemble a discretised three-body problem from its physical parameters.
+
+Grid (reading: n counts interior unknowns; n + 2 Gauss-Lobatto points including
+the two Dirichlet end points), coefficients in units with heavy mass 1, the
+Gaussian pair potential -V0 exp(-r^2/(2 w^2)), and the default preconditioner
+shift (the two-body ground energy on the y grid with the heavy-light reduced
+mass).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import cheb, operator, physics, precond, twobody
+
+
+@dataclass
+class Problem:
+    ndim: int
+    n: tuple
+    L: tuple
+    cx: float
+    cy: float
+    mu_hl: float
+    shape: str
+    v0: float
+    width: float
+    D2: tuple
+    grids: tuple
+    V: np.ndarray
+
+    @property
+    def N(self):
+        return int(np.prod(self.n))
+
+    def apply(self, X):
+        if self.ndim == 1:
+            return operator.apply_1d(self.D2[0], self.D2[1], self.cx, self.cy, self.V, X)
+        return operator.apply_2d(self.D2, self.cx, self.cy, self.V, X)
+
+    def kron(self):
+        if self.ndim == 1:
+            return operator.kron_1d(self.D2[0], self.D2[1], self.cx, self.cy, self.V)
+        return operator.kron_2d(self.D2, self.cx, self.cy, self.V)
+
+    def two_body_shift(self):
+        """Ground energy of -(1/(2 mu_hl)) d^2/dr^2 + u(|r|) on the y grid."""
+        k = 1 if self.ndim == 1 else 2
+        return twobody.ground_energy(self.n[k], self.L[k], self.mu_hl, self.shape,
+                                     self.v0, self.width)
+
+    def preconditioner(self, sigma=None):
+        if self.ndim != 1:
+            raise NotImplementedError("the kinetic Sylvester preconditioner is 1D")
+        if sigma is None:
+            sigma = self.two_body_shift()
+        return precond.KineticSylvester(self.D2[0], self.D2[1], self.cx, self.cy, sigma)
+
+
+def make_problem(ndim, n, L, alpha=None, v0=1.0, width=1.0, shape="gauss",
+                 units="unit_heavy", cx=None, cy=None, mu_hl=None, **_ignored):
+    nn = (n,) * (2 * ndim) if np.isscalar(n) else tuple(n)
+    LL = (L,) * (2 * ndim) if np.isscalar(L) else tuple(L)
+    if cx is None:
+        if units == "unit_heavy":
+            cx, cy, mu_hl = physics.coeffs_unit_heavy(alpha)
+        else:
+            cx, cy, mu_hl = physics.coeffs_paper_units(alpha)
+    D2 = tuple(cheb.second_derivative_dirichlet(k, l) for k, l in zip(nn, LL))
+    grids = tuple(cheb.nodes(k, l) for k, l in zip(nn, LL))
+    if ndim == 1:
+        V = physics.potential_1d(grids[0], grids[1], shape, v0, width)
+    else:
+        V = physics.potential_2d(*grids, shape, v0, width)
+    return Problem(ndim, nn, LL, cx, cy, mu_hl if mu_hl is not None else 1.0,
+                   shape, v0, width, D2, grids, V)
