@@ -1,0 +1,184 @@
+/*
+ * tp3b.h - tensor-product three-body eigensolver for AMD Instinct MI355X (gfx950).
+ *
+ * Implements the hot path of the tensor-product scheme of Thies, Hof, Zimmermann
+ * and Efremov ("Tensor Product Scheme for Computing Bound States of the Quantum
+ * Mechanical Three-Body Problem"): the pseudospectral three-body Hamiltonian
+ * applied in tensor form (Sec. 3.2-3.3, eqs. (9)-(11)), the kinetic-only shifted
+ * Sylvester preconditioner (Sec. 4.2, eq. (14)), block orthogonalisation and a
+ * block Jacobi-Davidson QR eigensolver (Sec. 4.1, eqs. (12)-(13)).
+ *
+ * Conventions shared by every call
+ *  - Every function returns a tp3b_status: 0 on success, a negative code on
+ *    failure.  No function aborts or exits; tp3b_last_error() returns a message
+ *    for the calling thread's last failure.
+ *  - Vectors are 2d-mode tensors stored with the x modes slowest: 1D
+ *    psi[i][j] at i*n_y + j (eq. (6)); 2D psi[x1][x2][y1][y2].  N is the product
+ *    of the mode sizes.
+ *  - A block of nvec vectors is a column-major N x nvec array with leading
+ *    dimension ld >= N: vector v starts at X + v*ld.
+ *  - Device pointers are HIP device (or managed) memory owned by the caller;
+ *    the library never frees or reallocates them.  Host pointers are ordinary
+ *    host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    apply/prec calls are stream-ordered and asynchronous; create, block_orth
+ *    and the eigensolver calls are synchronous.
+ *  - Buffers handed to TP3B_FP64 calls hold doubles; buffers handed to
+ *    TP3B_FP32 / TP3B_BF16X3 calls hold floats (storage follows the compute
+ *    precision).
+ *  - One handle per thread; distinct handles are independent.
+ */
+#ifndef TP3B_H
+#define TP3B_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TP3B_OK = 0,
+  TP3B_EINVAL = -1,     /* bad argument, shape or descriptor (checked before any launch) */
+  TP3B_ENOMEM = -2,     /* device or host allocation failed, or above the workspace cap */
+  TP3B_EDEVICE = -3,    /* a HIP call failed; the message carries the HIP error string */
+  TP3B_ENOCONV = -4,    /* eigensolver stopped before nev pairs converged */
+  TP3B_ENOTSUP = -5,    /* valid request this build does not support */
+  TP3B_ENONFINITE = -6  /* NaN or Inf found in an input (when checking is enabled) */
+} tp3b_status;
+
+/* Compute precision of the mode products.  FP64: MFMA f64.  FP32: MFMA f32 with
+ * FP32 accumulation.  BF16X3: each FP32 operand split into bf16 hi + lo, the
+ * product formed as hi*hi + hi*lo + lo*hi on bf16 MFMA with FP32 accumulation. */
+typedef enum { TP3B_FP64 = 0, TP3B_FP32 = 1, TP3B_BF16X3 = 2 } tp3b_prec;
+
+/* Pair potential u(r) between the light particle and one heavy particle; the
+ * three-body potential is V = u(|y - x/2|) + u(|y + x/2|) (eq. (3), read with x
+ * the heavy-heavy and y the light-particle Jacobi coordinate). */
+typedef enum {
+  TP3B_POT_GAUSS = 0,       /* -v0 exp(-r^2 / (2 width^2))          */
+  TP3B_POT_GAUSS_PAPER = 1, /* -v0 exp(-r^2)            (eq. (4))   */
+  TP3B_POT_LORENTZ3 = 2,    /* -v0 / (1 + r^2)^3        (eq. (5))   */
+  TP3B_POT_HARMONIC = 3,    /* +v0 r^2 / 2  (closed-form test case) */
+  TP3B_POT_TABLE = 4        /* V given point by point in V_table     */
+} tp3b_pot;
+
+typedef struct tp3b_op_s* tp3b_op;
+
+/* Problem descriptor (Sec. 2-3).  H = -c_x Lap_x - c_y Lap_y + V, discretised on
+ * n[k] interior Chebyshev-Gauss-Lobatto points of [-L[k], L[k]] per mode with
+ * homogeneous Dirichlet conditions (the two end points are removed). */
+typedef struct {
+  int32_t ndim;            /* 1 (two modes x, y) or 2 (four modes x1, x2, y1, y2) */
+  int32_t n[4];            /* points per mode, order x1,(x2),y1,(y2); each >= 2 */
+  double L[4];             /* half-widths of the intervals, > 0 */
+  double c_x, c_y;         /* kinetic coefficients, > 0 */
+  int32_t pot;             /* tp3b_pot */
+  double v0, width;        /* potential depth and (TP3B_POT_GAUSS) width */
+  const double* V_table;   /* TP3B_POT_TABLE: N host values in vector layout, copied */
+  const double* D2[4];     /* optional host n_k x n_k row-major second-derivative
+                              matrices (the operator form of eq. (9)); NULL selects
+                              the Chebyshev-Gauss-Lobatto matrix; copied */
+  double sigma;            /* preconditioner shift; NaN selects the two-body ground
+                              energy on the y grid with reduced mass mu_hl */
+  double mu_hl;            /* heavy-light reduced mass for the default shift */
+} tp3b_problem_desc;
+
+/* Creates an operator: builds the second-derivative matrices, the potential
+ * table, the preconditioner's eigen-factors (1D only) and uploads them to the
+ * current HIP device.  Synchronous.  *out receives the handle. */
+tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* out);
+tp3b_status tp3b_destroy(tp3b_op op);
+
+/* Sizes and derived quantities of an operator (any pointer may be NULL). */
+tp3b_status tp3b_op_info(tp3b_op op, int64_t* N, double* sigma, double* lambda_min_kinetic);
+
+/* Copies mode k's n_k x n_k second-derivative matrix (row-major) or the N
+ * potential values (vector layout) to host memory. */
+tp3b_status tp3b_get_D2(tp3b_op op, int32_t mode, double* host_out);
+tp3b_status tp3b_get_V(tp3b_op op, double* host_out);
+
+/* Y = H X for nvec vectors (eqs. (10), (11)): one dense product per tensor mode,
+ * all modes summed, plus V o X fused into the epilogue.  X and Y must not
+ * overlap.  `shifts`, if not NULL, is a device array of nvec doubles s_v and the
+ * call returns Y = (H - s_v I) X instead. */
+tp3b_status tp3b_apply_H(tp3b_op op, int32_t prec, int32_t nvec, const void* X, int64_t ldx,
+                         void* Y, int64_t ldy, void* stream);
+tp3b_status tp3b_apply_H_shifted(tp3b_op op, int32_t prec, int32_t nvec, const void* X,
+                                 int64_t ldx, void* Y, int64_t ldy, const double* shifts,
+                                 void* stream);
+
+/* Y = (K - sigma I)^{-1} X with K the kinetic Kronecker sum (eq. (14)): per
+ * vector the Sylvester equation (K_x - s_x I) Z + Z (K_y - s_y I)^T = B,
+ * s_x + s_y = sigma, split in proportion to c_x and c_y.  Solved in the
+ * eigenbasis of K_x and K_y (four mode products and a pointwise divide), which
+ * is exact, as the paper's Bartels-Stewart solve is.  1D operators only
+ * (TP3B_ENOTSUP for 2D).  X and Y may not overlap. */
+tp3b_status tp3b_apply_prec(tp3b_op op, int32_t prec, int32_t nvec, const void* X, int64_t ldx,
+                            void* Y, int64_t ldy, void* stream);
+
+/* Block orthogonalisation in FP64.  Q: device N x nq with orthonormal columns
+ * (nq may be 0); X: device N x nx, overwritten by an orthonormal basis of the
+ * part of span(X) orthogonal to Q.  Two classical Gram-Schmidt passes against Q,
+ * then Cholesky-QR applied twice.  On return, if *rank == nx,
+ * X_in = Q C_qx + X_out R_xx with R_xx upper triangular, positive diagonal.
+ * C_qx (device nq x nx, column-major, ld nq) and R_xx (device nx x nx,
+ * column-major) may be NULL.  A column whose norm after projection falls below
+ * 1e-7 of its input norm is replaced by a pseudo-random vector (seeded by
+ * `seed`) orthogonalised in its place, and *rank counts only the independent
+ * columns.  nx <= 32.  Synchronous.  ENONFINITE if X holds NaN/Inf. */
+tp3b_status tp3b_block_orth(int64_t N, int32_t nq, const double* Q, int64_t ldq, int32_t nx,
+                            double* X, int64_t ldx, double* C_qx, double* R_xx, int32_t* rank,
+                            uint64_t seed, void* stream);
+
+/* Eigensolver options (Sec. 4.1).  Zero/negative fields select defaults. */
+typedef struct {
+  int32_t nev;          /* wanted eigenpairs (smallest real part) */
+  int32_t block;        /* block size b (vectors added per outer iteration) */
+  int32_t m_min, m_max; /* restart sizes; default m_max = max(4b, 2(nev+b)) rounded
+                           up to a multiple of b, m_min = m_max/2 */
+  int32_t gmres_steps;  /* fixed GMRES steps per correction equation, default 10 */
+  int32_t max_outer;    /* outer iteration cap, default 1000 */
+  int32_t precond;      /* 0: none, 1: kinetic Sylvester preconditioner (1D) */
+  int32_t inner_prec;   /* tp3b_prec of the GMRES applies; outer work is FP64 */
+  double tol;           /* lock when ||r|| <= tol max(|theta|, 1); default 1e-12 */
+  double switch_tol;    /* use `target` as the correction shift while
+                           ||r|| > switch_tol |theta|; default 1e-2 */
+  double target;        /* NaN: the preconditioner shift sigma */
+  uint64_t seed;        /* start block and rank-repair vectors */
+  int32_t check_finite; /* reject NaN/Inf in X0 */
+  int32_t verbose;      /* print one line per outer iteration to stderr */
+} tp3b_jdqr_opts;
+
+typedef struct {
+  int32_t n_conv, n_outer, n_restart, n_lock_events;
+  int64_t n_apply_H_fp64, n_apply_H_low, n_apply_prec;
+  double t_apply, t_prec, t_orth, t_rr, t_gmres, t_total; /* seconds */
+} tp3b_jdqr_stats;
+
+tp3b_status tp3b_jdqr_default_opts(tp3b_jdqr_opts* opts);
+
+/* Partial Schur form H Q = Q R for the nev eigenvalues of smallest real part
+ * (eq. (12)) by block JDQR with GMRES on the correction equation (eq. (13)).
+ * X0: optional device N x b0 start block (NULL: seeded normal block).
+ * evals: host nev, ascending by real part (real parts; complex pairs are not
+ * expected for these operators and are reported by their real part).
+ * Q: optional device N x nev (ld N) Schur vectors; R: optional host nev x nev
+ * column-major; resnorm: optional host nev residual norms at locking.
+ * Synchronous.  ENOCONV: fewer than nev converged within max_outer; the
+ * converged prefix (stats->n_conv) is returned. */
+tp3b_status tp3b_jdqr_solve(tp3b_op op, const tp3b_jdqr_opts* opts, const double* X0, int32_t b0,
+                            double* evals, double* Q, double* R, double* resnorm,
+                            tp3b_jdqr_stats* stats);
+
+/* Library-internal dense host routine exposed for host-side testing: real Schur
+ * form of a small n x n row-major matrix A (overwritten by T), Schur vectors Z
+ * (row-major, may be NULL), eigenvalue real/imaginary parts wr, wi. */
+tp3b_status tp3b_host_schur(int32_t n, double* A, double* Z, double* wr, double* wi);
+
+const char* tp3b_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TP3B_H */

@@ -3,8 +3,10 @@
 Reading (the paper delegates this step to its eigensolver library): classical
 Gram-Schmidt against Q applied twice, followed by a Householder QR of the
 projected block, with R normalised to a positive diagonal so that the result is
-unique.  A column whose norm after projection falls below ``drop_tol`` times its
-norm before projection is linearly dependent on the rest; it is replaced by a
+unique.  A column whose norm after projection falls below ``drop_tol`` (1e-7)
+times its norm before projection is linearly dependent on the rest (1e-7 is
+about the square root of the FP64 unit roundoff, the smallest ratio a
+Gram-matrix based orthogonalisation can resolve); it is replaced by a
 seeded random vector, which is orthogonalised in its place, and the returned
 rank counts only the independent columns.
 """
@@ -24,7 +26,7 @@ def _project(Q, X):
     return X, C
 
 
-def block_orth(Q, X, seed=0, drop_tol=1e-10):
+def block_orth(Q, X, seed=0, drop_tol=1e-7):
     """Orthonormalise X (N, nx) against the orthonormal Q (N, nq) and itself.
 
     Returns (Xo, C, R, rank) with Xo^T Xo = I, Q^T Xo = 0 and, when rank == nx,

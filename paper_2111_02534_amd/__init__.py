@@ -1,0 +1,312 @@
+"""Python binding of libtp3b, the MI355X tensor-product three-body eigensolver.
+
+Argument marshalling only: every step of the computation runs in the native
+library (HIP kernels for gfx950 and its host driver).  PyTorch provides device
+memory and streams.  Blocks of vectors are torch tensors of shape (nvec, N),
+row v being vector v, i.e. the column-major N x nvec block the C ABI takes.
+
+The library must have been built (``python -m paper_2111_02534_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libtp3b.so")
+
+TP3B_OK = 0
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV", -5: "ENOTSUP",
+          -6: "ENONFINITE"}
+FP64, FP32, BF16X3 = 0, 1, 2
+POT = {"gauss": 0, "gauss_paper": 1, "lorentz3": 2, "harmonic": 3, "table": 4}
+
+
+class Tp3bError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tp3b {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32 * 4), ("L", ctypes.c_double * 4),
+                ("c_x", ctypes.c_double), ("c_y", ctypes.c_double), ("pot", ctypes.c_int32),
+                ("v0", ctypes.c_double), ("width", ctypes.c_double),
+                ("V_table", ctypes.POINTER(ctypes.c_double)),
+                ("D2", ctypes.POINTER(ctypes.c_double) * 4), ("sigma", ctypes.c_double),
+                ("mu_hl", ctypes.c_double)]
+
+
+class JdqrOpts(ctypes.Structure):
+    _fields_ = [("nev", ctypes.c_int32), ("block", ctypes.c_int32), ("m_min", ctypes.c_int32),
+                ("m_max", ctypes.c_int32), ("gmres_steps", ctypes.c_int32),
+                ("max_outer", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("inner_prec", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("switch_tol", ctypes.c_double), ("target", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("check_finite", ctypes.c_int32),
+                ("verbose", ctypes.c_int32)]
+
+
+class JdqrStats(ctypes.Structure):
+    _fields_ = [("n_conv", ctypes.c_int32), ("n_outer", ctypes.c_int32),
+                ("n_restart", ctypes.c_int32), ("n_lock_events", ctypes.c_int32),
+                ("n_apply_H_fp64", ctypes.c_int64), ("n_apply_H_low", ctypes.c_int64),
+                ("n_apply_prec", ctypes.c_int64), ("t_apply", ctypes.c_double),
+                ("t_prec", ctypes.c_double), ("t_orth", ctypes.c_double), ("t_rr", ctypes.c_double),
+                ("t_gmres", ctypes.c_double), ("t_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+EXPORTS = ["tp3b_create", "tp3b_destroy", "tp3b_op_info", "tp3b_get_D2", "tp3b_get_V",
+           "tp3b_apply_H", "tp3b_apply_H_shifted", "tp3b_apply_prec", "tp3b_block_orth",
+           "tp3b_jdqr_default_opts", "tp3b_jdqr_solve", "tp3b_host_schur", "tp3b_last_error"]
+
+_lib = None
+
+
+def lib():
+    """The loaded native library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libtp3b.so not built at {LIB_PATH}; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+        L.tp3b_create.argtypes = [ctypes.POINTER(ProblemDesc), vp, ctypes.POINTER(vp)]
+        L.tp3b_destroy.argtypes = [vp]
+        L.tp3b_op_info.argtypes = [vp, ctypes.POINTER(i64), dp, dp]
+        L.tp3b_get_D2.argtypes = [vp, i32, dp]
+        L.tp3b_get_V.argtypes = [vp, dp]
+        L.tp3b_apply_H.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp]
+        L.tp3b_apply_H_shifted.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp, vp]
+        L.tp3b_apply_prec.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp]
+        L.tp3b_block_orth.argtypes = [i64, i32, vp, i64, i32, vp, i64, vp, vp,
+                                      ctypes.POINTER(i32), ctypes.c_uint64, vp]
+        L.tp3b_jdqr_default_opts.argtypes = [ctypes.POINTER(JdqrOpts)]
+        L.tp3b_jdqr_solve.argtypes = [vp, ctypes.POINTER(JdqrOpts), vp, i32, dp, vp, dp, dp,
+                                      ctypes.POINTER(JdqrStats)]
+        L.tp3b_host_schur.argtypes = [i32, dp, dp, dp, dp]
+        L.tp3b_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "tp3b_last_error":
+                getattr(L, name).restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != TP3B_OK:
+        raise Tp3bError(code, lib().tp3b_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dbl_ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def jacobi_coefficients(alpha):
+    """(c_x, c_y, mu_hl) for heavy mass 1 and light mass 1/alpha (hbar = 1):
+    c_x = 1/(2 mu_x), mu_x = 1/2; c_y = 1/(2 mu_y), mu_y = 2m/(2 + m);
+    mu_hl = m/(1 + m)."""
+    m = 1.0 / alpha
+    return 1.0, (2.0 + m) / (4.0 * m), m / (1.0 + m)
+
+
+def paper_coefficients(alpha):
+    """(c_x, c_y, mu_hl) in the paper's units (eq. (2)): alpha_x/2, alpha_y/2, 1."""
+    return 1.0 / (1.0 + alpha), (1.0 + 2.0 * alpha) / (4.0 * (1.0 + alpha)), 1.0
+
+
+class Operator:
+    """A discretised three-body Hamiltonian and its preconditioner on the
+    current HIP device (a tp3b_op handle)."""
+
+    def __init__(self, ndim, n, L, c_x, c_y, pot="gauss", v0=1.0, width=1.0, sigma=None,
+                 mu_hl=1.0, V_table=None, D2=None):
+        import numpy as np
+        nm = 2 * ndim
+        n = [n] * nm if isinstance(n, int) else list(n)
+        L = [L] * nm if isinstance(L, (int, float)) else list(L)
+        d = ProblemDesc()
+        d.ndim = ndim
+        for k in range(nm):
+            d.n[k] = int(n[k])
+            d.L[k] = float(L[k])
+        d.c_x, d.c_y = float(c_x), float(c_y)
+        d.pot = POT[pot] if isinstance(pot, str) else int(pot)
+        d.v0, d.width = float(v0), float(width)
+        d.sigma = float("nan") if sigma is None else float(sigma)
+        d.mu_hl = float(mu_hl)
+        self._keep = []
+        if V_table is not None:
+            arr = np.ascontiguousarray(V_table, dtype=np.float64).ravel()
+            self._keep.append(arr)
+            d.V_table = _dbl_ptr(arr)
+            d.pot = POT["table"]
+        if D2 is not None:
+            for k, m in enumerate(D2):
+                if m is not None:
+                    arr = np.ascontiguousarray(m, dtype=np.float64)
+                    self._keep.append(arr)
+                    d.D2[k] = _dbl_ptr(arr)
+        h = ctypes.c_void_p()
+        _check(lib().tp3b_create(ctypes.byref(d), None, ctypes.byref(h)))
+        self.handle = h
+        self.ndim, self.n, self.L = ndim, n, L
+        N = ctypes.c_int64()
+        sig = ctypes.c_double()
+        lm = ctypes.c_double()
+        _check(lib().tp3b_op_info(h, ctypes.byref(N), ctypes.byref(sig), ctypes.byref(lm)))
+        self.N, self.sigma = N.value, sig.value
+
+    @classmethod
+    def from_config(cls, cfg, units="unit_heavy", **kw):
+        if units == "unit_heavy":
+            cx, cy, mu = jacobi_coefficients(cfg["alpha"])
+        else:
+            cx, cy, mu = paper_coefficients(cfg["alpha"])
+        return cls(cfg["ndim"], cfg["n"], cfg["L"], cx, cy, pot=kw.pop("pot", "gauss"),
+                   v0=cfg["v0"], width=cfg.get("width", 1.0), mu_hl=mu, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().tp3b_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def D2(self, mode):
+        import numpy as np
+        out = np.empty((self.n[mode], self.n[mode]))
+        _check(lib().tp3b_get_D2(self.handle, mode, _dbl_ptr(out)))
+        return out
+
+    def V(self):
+        import numpy as np
+        out = np.empty(self.N)
+        _check(lib().tp3b_get_V(self.handle, _dbl_ptr(out)))
+        return out
+
+    @staticmethod
+    def _prec_of(t):
+        import torch
+        if t.dtype == torch.float64:
+            return FP64
+        if t.dtype == torch.float32:
+            return FP32
+        raise TypeError("blocks must be float64 or float32 tensors")
+
+    def _blk(self, X, Y):
+        if X.dim() != 2 or X.shape[1] != self.N or X.stride(1) != 1:
+            raise ValueError("blocks are (nvec, N) tensors with unit stride along N")
+        if Y.shape != X.shape or Y.stride(1) != 1 or Y.dtype != X.dtype:
+            raise ValueError("Y must match X")
+        if X.shape[0] == 1:  # a single vector: the row stride is irrelevant
+            return 1, self.N, self.N
+        return X.shape[0], X.stride(0), Y.stride(0)
+
+    def apply_H(self, X, Y, prec=None, shifts=None, stream=None):
+        nvec, ldx, ldy = self._blk(X, Y)
+        p = self._prec_of(X) if prec is None else prec
+        if shifts is None:
+            _check(lib().tp3b_apply_H(self.handle, p, nvec, _ptr(X), ldx, _ptr(Y), ldy,
+                                      _stream(stream)))
+        else:
+            _check(lib().tp3b_apply_H_shifted(self.handle, p, nvec, _ptr(X), ldx, _ptr(Y), ldy,
+                                              _ptr(shifts), _stream(stream)))
+        return Y
+
+    def apply_prec(self, X, Y, prec=None, stream=None):
+        nvec, ldx, ldy = self._blk(X, Y)
+        p = self._prec_of(X) if prec is None else prec
+        _check(lib().tp3b_apply_prec(self.handle, p, nvec, _ptr(X), ldx, _ptr(Y), ldy,
+                                     _stream(stream)))
+        return Y
+
+    def jdqr(self, nev, block, *, X0=None, inner_prec=FP64, precond=True, tol=1e-12,
+             gmres_steps=10, m_min=0, m_max=0, max_outer=1000, seed=0, switch_tol=1e-2,
+             target=None, verbose=False, want_Q=True):
+        import numpy as np
+        import torch
+        o = JdqrOpts()
+        _check(lib().tp3b_jdqr_default_opts(ctypes.byref(o)))
+        o.nev, o.block, o.m_min, o.m_max = nev, block, m_min, m_max
+        o.gmres_steps, o.max_outer, o.precond = gmres_steps, max_outer, int(bool(precond))
+        o.inner_prec, o.tol, o.switch_tol = inner_prec, tol, switch_tol
+        o.target = float("nan") if target is None else float(target)
+        o.seed, o.verbose = seed, int(verbose)
+        evals = np.empty(nev)
+        R = np.empty((nev, nev), order="F")
+        res = np.empty(nev)
+        Q = torch.empty((nev, self.N), dtype=torch.float64, device="cuda") if want_Q else None
+        st = JdqrStats()
+        b0 = 0 if X0 is None else X0.shape[0]
+        code = lib().tp3b_jdqr_solve(self.handle, ctypes.byref(o), _ptr(X0), b0, _dbl_ptr(evals),
+                                     _ptr(Q), R.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     _dbl_ptr(res), ctypes.byref(st))
+        result = JdqrResult(evals, Q, R, res, st.as_dict(), code)
+        if code != TP3B_OK:
+            err = Tp3bError(code, lib().tp3b_last_error().decode())
+            err.result = result
+            raise err
+        return result
+
+
+@dataclass
+class JdqrResult:
+    evals: object
+    Q: object
+    R: object
+    resnorm: object
+    stats: dict
+    status: int
+
+
+def block_orth(Q, X, seed=0, want_factors=True, stream=None):
+    """Orthonormalise the block X (nx, N) in place against Q (nq, N) (FP64).
+    Returns (C, R, rank) with C (nq x nx) and R (nx x nx) as torch tensors in
+    column-major order (C[:, j] = coefficients of column j)."""
+    import torch
+    nx, N = X.shape
+    nq = 0 if Q is None else Q.shape[0]
+    C = torch.empty((nx, max(nq, 1)), dtype=torch.float64, device=X.device) if want_factors else None
+    R = torch.empty((nx, nx), dtype=torch.float64, device=X.device) if want_factors else None
+    rank = ctypes.c_int32()
+    _check(lib().tp3b_block_orth(N, nq, _ptr(Q), Q.stride(0) if nq else N, nx, _ptr(X),
+                                 X.stride(0), _ptr(C) if nq else ctypes.c_void_p(0), _ptr(R),
+                                 ctypes.byref(rank), seed, _stream(stream)))
+    Cm = C.T[:nq] if (want_factors and nq) else None
+    Rm = R.T if want_factors else None
+    return Cm, Rm, rank.value
+
+
+def host_schur(A):
+    """Real Schur form of a small matrix with the library's host QR iteration
+    (for host-side tests).  Returns (T, Z, eigenvalues)."""
+    import numpy as np
+    A = np.array(A, dtype=np.float64, order="C", copy=True)
+    n = A.shape[0]
+    Z = np.empty_like(A)
+    wr = np.empty(n)
+    wi = np.empty(n)
+    _check(lib().tp3b_host_schur(n, _dbl_ptr(A), _dbl_ptr(Z), _dbl_ptr(wr), _dbl_ptr(wi)))
+    return A, Z, wr + 1j * wi

@@ -1,0 +1,82 @@
+// Library-internal state shared by the C-ABI entry points and the eigensolver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tp3b.h"
+#include "kernels.h"
+
+namespace tp3b {
+
+// Device copies of one operand set in one storage precision.
+template <typename T>
+struct DevOps {
+  T* K[4] = {nullptr, nullptr, nullptr, nullptr};   // -c D2 of each mode, row-major
+  T* KT[4] = {nullptr, nullptr, nullptr, nullptr};  // its transpose (right operand)
+  T* V = nullptr;                                   // potential table, vector layout
+  // 1D preconditioner factors: K_x = Sx diag(lx) Sx^{-1}, K_y = Sy diag(ly) Sy^{-1}.
+  T* Sxi = nullptr;   // Sx^{-1}        (left operand)
+  T* Sx = nullptr;    // Sx             (left operand)
+  T* SyiT = nullptr;  // (Sy^{-1})^T    (right operand: Z Sy^{-T})
+  T* SyT = nullptr;   // Sy^T           (right operand: Z Sy^T)
+  T* lx = nullptr;
+  T* ly = nullptr;
+  T* work = nullptr;  // preconditioner intermediate, work_vecs vectors
+};
+
+}  // namespace tp3b
+
+struct tp3b_op_s {
+  int ndim = 1;
+  int n[4] = {0, 0, 0, 0};
+  int nmodes = 2;
+  double L[4] = {0, 0, 0, 0};
+  double cx = 0, cy = 0;
+  int pot = 0;
+  double v0 = 0, width = 1;
+  double sigma = 0;
+  double mu_hl = 1;
+  int64_t N = 0;
+  int device = 0;
+  bool have_prec = false;
+  double lam_min = 0;  // smallest kinetic eigenvalue (sum over modes)
+  std::vector<double> D2h[4];  // host copies (row-major)
+  std::vector<double> Vh;      // host potential
+  tp3b::DevOps<double> d64;
+  tp3b::DevOps<float> d32;
+  int work_vecs = 0;
+  // tile choice per (precision, kernel role); -1 = heuristic
+  int tile_override = -1;
+};
+
+namespace tp3b {
+
+void set_error(const std::string& msg);
+tp3b_status fail(tp3b_status code, const std::string& msg);
+tp3b_status hip_fail(hipError_t e, const char* where);
+
+#define TP3B_HIP(...)                                              \
+  do {                                                             \
+    hipError_t _e = (__VA_ARGS__);                                 \
+    if (_e != hipSuccess) return tp3b::hip_fail(_e, #__VA_ARGS__); \
+  } while (0)
+
+// Precision-generic internal applies (no argument validation).
+template <typename T>
+tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, int64_t ldy,
+                         const double* shifts, hipStream_t s);
+template <typename T>
+tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, int64_t ldy,
+                            hipStream_t s);
+int choose_tile(int M, int Nc, int64_t nbatch, bool fp64);
+
+// Device scratch for the dot reductions (grows on demand, per device).
+double* dot_scratch(int64_t doubles);
+tp3b_status block_orth_impl(int64_t N, int nq, const double* Q, int64_t ldq, int nx, double* X,
+                            int64_t ldx, double* C_qx, double* R_xx, int* rank, uint64_t seed,
+                            hipStream_t s);
+
+}  // namespace tp3b

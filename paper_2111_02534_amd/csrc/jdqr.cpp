@@ -1,0 +1,533 @@
+// Block Jacobi-Davidson QR (Sec. 4.1, eqs. (12)-(13)) with preconditioned
+// GMRES on the correction equation (Sec. 4.1-4.2).
+//
+// Everything of size N lives on the device; the host holds only the projected
+// m x m problem, the small Hessenberg least-squares problems and the partial
+// Schur factor R.  One outer iteration:
+//   1. ordered real Schur form of M = V^T A V (host), V and AV rotated to it;
+//   2. partial-Schur residuals of the leading b Schur vectors (FP64);
+//   3. locking of the converged prefix, restart to m_min vectors at m_max;
+//   4. b correction equations (eq. (13)) with Q~ = [Q_lock, u_1..u_b] solved by
+//      left-preconditioned GMRES with the skew projection
+//      (I - Y H^{-1} Q~^T) P^{-1}, Y = P^{-1} Q~, H = Q~^T Y, a fixed number of
+//      steps, in the inner working precision (FP64 or FP32);
+//   5. FP64 block orthogonalisation of the corrections against [Q_lock, V] and
+//      FP64 products with A to extend V and A V.
+// Rayleigh-Ritz, residuals, locking and orthogonalisation are always FP64, so
+// the converged pairs meet the FP64 residual tolerance whatever the inner
+// precision.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "dense_la.h"
+#include "internal.h"
+
+namespace tp3b {
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  template <typename T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+hipError_t dalloc(DevBuf& b, size_t bytes) { return hipMalloc(&b.p, bytes ? bytes : 8); }
+
+// Copy the (r0.., c0..) nr x nc sub-block of a row-major host matrix (ld cols)
+// into a column-major host array with leading dimension nr.
+std::vector<double> colmajor(const std::vector<double>& A, int ld, int r0, int c0, int nr, int nc) {
+  std::vector<double> out((size_t)nr * nc);
+  for (int j = 0; j < nc; ++j)
+    for (int i = 0; i < nr; ++i) out[i + (size_t)j * nr] = A[(size_t)(r0 + i) * ld + (c0 + j)];
+  return out;
+}
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+template <typename TW>
+static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X0, int b0,
+                            double* evals, double* Qout, double* Rout, double* resnorm,
+                            tp3b_jdqr_stats* st) {
+  const double t_start = now();
+  hipStream_t s = nullptr;
+  const int64_t N = op->N;
+  const int nev = o.nev, b = o.block, steps = o.gmres_steps;
+  const int m_max = o.m_max, m_min = o.m_min;
+  const bool use_prec = o.precond != 0;
+  const bool low = sizeof(TW) == 4;
+  const double target = std::isnan(o.target) ? op->sigma : o.target;
+  tp3b_jdqr_stats stats{};
+
+  // ---- device buffers
+  const int qv_cols = nev + m_max + b;
+  const int av_cols = m_max + b + nev;
+  const int qt_max = nev + b;
+  DevBuf QVb, AVb, TMPb, Rresb, PQb, Ypb, Qtwb, Ypwb, Vgb, Wb, Zb, Tcb, smallb;
+  TP3B_HIP(dalloc(QVb, sizeof(double) * N * qv_cols));
+  TP3B_HIP(dalloc(AVb, sizeof(double) * N * av_cols));
+  TP3B_HIP(dalloc(TMPb, sizeof(double) * N * (m_max + b)));
+  TP3B_HIP(dalloc(Rresb, sizeof(double) * N * b));
+  if (use_prec) {
+    TP3B_HIP(dalloc(PQb, sizeof(double) * N * qt_max));
+    TP3B_HIP(dalloc(Ypb, sizeof(double) * N * qt_max));
+  }
+  if (low) {
+    TP3B_HIP(dalloc(Qtwb, sizeof(TW) * N * qt_max));
+    TP3B_HIP(dalloc(Ypwb, sizeof(TW) * N * qt_max));
+  }
+  TP3B_HIP(dalloc(Vgb, sizeof(TW) * N * b * (steps + 1)));
+  TP3B_HIP(dalloc(Wb, sizeof(TW) * N * b));
+  TP3B_HIP(dalloc(Zb, sizeof(TW) * N * b));
+  TP3B_HIP(dalloc(Tcb, sizeof(double) * N * b));
+  // small device arrays (doubles)
+  const int hld = steps + 2;
+  const size_t n_small = (size_t)(m_max + b) * (m_max + b) * 2 + (size_t)qt_max * qt_max +
+                         (size_t)qt_max * b * 2 + (size_t)steps * b * hld * 2 + (size_t)steps * b +
+                         (size_t)b * 4 + (size_t)(steps + 1) * b + 64;
+  TP3B_HIP(dalloc(smallb, sizeof(double) * n_small));
+  double* QV = QVb.as<double>();
+  double* AVbase = AVb.as<double>();
+  double* TMP = TMPb.as<double>();
+  double* Rres = Rresb.as<double>();
+  double* PQ = PQb.as<double>();
+  double* Yp = Ypb.as<double>();
+  TW* Vg = Vgb.as<TW>();
+  TW* W = Wb.as<TW>();
+  TW* Zt = Zb.as<TW>();
+  double* Tc = Tcb.as<double>();
+  double* dS = smallb.as<double>();                                  // (m_max+b)^2
+  double* dM2 = dS + (size_t)(m_max + b) * (m_max + b);              // (m_max+b)^2
+  double* dHinv = dM2 + (size_t)(m_max + b) * (m_max + b);           // qt_max^2
+  double* dC = dHinv + (size_t)qt_max * qt_max;                      // qt_max*b
+  double* dC2 = dC + (size_t)qt_max * b;                             // qt_max*b
+  double* dH1 = dC2 + (size_t)qt_max * b;                            // steps*b*hld
+  double* dH2 = dH1 + (size_t)steps * b * hld;                       // steps*b*hld
+  double* dHs = dH2 + (size_t)steps * b * hld;                       // steps*b
+  double* dShift = dHs + (size_t)steps * b;                          // b
+  double* dNrm = dShift + b;                                         // b
+  double* dBeta = dNrm + b;                                          // b
+  double* dY = dBeta + 2 * b;                                        // (steps+1)*b
+  const int64_t dscr = dot_scratch_doubles(N, qt_max + m_max + b, qt_max + m_max + b) +
+                       bdot_scratch_doubles(N, b, steps + 2) + 8 * (int64_t)(qv_cols + 1) * b +
+                       8 * (int64_t)b * b + 1024;
+  double* part = dot_scratch(dscr);
+  if (!part) return fail(TP3B_ENOMEM, "jdqr: scratch allocation failed");
+
+  int k = 0;      // locked vectors: QV[:, 0:k]
+  int m = 0;      // search space: QV[:, k:k+m], A V in AV[:, 0:m]
+  int av0 = 0;    // column offset of A V inside its buffer
+  std::vector<double> Rl;          // partial Schur factor, column-major nev x nev
+  Rl.assign((size_t)nev * nev, 0.0);
+  std::vector<double> lockres;
+  std::vector<int> lock_pair;
+  std::vector<double> M;           // row-major m x m projected matrix
+
+  auto V = [&]() { return QV + (int64_t)k * N; };
+  auto AV = [&]() { return AVbase + (int64_t)av0 * N; };
+  auto applyA64 = [&](int nv, const double* X, double* Y) -> tp3b_status {
+    stats.n_apply_H_fp64 += nv;
+    return apply_H_impl<double>(op, nv, X, N, Y, N, nullptr, s);
+  };
+  auto dot = [&](int p, int q, const double* A, const double* B, std::vector<double>& host,
+                 int ldc) -> tp3b_status {
+    // host (row-major p x q) = A^T B
+    TP3B_HIP(launch_dot_tn<double, double>(N, p, q, A, N, B, N, dM2, p, part, s));
+    std::vector<double> cm((size_t)p * q);
+    TP3B_HIP(hipMemcpyAsync(cm.data(), dM2, sizeof(double) * p * q, hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipStreamSynchronize(s));
+    host.assign((size_t)p * ldc, 0.0);
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < q; ++j) host[(size_t)i * ldc + j] = cm[i + (size_t)j * p];
+    return TP3B_OK;
+  };
+
+  // ---- start block
+  {
+    const int nb0 = (X0 && b0 > 0) ? std::min(b0, b) : 0;
+    if (nb0 > 0) {
+      if (o.check_finite) {
+        int* flag = (int*)dY;
+        TP3B_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+        TP3B_HIP(launch_check_finite<double>(N, nb0, X0, N, flag, s));
+        int hf = 0;
+        TP3B_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        TP3B_HIP(hipStreamSynchronize(s));
+        if (hf) return fail(TP3B_ENONFINITE, "jdqr: non-finite start block");
+      }
+      TP3B_HIP(hipMemcpyAsync(QV, X0, sizeof(double) * N * nb0, hipMemcpyDeviceToDevice, s));
+    }
+    for (int j = nb0; j < b; ++j)
+      TP3B_HIP(launch_hash_fill(N, QV + (int64_t)j * N, o.seed, 1000003ull + j, s));
+    int rank = 0;
+    double t0 = now();
+    tp3b_status rs = block_orth_impl(N, 0, nullptr, N, b, QV, N, nullptr, nullptr, &rank,
+                                     o.seed + 17, s);
+    stats.t_orth += now() - t0;
+    if (rs != TP3B_OK) return rs;
+    part = dot_scratch(dscr);
+    m = b;
+    t0 = now();
+    tp3b_status as = applyA64(m, V(), AV());
+    if (as != TP3B_OK) return as;
+    tp3b_status ds = dot(m, m, V(), AV(), M, m);
+    if (ds != TP3B_OK) return ds;
+    stats.t_apply += now() - t0;
+  }
+
+  std::vector<double> S, T;
+  std::vector<int> pair;
+  int outer = 0;
+  while (k < nev && outer < o.max_outer) {
+    // ---- 1. ordered Schur form of the projected matrix, rotate V and A V
+    double t0 = now();
+    S.assign((size_t)m * m, 0.0);
+    T.assign((size_t)m * m, 0.0);
+    pair.assign(m, 0);
+    if (!ordered_schur(m, M.data(), S.data(), T.data(), pair.data()))
+      return fail(TP3B_ENOCONV, "jdqr: projected Schur form did not converge");
+    bool ident = true;
+    for (int i = 0; i < m && ident; ++i)
+      for (int j = 0; j < m; ++j)
+        if (S[(size_t)i * m + j] != (i == j ? 1.0 : 0.0)) { ident = false; break; }
+    if (!ident) {
+      std::vector<double> Sc = colmajor(S, m, 0, 0, m, m);
+      TP3B_HIP(hipMemcpyAsync(dS, Sc.data(), sizeof(double) * m * m, hipMemcpyHostToDevice, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, m, m, 1.0, V(), N, dS, m, 0.0, TMP, N, s));
+      TP3B_HIP(hipMemcpyAsync(V(), TMP, sizeof(double) * N * m, hipMemcpyDeviceToDevice, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, m, m, 1.0, AV(), N, dS, m, 0.0, TMP, N, s));
+      TP3B_HIP(hipMemcpyAsync(AV(), TMP, sizeof(double) * N * m, hipMemcpyDeviceToDevice, s));
+    }
+    M = T;
+    const int nb = std::min(b, m);
+    // ---- 2. residuals R = (I - Q Q^T)(A U - V T[:, :nb])
+    TP3B_HIP(hipMemcpyAsync(Rres, AV(), sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
+    {
+      std::vector<double> Tc_ = colmajor(T, m, 0, 0, m, nb);
+      TP3B_HIP(hipMemcpyAsync(dS, Tc_.data(), sizeof(double) * m * nb, hipMemcpyHostToDevice, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, m, nb, -1.0, V(), N, dS, m, 1.0, Rres, N, s));
+    }
+    std::vector<double> Cq((size_t)std::max(k, 1) * nb, 0.0);  // Q^T A U, column-major k x nb
+    if (k > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        TP3B_HIP(launch_dot_tn<double, double>(N, k, nb, QV, N, Rres, N, dC, k, part, s));
+        TP3B_HIP(launch_gemm_nn<double>(N, k, nb, -1.0, QV, N, dC, k, 1.0, Rres, N, s));
+        std::vector<double> c((size_t)k * nb);
+        TP3B_HIP(hipMemcpyAsync(c.data(), dC, sizeof(double) * k * nb, hipMemcpyDeviceToHost, s));
+        TP3B_HIP(hipStreamSynchronize(s));
+        for (size_t e = 0; e < c.size(); ++e) Cq[e] += c[e];
+      }
+    }
+    TP3B_HIP(launch_bdot_diag<double>(N, nb, 1, Rres, 0, Rres, dNrm, 1, part, s));
+    std::vector<double> rn(nb);
+    TP3B_HIP(hipMemcpyAsync(rn.data(), dNrm, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < nb; ++j) rn[j] = std::sqrt(std::max(rn[j], 0.0));
+    std::vector<double> theta(nb);
+    for (int j = 0; j < nb; ++j) theta[j] = T[(size_t)j * m + j];
+    stats.t_rr += now() - t0;
+    if (o.verbose)
+      fprintf(stderr, "[tp3b jdqr] outer %d locked %d m %d theta0 %.15g res0 %.3e\n", outer, k, m,
+              theta[0], rn[0]);
+    for (int j = 0; j < nb; ++j)
+      if (!std::isfinite(rn[j]) || !std::isfinite(theta[j]))
+        return fail(TP3B_ENONFINITE, "jdqr: non-finite residual");
+
+    // ---- 3. locking of the converged prefix
+    int p = 0;
+    while (p < nb && k + p < nev) {
+      const int blk = pair[p] ? 2 : 1;
+      bool ok = p + blk <= nb;
+      for (int q = p; ok && q < p + blk; ++q)
+        ok = rn[q] <= o.tol * std::max(std::fabs(theta[q]), 1.0);
+      if (!ok) break;
+      p += blk;
+    }
+    if (p > 0) {
+      if (k + p > nev) p = nev - k;  // never split beyond nev (pairs are not expected here)
+      const int m_old = m;
+      for (int j = 0; j < p; ++j) {
+        for (int i = 0; i < k; ++i) Rl[i + (size_t)(k + j) * nev] = Cq[i + (size_t)j * k];
+        // upper-triangular part of T, plus the subdiagonal entry of a 2 x 2 block
+        for (int i = 0; i < p; ++i)
+          if (i <= j || (i == j + 1 && pair[j])) Rl[(k + i) + (size_t)(k + j) * nev] = T[(size_t)i * m_old + j];
+        lock_pair.push_back(pair[j]);
+        lockres.push_back(rn[j]);
+      }
+      if (use_prec) {
+        double tp = now();
+        tp3b_status ps = apply_prec_impl<double>(op, p, V(), N, PQ + (int64_t)k * N, N, s);
+        if (ps != TP3B_OK) return ps;
+        stats.n_apply_prec += p;
+        stats.t_prec += now() - tp;
+      }
+      k += p;
+      m -= p;
+      av0 += p;
+      std::vector<double> Mn((size_t)m * m);
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) Mn[(size_t)i * m + j] = T[(size_t)(i + p) * m_old + (j + p)];
+      M = Mn;
+      stats.n_lock_events++;
+      if (k >= nev || m == 0) break;
+      continue;
+    }
+    ++outer;
+    // ---- restart
+    if (m + nb > m_max) {
+      const int keep = std::max(m_min, nb);
+      m = keep;
+      // Recompute the projected matrix from the kept vectors (limits drift).
+      tp3b_status ds = dot(m, m, V(), AV(), M, m);
+      if (ds != TP3B_OK) return ds;
+      stats.n_restart++;
+    }
+    // ---- 4. correction equations
+    std::vector<double> shift(nb);
+    for (int j = 0; j < nb; ++j)
+      shift[j] = (rn[j] > o.switch_tol * std::fabs(theta[j])) ? target : theta[j];
+    TP3B_HIP(hipMemcpyAsync(dShift, shift.data(), sizeof(double) * nb, hipMemcpyHostToDevice, s));
+    const int nqt = k + nb;  // Q~ = QV[:, 0:nqt]
+    const double* Qt = QV;
+    const double* Yq = Qt;   // P^{-1} Q~ H^{-1} (or Q~ without preconditioner)
+    if (use_prec) {
+      double tp = now();
+      tp3b_status ps = apply_prec_impl<double>(op, nb, V(), N, PQ + (int64_t)k * N, N, s);
+      if (ps != TP3B_OK) return ps;
+      stats.n_apply_prec += nb;
+      stats.t_prec += now() - tp;
+      std::vector<double> Hh;
+      tp3b_status ds = dot(nqt, nqt, Qt, PQ, Hh, nqt);
+      if (ds != TP3B_OK) return ds;
+      std::vector<double> Hi((size_t)nqt * nqt);
+      if (!lu_inverse(nqt, Hh.data(), Hi.data()))
+        return fail(TP3B_ENOCONV, "jdqr: singular projected preconditioner");
+      std::vector<double> Hic = colmajor(Hi, nqt, 0, 0, nqt, nqt);
+      TP3B_HIP(hipMemcpyAsync(dHinv, Hic.data(), sizeof(double) * nqt * nqt, hipMemcpyHostToDevice, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, nqt, nqt, 1.0, PQ, N, dHinv, nqt, 0.0, Yp, N, s));
+      Yq = Yp;
+    }
+    const TW* Qtw;
+    const TW* Yqw;
+    if (low) {
+      TP3B_HIP((launch_convert<double, TW>(N, nqt, 1.0, Qt, N, Qtwb.as<TW>(), N, s)));
+      TP3B_HIP((launch_convert<double, TW>(N, nqt, 1.0, Yq, N, Ypwb.as<TW>(), N, s)));
+      Qtw = Qtwb.as<TW>();
+      Yqw = Ypwb.as<TW>();
+    } else {
+      Qtw = (const TW*)Qt;
+      Yqw = (const TW*)Yq;
+    }
+    const double tg0 = now();
+    auto precond_w = [&](const TW* in, TW* out) -> tp3b_status {
+      stats.n_apply_prec += nb;
+      return apply_prec_impl<TW>(op, nb, in, N, out, N, s);
+    };
+    auto project = [&](TW* Zp) -> tp3b_status {
+      TP3B_HIP((launch_dot_tn<TW, TW>(N, nqt, nb, Qtw, N, Zp, N, dC2, nqt, part, s)));
+      TP3B_HIP((launch_gemm_nn<TW>(N, nqt, nb, -1.0, Yqw, N, dC2, nqt, 1.0, Zp, N, s)));
+      return TP3B_OK;
+    };
+    // right-hand side: proj(P^{-1}(-r))
+    TW* rhs = W;
+    if (use_prec) {
+      TP3B_HIP((launch_convert<double, TW>(N, nb, -1.0, Rres, N, Zt, N, s)));
+      tp3b_status ps = precond_w(Zt, rhs);
+      if (ps != TP3B_OK) return ps;
+    } else {
+      TP3B_HIP((launch_convert<double, TW>(N, nb, -1.0, Rres, N, rhs, N, s)));
+    }
+    { tp3b_status ps = project(rhs); if (ps != TP3B_OK) return ps; }
+    TP3B_HIP(launch_bdot_diag<TW>(N, nb, 1, rhs, 0, rhs, dNrm, 1, part, s));
+    TP3B_HIP(launch_normalize_cols<TW>(N, nb, dNrm, rhs, Vg, dBeta, 1, s));
+    const int64_t bs = N * nb;
+    for (int kk = 0; kk < steps; ++kk) {
+      TW* vk = Vg + (int64_t)kk * bs;
+      TW* w = W;
+      if (use_prec) {
+        stats.n_apply_H_low += low ? nb : 0;
+        stats.n_apply_H_fp64 += low ? 0 : nb;
+        tp3b_status as = apply_H_impl<TW>(op, nb, vk, N, Zt, N, dShift, s);
+        if (as != TP3B_OK) return as;
+        tp3b_status ps = precond_w(Zt, w);
+        if (ps != TP3B_OK) return ps;
+      } else {
+        stats.n_apply_H_low += low ? nb : 0;
+        stats.n_apply_H_fp64 += low ? 0 : nb;
+        tp3b_status as = apply_H_impl<TW>(op, nb, vk, N, w, N, dShift, s);
+        if (as != TP3B_OK) return as;
+      }
+      { tp3b_status ps = project(w); if (ps != TP3B_OK) return ps; }
+      double* h1 = dH1 + (size_t)kk * b * hld;
+      double* h2 = dH2 + (size_t)kk * b * hld;
+      TP3B_HIP(launch_bdot_diag<TW>(N, nb, kk + 1, Vg, bs, w, h1, hld, part, s));
+      TP3B_HIP(launch_bupdate_diag<TW>(N, nb, kk + 1, -1.0, Vg, bs, h1, hld, w, s));
+      TP3B_HIP(launch_bdot_diag<TW>(N, nb, kk + 1, Vg, bs, w, h2, hld, part, s));
+      TP3B_HIP(launch_bupdate_diag<TW>(N, nb, kk + 1, -1.0, Vg, bs, h2, hld, w, s));
+      TP3B_HIP(launch_bdot_diag<TW>(N, nb, 1, w, 0, w, dNrm, 1, part, s));
+      TP3B_HIP(launch_normalize_cols<TW>(N, nb, dNrm, w, Vg + (int64_t)(kk + 1) * bs,
+                                         dHs + (size_t)kk * b, 1, s));
+    }
+    std::vector<double> hH1((size_t)steps * b * hld), hH2((size_t)steps * b * hld),
+        hHs((size_t)steps * b), hBeta(b);
+    TP3B_HIP(hipMemcpyAsync(hH1.data(), dH1, sizeof(double) * hH1.size(), hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipMemcpyAsync(hH2.data(), dH2, sizeof(double) * hH2.size(), hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipMemcpyAsync(hHs.data(), dHs, sizeof(double) * hHs.size(), hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipMemcpyAsync(hBeta.data(), dBeta, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipStreamSynchronize(s));
+    // Least squares per column; y stored as H-like layout yv[j*hld + i].
+    std::vector<double> yv((size_t)b * hld, 0.0);
+    int ksteps_max = 0;
+    for (int j = 0; j < nb; ++j) {
+      const double beta = hBeta[j];
+      if (!(beta > 0)) continue;
+      int ks = 0;
+      for (int kk = 0; kk < steps; ++kk) {
+        ks = kk + 1;
+        if (!(hHs[(size_t)kk * b + j] > 1e-14 * beta)) break;
+      }
+      std::vector<double> Hm((size_t)(ks + 1) * ks, 0.0);
+      for (int kk = 0; kk < ks; ++kk) {
+        const double* a1 = hH1.data() + (size_t)kk * b * hld + (size_t)j * hld;
+        const double* a2 = hH2.data() + (size_t)kk * b * hld + (size_t)j * hld;
+        for (int i = 0; i <= kk; ++i) Hm[(size_t)i * ks + kk] = a1[i] + a2[i];
+        Hm[(size_t)(kk + 1) * ks + kk] = hHs[(size_t)kk * b + j];
+      }
+      std::vector<double> y(ks);
+      hessenberg_lstsq(ks, Hm.data(), ks, beta, y.data());
+      for (int i = 0; i < ks; ++i) yv[(size_t)j * hld + i] = y[i];
+      ksteps_max = std::max(ksteps_max, ks);
+    }
+    TP3B_HIP(hipMemcpyAsync(dY, yv.data(), sizeof(double) * b * hld, hipMemcpyHostToDevice, s));
+    TP3B_HIP(hipMemsetAsync(W, 0, sizeof(TW) * N * nb, s));
+    TP3B_HIP(launch_bupdate_diag<TW>(N, nb, ksteps_max, 1.0, Vg, bs, dY, hld, W, s));
+    TP3B_HIP((launch_convert<TW, double>(N, nb, 1.0, W, N, Tc, N, s)));
+    TP3B_HIP(hipStreamSynchronize(s));
+    stats.t_gmres += now() - tg0;
+
+    // ---- 5. expand the basis
+    double to = now();
+    double* Vn = QV + (int64_t)(k + m) * N;
+    TP3B_HIP(hipMemcpyAsync(Vn, Tc, sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
+    int rank = 0;
+    tp3b_status os = block_orth_impl(N, k + m, QV, N, nb, Vn, N, nullptr, nullptr, &rank,
+                                     o.seed + 7919ull * (uint64_t)outer, s);
+    if (os != TP3B_OK) return os;
+    part = dot_scratch(dscr);
+    if (!part) return fail(TP3B_ENOMEM, "jdqr: scratch allocation failed");
+    stats.t_orth += now() - to;
+    double ta = now();
+    tp3b_status as = applyA64(nb, Vn, AV() + (int64_t)m * N);
+    if (as != TP3B_OK) return as;
+    std::vector<double> top, left;
+    tp3b_status ds = dot(m + nb, nb, V(), AV() + (int64_t)m * N, top, nb);
+    if (ds != TP3B_OK) return ds;
+    ds = dot(nb, m, Vn, AV(), left, m);
+    if (ds != TP3B_OK) return ds;
+    std::vector<double> Mn((size_t)(m + nb) * (m + nb), 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) Mn[(size_t)i * (m + nb) + j] = M[(size_t)i * m + j];
+    for (int i = 0; i < m + nb; ++i)
+      for (int j = 0; j < nb; ++j) Mn[(size_t)i * (m + nb) + m + j] = top[(size_t)i * nb + j];
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < m; ++j) Mn[(size_t)(m + i) * (m + nb) + j] = left[(size_t)i * m + j];
+    m += nb;
+    M = Mn;
+    stats.t_apply += now() - ta;
+  }
+
+  // ---- outputs
+  const int nconv = k;
+  std::vector<double> ev(nconv);
+  for (int i = 0; i < nconv; ++i) {
+    // 2 x 2 blocks (complex pairs) are reported by their real part.
+    if (i + 1 < nconv && lock_pair[i]) {
+      const double a = Rl[i + (size_t)i * nev], d = Rl[(i + 1) + (size_t)(i + 1) * nev];
+      ev[i] = ev[i + 1] = 0.5 * (a + d);
+      ++i;
+    } else {
+      ev[i] = Rl[i + (size_t)i * nev];
+    }
+  }
+  std::vector<double> evs = ev;
+  std::sort(evs.begin(), evs.end());
+  if (evals)
+    for (int i = 0; i < nev; ++i) evals[i] = i < nconv ? evs[i] : NAN;
+  if (Qout && nconv > 0)
+    TP3B_HIP(hipMemcpy(Qout, QV, sizeof(double) * N * nconv, hipMemcpyDeviceToDevice));
+  if (Rout) std::memcpy(Rout, Rl.data(), sizeof(double) * nev * nev);
+  if (resnorm)
+    for (int i = 0; i < nev; ++i) resnorm[i] = i < (int)lockres.size() ? lockres[i] : NAN;
+  stats.n_conv = nconv;
+  stats.n_outer = outer;
+  stats.t_total = now() - t_start;
+  if (st) *st = stats;
+  if (nconv < nev) return fail(TP3B_ENOCONV, "jdqr: not converged within max_outer");
+  return TP3B_OK;
+}
+
+}  // namespace tp3b
+
+using namespace tp3b;
+
+extern "C" {
+
+tp3b_status tp3b_jdqr_default_opts(tp3b_jdqr_opts* o) {
+  if (!o) return fail(TP3B_EINVAL, "null options");
+  std::memset(o, 0, sizeof(*o));
+  o->nev = 1;
+  o->block = 1;
+  o->gmres_steps = 10;
+  o->max_outer = 1000;
+  o->precond = 1;
+  o->inner_prec = TP3B_FP64;
+  o->tol = 1e-12;
+  o->switch_tol = 1e-2;
+  o->target = NAN;
+  o->seed = 0;
+  return TP3B_OK;
+}
+
+tp3b_status tp3b_jdqr_solve(tp3b_op op, const tp3b_jdqr_opts* opts, const double* X0, int32_t b0,
+                            double* evals, double* Q, double* R, double* resnorm,
+                            tp3b_jdqr_stats* stats) {
+  if (!op || !opts) return fail(TP3B_EINVAL, "null operator or options");
+  tp3b_jdqr_opts o = *opts;
+  if (o.nev < 1 || o.block < 1) return fail(TP3B_EINVAL, "nev and block must be >= 1");
+  if (o.block > 32) return fail(TP3B_EINVAL, "block must be <= 32");
+  if (o.gmres_steps <= 0) o.gmres_steps = 10;
+  if (o.gmres_steps > 38) return fail(TP3B_EINVAL, "gmres_steps must be <= 38");
+  if (o.max_outer <= 0) o.max_outer = 1000;
+  if (!(o.tol > 0)) o.tol = 1e-12;
+  if (!(o.switch_tol > 0)) o.switch_tol = 1e-2;
+  int mmax = std::max(4 * o.block, 2 * (o.nev + o.block));
+  mmax = ((mmax + o.block - 1) / o.block) * o.block;
+  if (o.m_max <= 0) o.m_max = mmax;
+  if (o.m_min <= 0) o.m_min = o.m_max / 2;
+  if (o.m_min < o.block || o.m_max < o.m_min + o.block)
+    return fail(TP3B_EINVAL, "need block <= m_min and m_min + block <= m_max");
+  if (op->N < (int64_t)(o.nev + o.m_max + o.block))
+    return fail(TP3B_EINVAL, "problem too small for nev + m_max + block basis vectors");
+  if (o.precond && (op->ndim != 1 || !op->have_prec))
+    return fail(TP3B_ENOTSUP, "the kinetic preconditioner is available for 1D operators only");
+  if (o.inner_prec == TP3B_BF16X3) return fail(TP3B_ENOTSUP, "BF16x3 inner solves are not built");
+  if (X0 && b0 < 0) return fail(TP3B_EINVAL, "b0 must be >= 0");
+  TP3B_HIP(hipSetDevice(op->device));
+  if (o.inner_prec == TP3B_FP32) return jdqr_run<float>(op, o, X0, b0, evals, Q, R, resnorm, stats);
+  return jdqr_run<double>(op, o, X0, b0, evals, Q, R, resnorm, stats);
+}
+
+}  // extern "C"

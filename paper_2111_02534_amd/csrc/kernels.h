@@ -1,0 +1,95 @@
+// Device kernels of the tensor-product three-body library (gfx950) and their
+// host launchers.  All launchers are stream-ordered and return hipError_t.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tp3b {
+
+enum Epi { EPI_NONE = 0, EPI_V = 1, EPI_DIV = 2 };
+
+// One strided, batched mode product (Sec. 3.2-3.3): for every batch item q
+// (vector vec = q / per_vec, item = q % per_vec) with
+//   Xq = X + vec*ldx + item*bstride,  element (i, j) at Xq[i*rs + j],
+// computes   Y = [L Xq] + [Xq R] (+ epilogue)   with L an M x M and R an
+// Nc x Nc row-major operator (either may be absent), and the epilogue
+//   EPI_V:   + (V[item*bstride + i*rs + j] - shift[vec]) * Xq[i, j]
+//   EPI_DIV: / (lamL[i] + lamR[j] - sigma)
+// optionally accumulated into Y (acc != 0).
+template <typename T>
+struct ModeProd {
+  int M, Nc;
+  int64_t rs, bstride, ldx, ldy;
+  int per_vec, nbatch;
+  const T* X;
+  T* Y;
+  const T* L;
+  const T* R;
+  const T* V;
+  const double* shifts;
+  const T* lamL;
+  const T* lamR;
+  double sigma;
+  int epi;
+  int acc;
+};
+
+// Tile configurations (output tile TM x TN per 256-thread workgroup).
+enum TileCfg { TILE_32 = 0, TILE_64 = 1, TILE_128 = 2, TILE_64x128 = 3, NUM_TILE_CFGS = 4 };
+
+template <typename T>
+hipError_t launch_modeprod(const ModeProd<T>& a, int tile, hipStream_t s);
+
+// C (p x q, column-major, ldc) = A^T B, A: N x p (lda), B: N x q (ldb), FP64
+// accumulation; `partial` is device scratch of at least dot_scratch_doubles().
+template <typename TA, typename TB>
+hipError_t launch_dot_tn(int64_t N, int p, int q, const TA* A, int64_t lda, const TB* B,
+                         int64_t ldb, double* C, int ldc, double* partial, hipStream_t s);
+int64_t dot_scratch_doubles(int64_t N, int p, int q);
+
+// Y (N x q, ldy) = beta Y + alpha A (N x p, lda) C (p x q column-major, ldc,
+// device doubles).  Y must not alias A.
+template <typename T>
+hipError_t launch_gemm_nn(int64_t N, int p, int q, double alpha, const T* A, int64_t lda,
+                          const double* C, int ldc, double beta, T* Y, int64_t ldy,
+                          hipStream_t s);
+
+// Batched per-column dots for b independent Krylov bases stored as blocks
+// Vb[i] = V + i*bs (each N x b, ld N):  H[j*hld + i] = sum_r Vb[i][r, j] W[r, j]
+// for i < nb.  `partial` as for the dot.
+template <typename T>
+hipError_t launch_bdot_diag(int64_t N, int b, int nb, const T* V, int64_t bs, const T* W,
+                            double* H, int hld, double* partial, hipStream_t s);
+int64_t bdot_scratch_doubles(int64_t N, int b, int nb);
+// W[r, j] += alpha * sum_{i<nb} Vb[i][r, j] H[j*hld + i]
+template <typename T>
+hipError_t launch_bupdate_diag(int64_t N, int b, int nb, double alpha, const T* V, int64_t bs,
+                               const double* H, int hld, T* W, hipStream_t s);
+// Vout[:, j] = W[:, j] / sqrt(nrm2[j]) (0 if the norm is not positive);
+// also stores hout[j*hld] = sqrt(nrm2[j]).
+template <typename T>
+hipError_t launch_normalize_cols(int64_t N, int b, const double* nrm2, const T* W, T* Vout,
+                                 double* hout, int hld, hipStream_t s);
+
+// Y[:, j] = alpha * X[:, j] (type conversion included).
+template <typename TI, typename TO>
+hipError_t launch_convert(int64_t N, int ncol, double alpha, const TI* X, int64_t ldx, TO* Y,
+                          int64_t ldy, hipStream_t s);
+
+// Cholesky of the nx x nx Gram matrix G (column-major): R upper, flags[j] = 1
+// where the pivot falls below (drop_tol * norm0[j])^2.  Single thread.
+hipError_t launch_chol_small(int nx, const double* G, const double* norm0sq, double drop_tol,
+                             double* R, int* flags, hipStream_t s);
+// X (N x nx) <- X R^{-1} for upper-triangular R (column-major nx x nx).
+hipError_t launch_trsm_right(int64_t N, int nx, const double* R, double* X, int64_t ldx,
+                             hipStream_t s);
+// Fill column `col` of X with counter-based pseudo-random values in [-1, 1).
+hipError_t launch_hash_fill(int64_t N, double* X, uint64_t seed, uint64_t stream_id,
+                            hipStream_t s);
+// flag[0] |= 1 if any entry of the N x ncol block is not finite.
+template <typename T>
+hipError_t launch_check_finite(int64_t N, int ncol, const T* X, int64_t ldx, int* flag,
+                               hipStream_t s);
+
+}  // namespace tp3b

@@ -1,0 +1,658 @@
+// C-ABI entry points: operator set-up, Hamiltonian and preconditioner applies,
+// block orthogonalisation.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dense_la.h"
+#include "internal.h"
+
+namespace tp3b {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+tp3b_status fail(tp3b_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+tp3b_status hip_fail(hipError_t e, const char* where) {
+  g_err = std::string("HIP error '") + hipGetErrorString(e) + "' in " + where;
+  return e == hipErrorOutOfMemory ? TP3B_ENOMEM : TP3B_EDEVICE;
+}
+
+// ---------------------------------------------------------------- grids
+// Second-derivative collocation matrix on the n interior Chebyshev-Gauss-Lobatto
+// points of [-L, L] with homogeneous Dirichlet conditions (Sec. 3.1): the
+// Lagrange interpolant through K+1 = n+2 points t_j = cos(pi j/K) is
+// differentiated twice and the two boundary rows and columns are removed.
+// Nodes ascend: x_i = -L t_i, i = 1..n.
+static void cgl_second_derivative(int n, double L, std::vector<double>& D2,
+                                  std::vector<double>& x) {
+  const int K = n + 1;
+  std::vector<double> t(K + 1), c(K + 1), D((size_t)(K + 1) * (K + 1));
+  for (int j = 0; j <= K; ++j) {
+    // cos(pi j / K) evaluated symmetrically for exact antisymmetry
+    t[j] = (2 * j <= K) ? std::cos(M_PI * j / K) : -std::cos(M_PI * (K - j) / K);
+    c[j] = ((j % 2) ? -1.0 : 1.0) * ((j == 0 || j == K) ? 0.5 : 1.0);
+  }
+  for (int i = 0; i <= K; ++i) {
+    double rowsum = 0.0;
+    for (int j = 0; j <= K; ++j) {
+      if (i == j) continue;
+      const double v = (c[j] / c[i]) / (t[i] - t[j]);
+      D[(size_t)i * (K + 1) + j] = v;
+      rowsum += v;
+    }
+    D[(size_t)i * (K + 1) + i] = -rowsum;
+  }
+  D2.assign((size_t)n * n, 0.0);
+  const double s = 1.0 / (L * L);
+  for (int i = 1; i <= n; ++i)
+    for (int j = 1; j <= n; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k <= K; ++k) acc += D[(size_t)i * (K + 1) + k] * D[(size_t)k * (K + 1) + j];
+      D2[(size_t)(i - 1) * n + (j - 1)] = acc * s;
+    }
+  x.resize(n);
+  for (int i = 1; i <= n; ++i) x[i - 1] = -L * t[i];
+}
+
+static double pair_pot(int pot, double r, double v0, double w) {
+  switch (pot) {
+    case TP3B_POT_GAUSS: return -v0 * std::exp(-(r * r) / (2.0 * w * w));
+    case TP3B_POT_GAUSS_PAPER: return -v0 * std::exp(-(r * r));
+    case TP3B_POT_LORENTZ3: {
+      const double d = 1.0 + r * r;
+      return -v0 / (d * d * d);
+    }
+    case TP3B_POT_HARMONIC: return 0.5 * v0 * r * r;
+    default: return 0.0;
+  }
+}
+
+int choose_tile(int M, int Nc, int64_t nbatch, bool fp64) {
+  // Largest tile that still gives >= 1024 workgroups (4 per CU); otherwise the
+  // one giving the most parallelism without mostly-empty tiles.
+  struct C { int id, tm, tn; };
+  const C cfgs[] = {{TILE_128, 128, 128}, {TILE_64x128, 64, 128}, {TILE_64, 64, 64}, {TILE_32, 32, 32}};
+  (void)fp64;
+  for (const C& c : cfgs) {
+    if (c.tm > M || c.tn > Nc) continue;
+    int64_t wg = (int64_t)((M + c.tm - 1) / c.tm) * ((Nc + c.tn - 1) / c.tn) * nbatch;
+    if (wg >= 1024) return c.id;
+  }
+  return (M >= 64 && Nc >= 64 && (int64_t)((M + 63) / 64) * ((Nc + 63) / 64) * nbatch >= 512) ? TILE_64
+                                                                                            : TILE_32;
+}
+
+// --------------------------------------------------------------- scratch
+// One scratch area per thread and device: distinct threads may use the
+// library concurrently (one handle per thread).
+static thread_local double* g_scratch[64] = {nullptr};
+static thread_local int64_t g_scratch_sz[64] = {0};
+
+double* dot_scratch(int64_t doubles) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  if (g_scratch_sz[dev] < doubles) {
+    if (g_scratch[dev]) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(g_scratch[dev]);
+      g_scratch[dev] = nullptr;
+      g_scratch_sz[dev] = 0;
+    }
+    int64_t want = doubles < (1 << 16) ? (1 << 16) : doubles + doubles / 2;
+    if (hipMalloc((void**)&g_scratch[dev], sizeof(double) * want) != hipSuccess) return nullptr;
+    g_scratch_sz[dev] = want;
+  }
+  return g_scratch[dev];
+}
+
+template <typename T>
+static hipError_t upload(T** dst, const std::vector<double>& src) {
+  std::vector<T> tmp(src.begin(), src.end());
+  hipError_t e = hipMalloc((void**)dst, sizeof(T) * (tmp.empty() ? 1 : tmp.size()));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, tmp.data(), sizeof(T) * tmp.size(), hipMemcpyHostToDevice);
+}
+
+template <typename T>
+static void free_ops(tp3b::DevOps<T>& d) {
+  for (int k = 0; k < 4; ++k) {
+    if (d.K[k]) (void)hipFree(d.K[k]);
+    if (d.KT[k]) (void)hipFree(d.KT[k]);
+  }
+  T* ps[] = {d.V, d.Sxi, d.Sx, d.SyiT, d.SyT, d.lx, d.ly, d.work};
+  for (T* p : ps)
+    if (p) (void)hipFree(p);
+  d = tp3b::DevOps<T>();
+}
+
+static std::vector<double> transpose(const std::vector<double>& A, int n) {
+  std::vector<double> B((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) B[(size_t)j * n + i] = A[(size_t)i * n + j];
+  return B;
+}
+
+template <typename T>
+static tp3b_status upload_ops(tp3b_op op, tp3b::DevOps<T>& d, const std::vector<double>* Kh,
+                              const std::vector<double>* pre) {
+  for (int k = 0; k < op->nmodes; ++k) {
+    TP3B_HIP(upload(&d.K[k], Kh[k]));
+    TP3B_HIP(upload(&d.KT[k], transpose(Kh[k], op->n[k])));
+  }
+  TP3B_HIP(upload(&d.V, op->Vh));
+  if (op->have_prec) {
+    TP3B_HIP(upload(&d.Sxi, pre[0]));
+    TP3B_HIP(upload(&d.Sx, pre[1]));
+    TP3B_HIP(upload(&d.SyiT, pre[2]));
+    TP3B_HIP(upload(&d.SyT, pre[3]));
+    TP3B_HIP(upload(&d.lx, pre[4]));
+    TP3B_HIP(upload(&d.ly, pre[5]));
+    TP3B_HIP(hipMalloc((void**)&d.work, sizeof(T) * op->N * op->work_vecs));
+  }
+  return TP3B_OK;
+}
+
+// -------------------------------------------------------------- applies
+template <typename T>
+static tp3b::DevOps<T>& ops_for(tp3b_op op);
+template <>
+tp3b::DevOps<double>& ops_for<double>(tp3b_op op) { return op->d64; }
+template <>
+tp3b::DevOps<float>& ops_for<float>(tp3b_op op) { return op->d32; }
+
+template <typename T>
+tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, int64_t ldy,
+                         const double* shifts, hipStream_t s) {
+  tp3b::DevOps<T>& d = ops_for<T>(op);
+  const bool f64 = sizeof(T) == 8;
+  if (op->ndim == 1) {
+    // Y = K_x W + W K_y^T + (V - shift) o W per vector (eq. (10)).
+    ModeProd<T> a{};
+    a.M = op->n[0];
+    a.Nc = op->n[1];
+    a.rs = op->n[1];
+    a.bstride = 0;
+    a.ldx = ldx;
+    a.ldy = ldy;
+    a.per_vec = 1;
+    a.nbatch = nvec;
+    a.X = X;
+    a.Y = Y;
+    a.L = d.K[0];
+    a.R = d.KT[1];
+    a.V = d.V;
+    a.shifts = shifts;
+    a.epi = EPI_V;
+    a.acc = 0;
+    int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, nvec, f64);
+    TP3B_HIP(launch_modeprod(a, tile, s));
+    return TP3B_OK;
+  }
+  // 2D (eq. (11)): pass A applies the two y modes and the potential on every
+  // contiguous (y1, y2) plane; passes B1 and B2 accumulate the x2 and x1 modes.
+  const int nx1 = op->n[0], nx2 = op->n[1], ny1 = op->n[2], ny2 = op->n[3];
+  const int64_t Ny = (int64_t)ny1 * ny2;
+  {
+    ModeProd<T> a{};
+    a.M = ny1;
+    a.Nc = ny2;
+    a.rs = ny2;
+    a.bstride = Ny;
+    a.ldx = ldx;
+    a.ldy = ldy;
+    a.per_vec = nx1 * nx2;
+    a.nbatch = nvec * nx1 * nx2;
+    a.X = X;
+    a.Y = Y;
+    a.L = d.K[2];
+    a.R = d.KT[3];
+    a.V = d.V;
+    a.shifts = shifts;
+    a.epi = EPI_V;
+    a.acc = 0;
+    int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, a.nbatch, f64);
+    TP3B_HIP(launch_modeprod(a, tile, s));
+  }
+  {
+    ModeProd<T> a{};
+    a.M = nx2;
+    a.Nc = (int)Ny;
+    a.rs = Ny;
+    a.bstride = (int64_t)nx2 * Ny;
+    a.ldx = ldx;
+    a.ldy = ldy;
+    a.per_vec = nx1;
+    a.nbatch = nvec * nx1;
+    a.X = X;
+    a.Y = Y;
+    a.L = d.K[1];
+    a.R = nullptr;
+    a.epi = EPI_NONE;
+    a.acc = 1;
+    int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, a.nbatch, f64);
+    TP3B_HIP(launch_modeprod(a, tile, s));
+  }
+  {
+    ModeProd<T> a{};
+    a.M = nx1;
+    a.Nc = (int)((int64_t)nx2 * Ny);
+    a.rs = (int64_t)nx2 * Ny;
+    a.bstride = 0;
+    a.ldx = ldx;
+    a.ldy = ldy;
+    a.per_vec = 1;
+    a.nbatch = nvec;
+    a.X = X;
+    a.Y = Y;
+    a.L = d.K[0];
+    a.R = nullptr;
+    a.epi = EPI_NONE;
+    a.acc = 1;
+    int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, a.nbatch, f64);
+    TP3B_HIP(launch_modeprod(a, tile, s));
+  }
+  return TP3B_OK;
+}
+
+template <typename T>
+tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, int64_t ldy,
+                            hipStream_t s) {
+  tp3b::DevOps<T>& d = ops_for<T>(op);
+  const bool f64 = sizeof(T) == 8;
+  const int nx = op->n[0], ny = op->n[1];
+  const int64_t N = op->N;
+  // Z = Sx [ (Sx^{-1} B Sy^{-T}) / (lx_i + ly_j - sigma) ] Sy^T, four mode
+  // products; the work buffer and Y alternate as intermediates.
+  for (int v0 = 0; v0 < nvec; v0 += op->work_vecs) {
+    const int nv = (nvec - v0 < op->work_vecs) ? nvec - v0 : op->work_vecs;
+    const T* Xc = X + (int64_t)v0 * ldx;
+    T* Yc = Y + (int64_t)v0 * ldy;
+    ModeProd<T> a{};
+    a.M = nx;
+    a.Nc = ny;
+    a.rs = ny;
+    a.per_vec = 1;
+    a.nbatch = nv;
+    a.sigma = op->sigma;
+    int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(nx, ny, nv, f64);
+    // 1: W = Sx^{-1} B
+    a.X = Xc; a.ldx = ldx; a.Y = d.work; a.ldy = N;
+    a.L = d.Sxi; a.R = nullptr; a.epi = EPI_NONE;
+    TP3B_HIP(launch_modeprod(a, tile, s));
+    // 2: Y = (W Sy^{-T}) / (lx_i + ly_j - sigma)
+    a.X = d.work; a.ldx = N; a.Y = Yc; a.ldy = ldy;
+    a.L = nullptr; a.R = d.SyiT; a.epi = EPI_DIV; a.lamL = d.lx; a.lamR = d.ly;
+    TP3B_HIP(launch_modeprod(a, tile, s));
+    // 3: W = Sx Y
+    a.X = Yc; a.ldx = ldy; a.Y = d.work; a.ldy = N;
+    a.L = d.Sx; a.R = nullptr; a.epi = EPI_NONE;
+    TP3B_HIP(launch_modeprod(a, tile, s));
+    // 4: Y = W Sy^T
+    a.X = d.work; a.ldx = N; a.Y = Yc; a.ldy = ldy;
+    a.L = nullptr; a.R = d.SyT; a.epi = EPI_NONE;
+    TP3B_HIP(launch_modeprod(a, tile, s));
+  }
+  return TP3B_OK;
+}
+
+template tp3b_status apply_H_impl<double>(tp3b_op, int, const double*, int64_t, double*, int64_t,
+                                          const double*, hipStream_t);
+template tp3b_status apply_H_impl<float>(tp3b_op, int, const float*, int64_t, float*, int64_t,
+                                         const double*, hipStream_t);
+template tp3b_status apply_prec_impl<double>(tp3b_op, int, const double*, int64_t, double*,
+                                             int64_t, hipStream_t);
+template tp3b_status apply_prec_impl<float>(tp3b_op, int, const float*, int64_t, float*, int64_t,
+                                            hipStream_t);
+
+// ------------------------------------------------------------ block orth
+// A column keeping less than this fraction of its norm after projection counts
+// as dependent.  Cholesky-QR forms the Gram matrix, whose pivots carry absolute
+// errors of order eps |x|^2, so dependence is only detectable above ~sqrt(eps).
+constexpr double kDropTol = 1e-7;
+tp3b_status block_orth_impl(int64_t N, int nq, const double* Q, int64_t ldq, int nx, double* X,
+                            int64_t ldx, double* C_qx, double* R_xx, int* rank, uint64_t seed,
+                            hipStream_t s) {
+  const int pmax = nq > nx ? nq : nx;
+  const int64_t sc = dot_scratch_doubles(N, pmax, nx) + 4 * (int64_t)(nq + 1) * nx +
+                     6 * (int64_t)nx * nx + 2 * nx + 64;
+  double* scr = dot_scratch(sc);
+  if (!scr) return fail(TP3B_ENOMEM, "block_orth: scratch allocation failed");
+  double* part = scr;
+  double* C1 = part + dot_scratch_doubles(N, pmax, nx);
+  double* C2 = C1 + (int64_t)(nq + 1) * nx;
+  double* G = C2 + (int64_t)(nq + 1) * nx;
+  double* R1 = G + (int64_t)nx * nx;
+  double* R2 = R1 + (int64_t)nx * nx;
+  double* n0 = R2 + (int64_t)nx * nx;
+  int* flags = (int*)(n0 + nx + 1);
+  std::vector<double> hG((size_t)nx * nx), hR1((size_t)nx * nx), hR2((size_t)nx * nx);
+  std::vector<double> hC1((size_t)(nq + 1) * nx, 0.0), hC2((size_t)(nq + 1) * nx, 0.0);
+  std::vector<int> hflags(nx + 1, 0);
+
+  // Input column norms (for the rank test) and the finiteness check.
+  TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
+  TP3B_HIP(hipMemcpyAsync(hG.data(), G, sizeof(double) * nx * nx, hipMemcpyDeviceToHost, s));
+  TP3B_HIP(hipStreamSynchronize(s));
+  std::vector<double> hn0(nx);
+  for (int j = 0; j < nx; ++j) {
+    hn0[j] = hG[(size_t)j * nx + j];
+    if (!std::isfinite(hn0[j])) return fail(TP3B_ENONFINITE, "block_orth: non-finite input");
+  }
+  std::vector<int> replaced(nx, 0);
+  int deficient = 0;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    TP3B_HIP(hipMemcpyAsync(n0, hn0.data(), sizeof(double) * nx, hipMemcpyHostToDevice, s));
+    // Two classical Gram-Schmidt passes against Q.
+    if (nq > 0) {
+      TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, X, ldx, C1, nq, part, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, nq, nx, -1.0, Q, ldq, C1, nq, 1.0, X, ldx, s));
+      TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, X, ldx, C2, nq, part, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, nq, nx, -1.0, Q, ldq, C2, nq, 1.0, X, ldx, s));
+    }
+    // Cholesky-QR, twice.
+    TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
+    TP3B_HIP(launch_chol_small(nx, G, n0, kDropTol, R1, flags, s));
+    TP3B_HIP(hipMemcpyAsync(hflags.data(), flags, sizeof(int) * nx, hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipStreamSynchronize(s));
+    int bad = 0;
+    for (int j = 0; j < nx; ++j) bad += hflags[j];
+    if (bad && attempt < 3) {
+      // Replace the dependent columns by pseudo-random vectors and redo.
+      for (int j = 0; j < nx; ++j) {
+        if (!hflags[j]) continue;
+        if (!replaced[j]) ++deficient;
+        replaced[j] = 1;
+        TP3B_HIP(launch_hash_fill(N, X + (int64_t)j * ldx, seed, (uint64_t)(attempt * 64 + j), s));
+        hn0[j] = 0.0;  // recomputed below
+      }
+      TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
+      TP3B_HIP(hipMemcpyAsync(hG.data(), G, sizeof(double) * nx * nx, hipMemcpyDeviceToHost, s));
+      TP3B_HIP(hipStreamSynchronize(s));
+      for (int j = 0; j < nx; ++j)
+        if (replaced[j]) hn0[j] = hG[(size_t)j * nx + j];
+      if (nq > 0) {
+        TP3B_HIP(hipMemcpyAsync(hC1.data(), C1, sizeof(double) * nq * nx, hipMemcpyDeviceToHost, s));
+      }
+      continue;
+    }
+    if (bad) return fail(TP3B_EDEVICE, "block_orth: could not complete the basis");
+    TP3B_HIP(launch_trsm_right(N, nx, R1, X, ldx, s));
+    TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
+    std::vector<double> ones(nx, 0.0);
+    TP3B_HIP(hipMemcpyAsync(n0, ones.data(), sizeof(double) * nx, hipMemcpyHostToDevice, s));
+    TP3B_HIP(launch_chol_small(nx, G, n0, 0.0, R2, flags, s));
+    TP3B_HIP(launch_trsm_right(N, nx, R2, X, ldx, s));
+    TP3B_HIP(hipMemcpyAsync(hR1.data(), R1, sizeof(double) * nx * nx, hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipMemcpyAsync(hR2.data(), R2, sizeof(double) * nx * nx, hipMemcpyDeviceToHost, s));
+    if (nq > 0) {
+      TP3B_HIP(hipMemcpyAsync(hC1.data(), C1, sizeof(double) * nq * nx, hipMemcpyDeviceToHost, s));
+      TP3B_HIP(hipMemcpyAsync(hC2.data(), C2, sizeof(double) * nq * nx, hipMemcpyDeviceToHost, s));
+    }
+    TP3B_HIP(hipStreamSynchronize(s));
+    break;
+  }
+  if (rank) *rank = nx - deficient;
+  if (R_xx) {
+    // R = R2 R1 (both upper triangular, column-major).
+    std::vector<double> R((size_t)nx * nx, 0.0);
+    for (int j = 0; j < nx; ++j)
+      for (int i = 0; i <= j; ++i) {
+        double acc = 0.0;
+        for (int k = i; k <= j; ++k) acc += hR2[i + (size_t)k * nx] * hR1[k + (size_t)j * nx];
+        R[i + (size_t)j * nx] = replaced[j] ? 0.0 : acc;
+      }
+    TP3B_HIP(hipMemcpy(R_xx, R.data(), sizeof(double) * nx * nx, hipMemcpyHostToDevice));
+  }
+  if (C_qx && nq > 0) {
+    std::vector<double> C((size_t)nq * nx);
+    for (size_t e = 0; e < C.size(); ++e) C[e] = hC1[e] + hC2[e];
+    TP3B_HIP(hipMemcpy(C_qx, C.data(), sizeof(double) * nq * nx, hipMemcpyHostToDevice));
+  }
+  return TP3B_OK;
+}
+
+}  // namespace tp3b
+
+using namespace tp3b;
+
+extern "C" {
+
+const char* tp3b_last_error(void) { return g_err.c_str(); }
+
+tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* out) {
+  (void)stream;
+  if (!desc || !out) return fail(TP3B_EINVAL, "tp3b_create: null descriptor or output");
+  *out = nullptr;
+  if (desc->ndim != 1 && desc->ndim != 2) return fail(TP3B_EINVAL, "ndim must be 1 or 2");
+  const int nm = 2 * desc->ndim;
+  int64_t N = 1;
+  for (int k = 0; k < nm; ++k) {
+    if (desc->n[k] < 2 || desc->n[k] > 8192) return fail(TP3B_EINVAL, "mode sizes must be in [2, 8192]");
+    if (!(desc->L[k] > 0)) return fail(TP3B_EINVAL, "half-widths L must be positive");
+    N *= desc->n[k];
+  }
+  if (!(desc->c_x > 0) || !(desc->c_y > 0)) return fail(TP3B_EINVAL, "c_x and c_y must be positive");
+  if (desc->pot < TP3B_POT_GAUSS || desc->pot > TP3B_POT_TABLE) return fail(TP3B_EINVAL, "unknown potential");
+  if (desc->pot == TP3B_POT_TABLE && !desc->V_table) return fail(TP3B_EINVAL, "TP3B_POT_TABLE needs V_table");
+  if (desc->pot == TP3B_POT_GAUSS && !(desc->width > 0)) return fail(TP3B_EINVAL, "width must be positive");
+  if (desc->ndim == 2 && (desc->n[0] != desc->n[1] || desc->n[2] != desc->n[3]))
+    return fail(TP3B_ENOTSUP, "2D operators need n[0] == n[1] and n[2] == n[3]");
+
+  tp3b_op op = new tp3b_op_s();
+  op->ndim = desc->ndim;
+  op->nmodes = nm;
+  op->N = N;
+  op->cx = desc->c_x;
+  op->cy = desc->c_y;
+  op->pot = desc->pot;
+  op->v0 = desc->v0;
+  op->width = desc->width;
+  op->mu_hl = desc->mu_hl > 0 ? desc->mu_hl : 1.0;
+  (void)hipGetDevice(&op->device);
+  std::vector<double> x[4];
+  for (int k = 0; k < nm; ++k) {
+    op->n[k] = desc->n[k];
+    op->L[k] = desc->L[k];
+    std::vector<double> D2;
+    cgl_second_derivative(op->n[k], op->L[k], D2, x[k]);
+    if (desc->D2[k]) D2.assign(desc->D2[k], desc->D2[k] + (size_t)op->n[k] * op->n[k]);
+    op->D2h[k] = D2;
+  }
+  // Potential V = u(|y - x/2|) + u(|y + x/2|) on the tensor grid (eq. (3)).
+  op->Vh.resize(N);
+  if (desc->pot == TP3B_POT_TABLE) {
+    std::memcpy(op->Vh.data(), desc->V_table, sizeof(double) * N);
+  } else if (desc->ndim == 1) {
+    for (int i = 0; i < op->n[0]; ++i)
+      for (int j = 0; j < op->n[1]; ++j) {
+        const double xi = x[0][i], yj = x[1][j];
+        op->Vh[(size_t)i * op->n[1] + j] = pair_pot(op->pot, std::fabs(yj - 0.5 * xi), op->v0, op->width) +
+                                           pair_pot(op->pot, std::fabs(yj + 0.5 * xi), op->v0, op->width);
+      }
+  } else {
+    const int a = op->n[0], b = op->n[1], c = op->n[2], e = op->n[3];
+    for (int i1 = 0; i1 < a; ++i1)
+      for (int i2 = 0; i2 < b; ++i2)
+        for (int j1 = 0; j1 < c; ++j1)
+          for (int j2 = 0; j2 < e; ++j2) {
+            const double x1 = x[0][i1], x2 = x[1][i2], y1 = x[2][j1], y2 = x[3][j2];
+            const double rm = std::hypot(y1 - 0.5 * x1, y2 - 0.5 * x2);
+            const double rp = std::hypot(y1 + 0.5 * x1, y2 + 0.5 * x2);
+            op->Vh[(((size_t)i1 * b + i2) * c + j1) * e + j2] =
+                pair_pot(op->pot, rm, op->v0, op->width) + pair_pot(op->pot, rp, op->v0, op->width);
+          }
+  }
+  // Scaled kinetic factors K_k = -c D2_k.
+  std::vector<double> Kh[4];
+  for (int k = 0; k < nm; ++k) {
+    const double c = (k < nm / 2) ? op->cx : op->cy;
+    Kh[k].resize(op->D2h[k].size());
+    for (size_t e = 0; e < Kh[k].size(); ++e) Kh[k][e] = -c * op->D2h[k][e];
+  }
+  // Preconditioner shift: two-body ground energy on the y grid (Sec. 4.2).
+  if (std::isnan(desc->sigma)) {
+    const int ky = nm / 2, n = op->n[ky];
+    std::vector<double> A((size_t)n * n), wr(n), wi(n);
+    const double ck = 1.0 / (2.0 * op->mu_hl);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = -ck * op->D2h[ky][(size_t)i * n + j];
+    if (desc->pot == TP3B_POT_TABLE) {
+      op->sigma = 0.0;
+    } else {
+      for (int i = 0; i < n; ++i) A[(size_t)i * n + i] += pair_pot(op->pot, std::fabs(x[ky][i]), op->v0, op->width);
+      if (!real_schur(n, A.data(), nullptr, wr.data(), wi.data())) {
+        delete op;
+        return fail(TP3B_EDEVICE, "two-body eigenvalue iteration did not converge");
+      }
+      double m = wr[0];
+      for (int i = 1; i < n; ++i) m = std::min(m, wr[i]);
+      op->sigma = m;
+    }
+  } else {
+    op->sigma = desc->sigma;
+  }
+  // Fast-diagonalisation factors of the 1D kinetic Sylvester operator.
+  std::vector<double> pre[6];
+  if (op->ndim == 1) {
+    const int nx = op->n[0], ny = op->n[1];
+    std::vector<double> Sx((size_t)nx * nx), Sxi((size_t)nx * nx), lx(nx);
+    std::vector<double> Sy((size_t)ny * ny), Syi((size_t)ny * ny), ly(ny);
+    bool okx = eigen_decompose_real(nx, Kh[0].data(), Sx.data(), Sxi.data(), lx.data());
+    bool oky = eigen_decompose_real(ny, Kh[1].data(), Sy.data(), Syi.data(), ly.data());
+    if (okx && oky) {
+      double mn = 1e300;
+      for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j) mn = std::min(mn, std::fabs(lx[i] + ly[j] - op->sigma));
+      op->lam_min = mn;
+      if (mn > 0) {
+        op->have_prec = true;
+        pre[0] = Sxi;
+        pre[1] = Sx;
+        pre[2] = transpose(Syi, ny);
+        pre[3] = transpose(Sy, ny);
+        pre[4] = lx;
+        pre[5] = ly;
+      }
+    }
+    int64_t cap = (int64_t)(1ll << 30) / (N * 8);
+    op->work_vecs = (int)std::max<int64_t>(1, std::min<int64_t>(64, cap));
+  }
+  tp3b_status st = upload_ops<double>(op, op->d64, Kh, pre);
+  if (st == TP3B_OK) st = upload_ops<float>(op, op->d32, Kh, pre);
+  if (st != TP3B_OK) {
+    std::string msg = g_err;
+    tp3b_destroy(op);
+    return fail(st, msg);
+  }
+  *out = op;
+  return TP3B_OK;
+}
+
+tp3b_status tp3b_destroy(tp3b_op op) {
+  if (!op) return TP3B_OK;
+  free_ops(op->d64);
+  free_ops(op->d32);
+  delete op;
+  return TP3B_OK;
+}
+
+tp3b_status tp3b_op_info(tp3b_op op, int64_t* N, double* sigma, double* lam_min) {
+  if (!op) return fail(TP3B_EINVAL, "null operator");
+  if (N) *N = op->N;
+  if (sigma) *sigma = op->sigma;
+  if (lam_min) *lam_min = op->lam_min;
+  return TP3B_OK;
+}
+
+tp3b_status tp3b_get_D2(tp3b_op op, int32_t mode, double* out) {
+  if (!op || !out) return fail(TP3B_EINVAL, "null argument");
+  if (mode < 0 || mode >= op->nmodes) return fail(TP3B_EINVAL, "mode out of range");
+  std::memcpy(out, op->D2h[mode].data(), sizeof(double) * op->D2h[mode].size());
+  return TP3B_OK;
+}
+
+tp3b_status tp3b_get_V(tp3b_op op, double* out) {
+  if (!op || !out) return fail(TP3B_EINVAL, "null argument");
+  std::memcpy(out, op->Vh.data(), sizeof(double) * op->N);
+  return TP3B_OK;
+}
+
+static tp3b_status check_apply(tp3b_op op, int32_t prec, int32_t nvec, const void* X, int64_t ldx,
+                               void* Y, int64_t ldy) {
+  if (!op) return fail(TP3B_EINVAL, "null operator");
+  if (prec != TP3B_FP64 && prec != TP3B_FP32 && prec != TP3B_BF16X3)
+    return fail(TP3B_EINVAL, "unknown precision");
+  if (prec == TP3B_BF16X3) return fail(TP3B_ENOTSUP, "BF16x3 mode products are not built");
+  if (nvec < 0) return fail(TP3B_EINVAL, "nvec must be >= 0");
+  if (nvec == 0) return TP3B_OK;
+  if (!X || !Y) return fail(TP3B_EINVAL, "null X or Y");
+  if (ldx < op->N || ldy < op->N) return fail(TP3B_EINVAL, "leading dimension smaller than N");
+  const size_t es = prec == TP3B_FP64 ? 8 : 4;
+  const char* xb = (const char*)X;
+  const char* yb = (const char*)Y;
+  const char* xe = xb + es * ((size_t)(nvec - 1) * ldx + op->N);
+  const char* ye = yb + es * ((size_t)(nvec - 1) * ldy + op->N);
+  if (xb < ye && yb < xe) return fail(TP3B_EINVAL, "X and Y overlap");
+  return TP3B_OK;
+}
+
+tp3b_status tp3b_apply_H_shifted(tp3b_op op, int32_t prec, int32_t nvec, const void* X,
+                                 int64_t ldx, void* Y, int64_t ldy, const double* shifts,
+                                 void* stream) {
+  tp3b_status st = check_apply(op, prec, nvec, X, ldx, Y, ldy);
+  if (st != TP3B_OK || nvec == 0) return st;
+  TP3B_HIP(hipSetDevice(op->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == TP3B_FP64)
+    return apply_H_impl<double>(op, nvec, (const double*)X, ldx, (double*)Y, ldy, shifts, s);
+  return apply_H_impl<float>(op, nvec, (const float*)X, ldx, (float*)Y, ldy, shifts, s);
+}
+
+tp3b_status tp3b_apply_H(tp3b_op op, int32_t prec, int32_t nvec, const void* X, int64_t ldx,
+                         void* Y, int64_t ldy, void* stream) {
+  return tp3b_apply_H_shifted(op, prec, nvec, X, ldx, Y, ldy, nullptr, stream);
+}
+
+tp3b_status tp3b_apply_prec(tp3b_op op, int32_t prec, int32_t nvec, const void* X, int64_t ldx,
+                            void* Y, int64_t ldy, void* stream) {
+  tp3b_status st = check_apply(op, prec, nvec, X, ldx, Y, ldy);
+  if (st != TP3B_OK || nvec == 0) return st;
+  if (op->ndim != 1) return fail(TP3B_ENOTSUP, "the kinetic preconditioner is 1D only");
+  if (!op->have_prec) return fail(TP3B_ENOTSUP, "kinetic factors have complex spectrum or K - sigma is singular");
+  TP3B_HIP(hipSetDevice(op->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == TP3B_FP64)
+    return apply_prec_impl<double>(op, nvec, (const double*)X, ldx, (double*)Y, ldy, s);
+  return apply_prec_impl<float>(op, nvec, (const float*)X, ldx, (float*)Y, ldy, s);
+}
+
+tp3b_status tp3b_block_orth(int64_t N, int32_t nq, const double* Q, int64_t ldq, int32_t nx,
+                            double* X, int64_t ldx, double* C_qx, double* R_xx, int32_t* rank,
+                            uint64_t seed, void* stream) {
+  if (N < 0 || nq < 0 || nx < 0) return fail(TP3B_EINVAL, "negative size");
+  if (nx > 32) return fail(TP3B_EINVAL, "nx must be <= 32");
+  if (nx == 0) {
+    if (rank) *rank = 0;
+    return TP3B_OK;
+  }
+  if (!X || (nq > 0 && !Q)) return fail(TP3B_EINVAL, "null X or Q");
+  if (ldx < N || (nq > 0 && ldq < N)) return fail(TP3B_EINVAL, "leading dimension smaller than N");
+  if (N < nq + nx) return fail(TP3B_EINVAL, "N must be >= nq + nx");
+  return block_orth_impl(N, nq, Q, ldq, nx, X, ldx, C_qx, R_xx, rank, seed, (hipStream_t)stream);
+}
+
+tp3b_status tp3b_host_schur(int32_t n, double* A, double* Z, double* wr, double* wi) {
+  if (n < 1 || !A || !wr || !wi) return fail(TP3B_EINVAL, "bad arguments");
+  if (!real_schur(n, A, Z, wr, wi)) return fail(TP3B_ENOCONV, "QR iteration did not converge");
+  return TP3B_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,250 @@
+"""GPU parity: Hamiltonian and preconditioner applies against the oracle.
+
+Bars (written per test): FP64 applies within 1e-12 normwise relative error on
+N(0,1) blocks, and within a GEMM-like componentwise bound on smooth blocks; the
+FP64 preconditioner within 1e-10 of the oracle's Bartels-Stewart solve; FP32
+forms within a componentwise bound of a few FP32 units times n."""
+import numpy as np
+import pytest
+
+from gpu_util import need_gpu, say, to_dev
+from oracle import operator, physics, problem
+from workloads import config, gaussian_bumps_1d, normal_block
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(cfg):
+    t3 = need_gpu()
+    P = problem.make_problem(**cfg)
+    op = t3.Operator.from_config(cfg)
+    return t3, P, op
+
+
+def _absH_absW(P, Xn):
+    """|H||W| per entry (componentwise error scale), 1D."""
+    Kx, Ky = np.abs(P.cx * P.D2[0]), np.abs(P.cy * P.D2[1])
+    out = np.empty_like(Xn)
+    for v in range(Xn.shape[1]):
+        W = np.abs(Xn[:, v]).reshape(P.n[0], P.n[1])
+        out[:, v] = (Kx @ W + W @ Ky.T + np.abs(P.V) * W).ravel()
+    return out
+
+
+def test_setup_matches_oracle():
+    """Library's own grid: D2 and V equal the oracle's (same formulas, written twice)."""
+    for name in ("c1", "c2"):
+        cfg = config(name)
+        _, P, op = _pair(cfg)
+        for k in range(2):
+            D = op.D2(k)
+            assert np.max(np.abs(D - P.D2[k])) <= 1e-13 * np.max(np.abs(P.D2[k]))
+        assert np.max(np.abs(op.V() - P.V.ravel())) <= 1e-14 * max(1.0, np.max(np.abs(P.V)))
+        assert abs(op.sigma - P.two_body_shift()) <= 1e-11 * abs(op.sigma)
+
+
+@pytest.mark.parametrize("name,nvec", [("c1", 4), ("c2", 8), ("c1", 1), ("c2", 3)])
+def test_apply_fp64_random(name, nvec):
+    import torch
+    cfg = config(name)
+    t3, P, op = _pair(cfg)
+    Xn = normal_block(P.N, nvec, cfg["seed_apply"])
+    say("apply fp64", name, nvec)
+    X = to_dev(Xn)
+    Y = torch.empty_like(X)
+    op.apply_H(X, Y)
+    torch.cuda.synchronize()
+    Yr = P.apply(Xn.T).T
+    err = np.linalg.norm(Y.cpu().numpy() - Yr) / np.linalg.norm(Yr)
+    say("  normwise rel err", err)
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("nx,ny,nvec", [(37, 50, 3), (50, 37, 5), (130, 70, 2), (2, 2, 1), (64, 200, 2)])
+def test_apply_fp64_ragged_smooth(nx, ny, nvec):
+    """Ragged (non-tile-multiple, non-square) grids on smooth inputs:
+    componentwise error within 4 (n_x + n_y + 1) eps of |H||W|."""
+    import torch
+    t3 = need_gpu()
+    cx, cy, mu = physics.coeffs_unit_heavy(7.0)
+    P = problem.make_problem(ndim=1, n=(nx, ny), L=(9.0, 6.0), alpha=7.0, v0=1.5, width=0.8)
+    op = t3.Operator(1, [nx, ny], [9.0, 6.0], cx, cy, v0=1.5, width=0.8, mu_hl=mu)
+    Xn = gaussian_bumps_1d(P.grids[0], P.grids[1], nvec, seed=nx * 131 + ny).T.copy()
+    say("apply fp64 ragged", nx, ny, nvec)
+    X = to_dev(Xn.T)
+    Y = torch.empty_like(X)
+    op.apply_H(X, Y)
+    torch.cuda.synchronize()
+    Yr = P.apply(Xn)
+    scale = _absH_absW(P, Xn)
+    err = np.max(np.abs(Y.cpu().numpy().T - Yr) / np.maximum(scale, 1e-300))
+    say("  componentwise", err)
+    assert err <= 4 * (nx + ny + 1) * 2.2e-16
+
+
+def test_apply_shifted_fp64():
+    import torch
+    cfg = config("c1")
+    t3, P, op = _pair(cfg)
+    Xn = normal_block(P.N, 3, 11)
+    sh = np.array([0.5, -1.25, 3.0])
+    X = to_dev(Xn)
+    Y = torch.empty_like(X)
+    op.apply_H(X, Y, shifts=to_dev(sh))
+    torch.cuda.synchronize()
+    Yr = P.apply(Xn.T).T - sh[:, None] * Xn
+    assert np.linalg.norm(Y.cpu().numpy() - Yr) <= 1e-12 * np.linalg.norm(Yr)
+
+
+def test_apply_strided_blocks():
+    """Leading dimension > N (vectors inside a wider buffer)."""
+    import torch
+    cfg = config("c1")
+    t3, P, op = _pair(cfg)
+    Xn = normal_block(P.N, 3, 12)
+    buf = torch.zeros((3, P.N + 17), dtype=torch.float64, device="cuda")
+    buf[:, :P.N] = to_dev(Xn)
+    out = torch.full((3, P.N + 5), 7.0, dtype=torch.float64, device="cuda")
+    op.apply_H(buf[:, :P.N], out[:, :P.N])
+    torch.cuda.synchronize()
+    Yr = P.apply(Xn.T).T
+    o = out.cpu().numpy()
+    assert np.linalg.norm(o[:, :P.N] - Yr) <= 1e-12 * np.linalg.norm(Yr)
+    assert np.all(o[:, P.N:] == 7.0)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_apply_fp32(name):
+    import torch
+    cfg = config(name)
+    t3, P, op = _pair(cfg)
+    Xn = normal_block(P.N, 4, 21).astype(np.float32).astype(np.float64)
+    X = to_dev(Xn, torch.float32)
+    Y = torch.empty_like(X)
+    op.apply_H(X, Y)
+    torch.cuda.synchronize()
+    Yr = P.apply(Xn.T)
+    scale = _absH_absW(P, Xn.T)
+    err = np.max(np.abs(Y.cpu().numpy().astype(np.float64).T - Yr) / scale)
+    nerr = np.linalg.norm(Y.cpu().numpy().T - Yr) / np.linalg.norm(Yr)
+    say("fp32", name, "componentwise", err, "normwise", nerr)
+    assert err <= 4 * (2 * P.n[0] + 2) * 6e-8
+
+
+@pytest.mark.parametrize("name,nvec", [("c1", 4), ("c2", 8), ("c2", 3)])
+def test_prec_fp64_matches_bartels_stewart(name, nvec):
+    import torch
+    cfg = config(name)
+    t3, P, op = _pair(cfg)
+    pc = P.preconditioner()
+    Xn = normal_block(P.N, nvec, cfg["seed_apply"] + 100)
+    X = to_dev(Xn)
+    Y = torch.empty_like(X)
+    say("prec fp64", name, nvec)
+    op.apply_prec(X, Y)
+    torch.cuda.synchronize()
+    Zr = pc.apply(Xn.T).T
+    err = np.linalg.norm(Y.cpu().numpy() - Zr) / np.linalg.norm(Zr)
+    say("  rel err", err)
+    assert err <= 1e-10
+
+
+def test_prec_fp64_ragged():
+    import torch
+    t3 = need_gpu()
+    cx, cy, mu = physics.coeffs_unit_heavy(3.0)
+    P = problem.make_problem(ndim=1, n=(45, 29), L=(10.0, 8.0), alpha=3.0, v0=2.0)
+    op = t3.Operator(1, [45, 29], [10.0, 8.0], cx, cy, v0=2.0, mu_hl=mu)
+    pc = P.preconditioner(sigma=op.sigma)
+    Xn = normal_block(P.N, 3, 5)
+    X = to_dev(Xn)
+    Y = torch.empty_like(X)
+    op.apply_prec(X, Y)
+    torch.cuda.synchronize()
+    Zr = pc.apply(Xn.T).T
+    assert np.linalg.norm(Y.cpu().numpy() - Zr) <= 1e-10 * np.linalg.norm(Zr)
+
+
+def test_prec_fp32():
+    import torch
+    cfg = config("c2")
+    t3, P, op = _pair(cfg)
+    pc = P.preconditioner()
+    Xn = normal_block(P.N, 4, 33).astype(np.float32)
+    X = to_dev(Xn)
+    Y = torch.empty_like(X)
+    op.apply_prec(X, Y)
+    torch.cuda.synchronize()
+    Zr = pc.apply(Xn.T.astype(np.float64)).T
+    err = np.linalg.norm(Y.cpu().numpy() - Zr) / np.linalg.norm(Zr)
+    say("prec fp32 rel err", err)
+    assert err <= 1e-4
+
+
+def test_apply_2d_small():
+    import torch
+    t3 = need_gpu()
+    cx, cy, mu = physics.coeffs_unit_heavy(20.0)
+    n = (9, 9, 7, 7)
+    P = problem.make_problem(ndim=2, n=n, L=(6.0, 6.0, 5.0, 5.0), alpha=20.0, v0=3.0)
+    op = t3.Operator(2, list(n), [6.0, 6.0, 5.0, 5.0], cx, cy, v0=3.0, mu_hl=mu)
+    assert np.max(np.abs(op.V() - P.V.ravel())) <= 1e-14
+    Xn = normal_block(P.N, 3, 41)
+    X = to_dev(Xn)
+    Y = torch.empty_like(X)
+    op.apply_H(X, Y)
+    torch.cuda.synchronize()
+    Yr = P.apply(Xn.T).T
+    Hd = P.kron()
+    assert np.linalg.norm(Yr - (Hd @ Xn.T).T) <= 1e-13 * np.linalg.norm(Yr)
+    err = np.linalg.norm(Y.cpu().numpy() - Yr) / np.linalg.norm(Yr)
+    say("2d small rel err", err)
+    assert err <= 1e-12
+    Y32 = torch.empty((3, P.N), dtype=torch.float32, device="cuda")
+    op.apply_H(X.float(), Y32)
+    torch.cuda.synchronize()
+    err32 = np.linalg.norm(Y32.double().cpu().numpy() - Yr) / np.linalg.norm(Yr)
+    say("2d small fp32 rel err", err32)
+    assert err32 <= 1e-5
+
+
+def _sample_1d(P, Xn, v, idx):
+    nx, ny = P.n
+    W = Xn[v].reshape(nx, ny)
+    out = []
+    for e in idx:
+        i, j = divmod(int(e), ny)
+        val = (-P.cx * (P.D2[0][i, :] @ W[:, j]) - P.cy * (W[i, :] @ P.D2[1][j, :])
+               + P.V[i, j] * W[i, j])
+        out.append(val)
+    return np.array(out)
+
+
+def test_apply_c3_full_size_sampled():
+    """n = 1024, 16 vectors (the low-precision workload's shape) in FP64 and FP32;
+    sampled outputs computed one by one by the oracle's formula."""
+    import torch
+    cfg = config("c3")
+    t3, P, op = _pair(cfg)
+    b = cfg["block"]
+    Xn = normal_block(P.N, b, cfg["seed_apply"])
+    X = to_dev(Xn)
+    Y = torch.empty_like(X)
+    say("c3 fp64 full-size apply")
+    op.apply_H(X, Y)
+    X32 = X.float()
+    Y32 = torch.empty_like(X32)
+    op.apply_H(X32, Y32)
+    torch.cuda.synchronize()
+    Yh, Y32h = Y.cpu().numpy(), Y32.cpu().numpy()
+    rng = np.random.default_rng(0)
+    X32n = X32.double().cpu().numpy()
+    for v in range(0, b, 5):
+        idx = rng.integers(0, P.N, 300)
+        ref = _sample_1d(P, Xn, v, idx)
+        err = np.max(np.abs(Yh[v, idx] - ref)) / np.max(np.abs(ref))
+        ref32 = _sample_1d(P, X32n, v, idx)
+        err32 = np.max(np.abs(Y32h[v, idx] - ref32)) / np.max(np.abs(ref32))
+        say("  vec", v, "fp64 rel", err, "fp32 rel", err32)
+        assert err <= 1e-12
+        assert err32 <= 1e-4

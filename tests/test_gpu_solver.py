@@ -1,0 +1,108 @@
+"""GPU parity: block orthogonalisation and the JDQR eigensolver against the
+oracle (eigenvalues within 1e-10 relative of the FP64 oracle/dense reference)."""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import need_gpu, say, to_dev
+from oracle import dense, orth, problem
+from workloads import config, normal_block
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("N,nq,nx", [(5000, 7, 4), (70000, 40, 8), (1000, 0, 3), (333, 17, 16)])
+def test_block_orth_matches_oracle(N, nq, nx):
+    import torch
+    t3 = need_gpu()
+    rng = np.random.default_rng(N + nq)
+    Q = np.linalg.qr(rng.standard_normal((N, nq)))[0] if nq else np.zeros((N, 0))
+    X = rng.standard_normal((N, nx)) + (Q @ rng.standard_normal((nq, nx)) if nq else 0)
+    Xo, C, R, rank = orth.block_orth(Q, X)
+    Xd = to_dev(X.T)
+    Qd = to_dev(Q.T) if nq else None
+    say("orth", N, nq, nx)
+    Cg, Rg, rk = t3.block_orth(Qd, Xd)
+    torch.cuda.synchronize()
+    assert rk == rank == nx
+    assert np.max(np.abs(Xd.cpu().numpy().T - Xo)) <= 1e-12
+    assert np.max(np.abs(Rg.cpu().numpy() - R)) <= 1e-12 * np.max(np.abs(R))
+    if nq:
+        assert np.max(np.abs(Cg.cpu().numpy() - C)) <= 1e-12 * np.max(np.abs(C))
+
+
+def test_block_orth_rank_deficient():
+    import torch
+    t3 = need_gpu()
+    rng = np.random.default_rng(3)
+    N = 4000
+    Q = np.linalg.qr(rng.standard_normal((N, 5)))[0]
+    X = rng.standard_normal((N, 4))
+    X[:, 2] = X[:, 0] - 2 * X[:, 1] + Q @ np.arange(5.0)
+    Xd = to_dev(X.T)
+    _, _, rk = t3.block_orth(to_dev(Q.T), Xd)
+    torch.cuda.synchronize()
+    Xo = Xd.cpu().numpy().T
+    assert rk == 3
+    assert np.max(np.abs(Xo.T @ Xo - np.eye(4))) <= 1e-12
+    assert np.max(np.abs(Q.T @ Xo)) <= 1e-12
+    # span of the independent input columns is kept
+    for j in (0, 1, 3):
+        r = X[:, j] - Q @ (Q.T @ X[:, j])
+        r -= Xo @ (Xo.T @ r)
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(X[:, j])
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_jdqr_c1_matches_dense(inner):
+    t3 = need_gpu()
+    cfg = config("c1")
+    P = problem.make_problem(**cfg)
+    ref = dense.lowest_eigenvalues(P.kron(), cfg["nev"]).real
+    op = t3.Operator.from_config(cfg)
+    say("jdqr c1", inner)
+    r = op.jdqr(cfg["nev"], cfg["block"], inner_prec=t3.FP64 if inner == "fp64" else t3.FP32,
+                seed=cfg["seed_start"])
+    err = np.max(np.abs(r.evals - ref) / np.abs(ref))
+    say("  evals", r.evals, "err", err, r.stats)
+    assert err <= 1e-10
+    Q = r.Q.cpu().numpy().T
+    assert np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1]))) <= 1e-12
+    HQ = P.apply(Q)
+    assert np.linalg.norm(HQ - Q @ r.R) <= 1e-10 * np.linalg.norm(r.R)
+
+
+def test_jdqr_small_2d_matches_dense():
+    t3 = need_gpu()
+    from oracle import physics
+    cx, cy, mu = physics.coeffs_unit_heavy(20.0)
+    P = problem.make_problem(ndim=2, n=(7, 7, 6, 6), L=6.0, alpha=20.0, v0=3.0)
+    ref = dense.lowest_eigenvalues(P.kron(), 3).real
+    op = t3.Operator(2, [7, 7, 6, 6], 6.0, cx, cy, v0=3.0, mu_hl=mu)
+    r = op.jdqr(3, 4, precond=False, seed=4, max_outer=2000)
+    err = np.max(np.abs(r.evals - ref) / np.abs(ref))
+    say("2d jdqr", r.evals, ref, err, r.stats)
+    assert err <= 1e-10
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"{name}_evals.txt")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return np.loadtxt(path)[:, 0]
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_jdqr_c2_matches_oracle(inner):
+    t3 = need_gpu()
+    cfg = config("c2")
+    ref = _golden("c2")
+    op = t3.Operator.from_config(cfg)
+    say("jdqr c2", inner)
+    r = op.jdqr(cfg["nev"], cfg["block"], inner_prec=t3.FP64 if inner == "fp64" else t3.FP32,
+                seed=cfg["seed_start"])
+    err = np.max(np.abs(r.evals - ref) / np.abs(ref))
+    say("  err", err, r.stats)
+    assert err <= 1e-10
