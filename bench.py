@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the tensor-product three-body eigensolver on one MI355X.
+
+One step is one complete block Jacobi-Davidson QR solve of the workload, from a
+seeded start block to the wanted eigenpairs at the FP64 residual tolerance: it
+runs every stage of the hot path (Hamiltonian applies with the fused potential,
+the kinetic Sylvester preconditioner, GMRES on the correction equation, FP64
+block orthogonalisation and Rayleigh-Ritz).  Operator set-up (grids, potential
+table, preconditioner eigen-factors) happens before the timed region; the start
+block is generated on the device.
+
+Printed: one JSON line with the solve time (value), the Hamiltonian-apply
+throughput of the dominant kernel measured with HIP events inside the timed
+solves against the FP64 MFMA peak (roofline), the eigenvalue error against the
+CPU oracle's stored values, the same solve with FP32 inner GMRES ("mixed"), and
+the CPU oracle timed on this host (cpu_baseline).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H-apply GFLOP/s (% MFMA peak); JDQR s to k eigenpairs @1e-10, mixed vs FP64"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+HBM_PEAK_GBS = 8000.0
+
+
+def apply_flops(n):
+    """Algorithmic flops of one 1D Hamiltonian apply to one vector: two dense
+    mode products (2 n_x n_y (n_x + n_y)) plus the potential term (3 n_x n_y)."""
+    nx, ny = n
+    return 2.0 * nx * ny * (nx + ny) + 3.0 * nx * ny
+
+
+def golden(name):
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_evals.txt")
+    if not os.path.exists(path):
+        return None, None
+    iters = None
+    with open(path) as f:
+        for line in f:
+            if "outer iterations" in line:
+                for tok in line.replace(";", " ").replace(",", " ").split():
+                    if tok.isdigit():
+                        iters = int(tok)
+                        break
+    return np.loadtxt(path)[:, 0], iters
+
+
+def cpu_baseline(cfg, name, sample_iters, full_iters):
+    """The oracle's block JDQR on the same workload, timed for its first
+    `sample_iters` outer iterations and scaled to a full solve."""
+    import numpy as np
+    from oracle import jdqr, problem
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    P = problem.make_problem(**cfg)
+    pc = P.preconditioner()
+    sig = P.two_body_shift()
+    t0 = time.perf_counter()
+    r = jdqr.jdqr(P.apply, P.N, cfg["nev"], cfg["block"], precond=pc.apply,
+                  seed=cfg["seed_start"], target=sig, max_outer=sample_iters)
+    dt = time.perf_counter() - t0
+    n_done = max(r.n_outer, 1)
+    per_iter = dt / n_done
+    full = full_iters if full_iters else n_done
+    return {"value": per_iter * full, "unit": "s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"first {n_done} of the oracle's {full} outer iterations of the {name} "
+                       f"solve ({dt:.1f} s measured), scaled to the full solve; "
+                       f"NumPy/SciPy FP64, {threads} BLAS threads")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=3)
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2111_02534_amd as t3
+    from workloads import config
+
+    torch.cuda.init()
+    cfg = config(args.config)
+    nev, b = cfg["nev"], cfg["block"]
+    op = t3.Operator.from_config(cfg)
+    n = (cfg["n"], cfg["n"])
+    ref, ref_iters = golden(args.config)
+
+    def solve(inner, profile=False):
+        return op.jdqr(nev, b, inner_prec=inner, seed=cfg["seed_start"], want_Q=False,
+                       profile=profile)
+
+    for _ in range(args.warmup):
+        solve(t3.FP64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for _ in range(args.steps):
+        res.append(solve(t3.FP64, profile=True))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s_per_solve = elapsed / args.steps
+
+    # Dominant kernel: the FP64 Hamiltonian apply (b vectors per launch).
+    t_k = sum(r.stats["t_kernel"][0] for r in res)
+    n_k = sum(r.stats["n_kernel"][0] for r in res)
+    n_vec = sum(r.stats["n_apply_H_fp64"] for r in res)
+    vec_per_launch = n_vec / max(n_k, 1)
+    flops_launch = vec_per_launch * apply_flops(n)
+    avg_launch_s = t_k / max(n_k, 1)
+    achieved_tf = flops_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
+    t_prec = sum(r.stats["t_kernel"][2] for r in res)
+    err = None
+    if ref is not None:
+        err = float(max(np.max(np.abs(r.evals - ref) / np.abs(ref)) for r in res))
+
+    out = {
+        "metric": METRIC,
+        "value": s_per_solve,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * s_per_solve,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"{args.config}: 1D three-body, n={cfg['n']} per Jacobi coordinate "
+                                f"(N={op.N}), M/m={cfg['alpha']}, Gaussian V0={cfg['v0']}, "
+                                f"w={cfg['width']}, lowest {nev} eigenpairs, block {b}, "
+                                f"FP64 JDQR + Sylvester preconditioner"),
+                   "n": cfg["n"], "nev": nev, "block": b},
+        "roofline": {"bound": "mfma", "achieved": achieved_tf, "peak": PEAK_TFLOPS["f64"],
+                     "unit": "TFLOP/s", "frac": achieved_tf / PEAK_TFLOPS["f64"], "traffic": None,
+                     "kernel": "k_modeprod<double,*,*,16,0> (H apply, fused potential)",
+                     "launch_flops": flops_launch, "avg_launch_us": 1e6 * avg_launch_s,
+                     "launches": n_k},
+        "h_apply_gflops": achieved_tf * 1e3,
+        "jdqr": {"s_per_solve": s_per_solve, "outer_iters": res[-1].stats["n_outer"],
+                 "apply_H_vectors": res[-1].stats["n_apply_H_fp64"],
+                 "apply_prec_vectors": res[-1].stats["n_apply_prec"],
+                 "kernel_time_frac_H": t_k / elapsed, "kernel_time_frac_prec": t_prec / elapsed,
+                 "eig_max_rel_err_vs_oracle": err},
+    }
+    if not args.no_mixed:
+        solve(t3.FP32)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mres = [solve(t3.FP32) for _ in range(max(1, args.steps // 2))]
+        torch.cuda.synchronize()
+        m_s = (time.perf_counter() - t1) / len(mres)
+        m_err = None
+        if ref is not None:
+            m_err = float(max(np.max(np.abs(r.evals - ref) / np.abs(ref)) for r in mres))
+        out["mixed_vs_fp64"] = {"fp64_s": s_per_solve, "mixed_s": m_s, "speedup": s_per_solve / m_s,
+                                "mixed_outer_iters": mres[-1].stats["n_outer"],
+                                "mixed_eig_max_rel_err_vs_oracle": m_err}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.config, args.cpu_sample_iters, ref_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -148,12 +148,18 @@ typedef struct {
   uint64_t seed;        /* start block and rank-repair vectors */
   int32_t check_finite; /* reject NaN/Inf in X0 */
   int32_t verbose;      /* print one line per outer iteration to stderr */
+  int32_t profile;      /* time the mode-product launches with HIP events (stats) */
 } tp3b_jdqr_opts;
 
 typedef struct {
   int32_t n_conv, n_outer, n_restart, n_lock_events;
   int64_t n_apply_H_fp64, n_apply_H_low, n_apply_prec;
   double t_apply, t_prec, t_orth, t_rr, t_gmres, t_total; /* seconds */
+  /* with opts.profile: device time (s) and launch-group count of
+     [0] FP64 H applies, [1] low-precision H applies,
+     [2] FP64 preconditioner applies, [3] low-precision preconditioner applies */
+  double t_kernel[4];
+  int64_t n_kernel[4];
 } tp3b_jdqr_stats;
 
 tp3b_status tp3b_jdqr_default_opts(tp3b_jdqr_opts* opts);

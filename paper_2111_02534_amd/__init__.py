@@ -47,7 +47,7 @@ class JdqrOpts(ctypes.Structure):
                 ("inner_prec", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("switch_tol", ctypes.c_double), ("target", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("check_finite", ctypes.c_int32),
-                ("verbose", ctypes.c_int32)]
+                ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32)]
 
 
 class JdqrStats(ctypes.Structure):
@@ -56,10 +56,15 @@ class JdqrStats(ctypes.Structure):
                 ("n_apply_H_fp64", ctypes.c_int64), ("n_apply_H_low", ctypes.c_int64),
                 ("n_apply_prec", ctypes.c_int64), ("t_apply", ctypes.c_double),
                 ("t_prec", ctypes.c_double), ("t_orth", ctypes.c_double), ("t_rr", ctypes.c_double),
-                ("t_gmres", ctypes.c_double), ("t_total", ctypes.c_double)]
+                ("t_gmres", ctypes.c_double), ("t_total", ctypes.c_double),
+                ("t_kernel", ctypes.c_double * 4), ("n_kernel", ctypes.c_int64 * 4)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if name in ("t_kernel", "n_kernel") else v
+        return out
 
 
 EXPORTS = ["tp3b_create", "tp3b_destroy", "tp3b_op_info", "tp3b_get_D2", "tp3b_get_V",
@@ -244,7 +249,7 @@ class Operator:
 
     def jdqr(self, nev, block, *, X0=None, inner_prec=FP64, precond=True, tol=1e-12,
              gmres_steps=10, m_min=0, m_max=0, max_outer=1000, seed=0, switch_tol=1e-2,
-             target=None, verbose=False, want_Q=True):
+             target=None, verbose=False, want_Q=True, profile=False):
         import numpy as np
         import torch
         o = JdqrOpts()
@@ -253,7 +258,7 @@ class Operator:
         o.gmres_steps, o.max_outer, o.precond = gmres_steps, max_outer, int(bool(precond))
         o.inner_prec, o.tol, o.switch_tol = inner_prec, tol, switch_tol
         o.target = float("nan") if target is None else float(target)
-        o.seed, o.verbose = seed, int(verbose)
+        o.seed, o.verbose, o.profile = seed, int(verbose), int(profile)
         evals = np.empty(nev)
         R = np.empty((nev, nev), order="F")
         res = np.empty(nev)

@@ -52,6 +52,42 @@ std::vector<double> colmajor(const std::vector<double>& A, int ld, int r0, int c
   return out;
 }
 
+// Optional HIP-event timing of the mode-product launches inside the solve:
+// kind 0 = FP64 Hamiltonian applies, 1 = low-precision Hamiltonian applies,
+// 2 = FP64 preconditioner applies, 3 = low-precision preconditioner applies.
+struct KernelTimer {
+  bool on = false;
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;
+  size_t used = 0;
+  hipError_t mark(int k) {
+    if (!on) return hipSuccess;
+    if (used == ev.size()) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ev.push_back(e);
+      kind.push_back(-1);
+    }
+    kind[used] = k;
+    return hipEventRecord(ev[used++], s);
+  }
+  // pairs (2i, 2i+1) bracket one launch group
+  void collect(double* t, int64_t* n) {
+    for (size_t i = 0; i + 1 < used; i += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) {
+        t[kind[i]] += 1e-3 * ms;
+        n[kind[i]] += 1;
+      }
+    }
+  }
+  ~KernelTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -71,6 +107,9 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   const bool low = sizeof(TW) == 4;
   const double target = std::isnan(o.target) ? op->sigma : o.target;
   tp3b_jdqr_stats stats{};
+  KernelTimer kt;
+  kt.on = o.profile != 0;
+  kt.s = s;
 
   // ---- device buffers
   const int qv_cols = nev + m_max + b;
@@ -140,7 +179,18 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   auto AV = [&]() { return AVbase + (int64_t)av0 * N; };
   auto applyA64 = [&](int nv, const double* X, double* Y) -> tp3b_status {
     stats.n_apply_H_fp64 += nv;
-    return apply_H_impl<double>(op, nv, X, N, Y, N, nullptr, s);
+    TP3B_HIP(kt.mark(0));
+    tp3b_status r = apply_H_impl<double>(op, nv, X, N, Y, N, nullptr, s);
+    TP3B_HIP(kt.mark(0));
+    return r;
+  };
+  auto applyW = [&](int nv, const TW* X, TW* Y, const double* sh) -> tp3b_status {
+    const int kd = low ? 1 : 0;
+    (low ? stats.n_apply_H_low : stats.n_apply_H_fp64) += nv;
+    TP3B_HIP(kt.mark(kd));
+    tp3b_status r = apply_H_impl<TW>(op, nv, X, N, Y, N, sh, s);
+    TP3B_HIP(kt.mark(kd));
+    return r;
   };
   auto dot = [&](int p, int q, const double* A, const double* B, std::vector<double>& host,
                  int ldc) -> tp3b_status {
@@ -334,7 +384,11 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     const double tg0 = now();
     auto precond_w = [&](const TW* in, TW* out) -> tp3b_status {
       stats.n_apply_prec += nb;
-      return apply_prec_impl<TW>(op, nb, in, N, out, N, s);
+      const int kd = low ? 3 : 2;
+      TP3B_HIP(kt.mark(kd));
+      tp3b_status r = apply_prec_impl<TW>(op, nb, in, N, out, N, s);
+      TP3B_HIP(kt.mark(kd));
+      return r;
     };
     auto project = [&](TW* Zp) -> tp3b_status {
       TP3B_HIP((launch_dot_tn<TW, TW>(N, nqt, nb, Qtw, N, Zp, N, dC2, nqt, part, s)));
@@ -358,16 +412,12 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       TW* vk = Vg + (int64_t)kk * bs;
       TW* w = W;
       if (use_prec) {
-        stats.n_apply_H_low += low ? nb : 0;
-        stats.n_apply_H_fp64 += low ? 0 : nb;
-        tp3b_status as = apply_H_impl<TW>(op, nb, vk, N, Zt, N, dShift, s);
+        tp3b_status as = applyW(nb, vk, Zt, dShift);
         if (as != TP3B_OK) return as;
         tp3b_status ps = precond_w(Zt, w);
         if (ps != TP3B_OK) return ps;
       } else {
-        stats.n_apply_H_low += low ? nb : 0;
-        stats.n_apply_H_fp64 += low ? 0 : nb;
-        tp3b_status as = apply_H_impl<TW>(op, nb, vk, N, w, N, dShift, s);
+        tp3b_status as = applyW(nb, vk, w, dShift);
         if (as != TP3B_OK) return as;
       }
       { tp3b_status ps = project(w); if (ps != TP3B_OK) return ps; }
@@ -471,6 +521,10 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   if (Rout) std::memcpy(Rout, Rl.data(), sizeof(double) * nev * nev);
   if (resnorm)
     for (int i = 0; i < nev; ++i) resnorm[i] = i < (int)lockres.size() ? lockres[i] : NAN;
+  if (kt.on) {
+    TP3B_HIP(hipStreamSynchronize(s));
+    kt.collect(stats.t_kernel, stats.n_kernel);
+  }
   stats.n_conv = nconv;
   stats.n_outer = outer;
   stats.t_total = now() - t_start;

@@ -53,7 +53,10 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t g, int64_t G) {
 }
 
 // ------------------------------------------------------------------ mode product
-template <typename T, int TM, int TN, int KC>
+// ROLE only separates the kernel names seen by profilers: 0 = Hamiltonian apply
+// (both modes + potential), 1 = preconditioner mode products, 2 = 2D x-mode
+// accumulation passes.
+template <typename T, int TM, int TN, int KC, int ROLE>
 __global__ __launch_bounds__(256) void k_modeprod(ModeProd<T> a) {
   typedef typename Mma<T>::acc_t acc_t;
   constexpr int WM = TM / 2, WN = TN / 2;
@@ -187,29 +190,40 @@ __global__ __launch_bounds__(256) void k_modeprod(ModeProd<T> a) {
       }
 }
 
+template <typename T, int ROLE>
+static void launch_role(const ModeProd<T>& a, int tile, hipStream_t s, unsigned g32, unsigned g64,
+                        unsigned g128, unsigned g64x128) {
+  switch (tile) {
+    case TILE_32:
+      hipLaunchKernelGGL((k_modeprod<T, 32, 32, 16, ROLE>), dim3(g32), dim3(256), 0, s, a);
+      break;
+    case TILE_64:
+      hipLaunchKernelGGL((k_modeprod<T, 64, 64, 16, ROLE>), dim3(g64), dim3(256), 0, s, a);
+      break;
+    case TILE_128:
+      hipLaunchKernelGGL((k_modeprod<T, 128, 128, 16, ROLE>), dim3(g128), dim3(256), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_modeprod<T, 64, 128, 16, ROLE>), dim3(g64x128), dim3(256), 0, s, a);
+      break;
+  }
+}
+
 template <typename T>
 hipError_t launch_modeprod(const ModeProd<T>& a, int tile, hipStream_t s) {
   if (a.M <= 0 || a.Nc <= 0 || a.nbatch <= 0) return hipSuccess;
+  if (tile < 0 || tile >= NUM_TILE_CFGS) return hipErrorInvalidValue;
   auto grid = [&](int TM, int TN) {
     int64_t tiles = (int64_t)((a.M + TM - 1) / TM) * ((a.Nc + TN - 1) / TN);
     return (unsigned)(tiles * a.nbatch);
   };
-  switch (tile) {
-    case TILE_32:
-      hipLaunchKernelGGL((k_modeprod<T, 32, 32, 16>), dim3(grid(32, 32)), dim3(256), 0, s, a);
-      break;
-    case TILE_64:
-      hipLaunchKernelGGL((k_modeprod<T, 64, 64, 16>), dim3(grid(64, 64)), dim3(256), 0, s, a);
-      break;
-    case TILE_128:
-      hipLaunchKernelGGL((k_modeprod<T, 128, 128, 16>), dim3(grid(128, 128)), dim3(256), 0, s, a);
-      break;
-    case TILE_64x128:
-      hipLaunchKernelGGL((k_modeprod<T, 64, 128, 16>), dim3(grid(64, 128)), dim3(256), 0, s, a);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+  const unsigned g32 = grid(32, 32), g64 = grid(64, 64), g128 = grid(128, 128), g6412 = grid(64, 128);
+  if (a.L && a.R && a.epi == EPI_V)
+    launch_role<T, 0>(a, tile, s, g32, g64, g128, g6412);
+  else if (a.acc)
+    launch_role<T, 2>(a, tile, s, g32, g64, g128, g6412);
+  else
+    launch_role<T, 1>(a, tile, s, g32, g64, g128, g6412);
   return hipGetLastError();
 }
 
@@ -308,9 +322,13 @@ __global__ __launch_bounds__(256) void k_dot_tn(int64_t N, int p, int q, const T
   for (int e = tid; e < DOT_TP * DOT_TQ; e += 256) out[e] = red[e];
 }
 
-__global__ void k_dot_reduce(int p, int q, int nchunk, int tiles_q, const double* __restrict__ part,
-                             double* __restrict__ C, int ldc) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per output element: lanes stride over the workgroup partials,
+// then a shuffle reduction (fixed order, so the result is deterministic).
+__global__ __launch_bounds__(256) void k_dot_reduce(int p, int q, int nchunk, int tiles_q,
+                                                    const double* __restrict__ part,
+                                                    double* __restrict__ C, int ldc) {
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);  // element within the tile
   const int tile = blockIdx.y;
   if (e >= DOT_TP * DOT_TQ) return;
   const int pi = e % DOT_TP, qj = e / DOT_TP;
@@ -318,8 +336,9 @@ __global__ void k_dot_reduce(int p, int q, int nchunk, int tiles_q, const double
   if (gp >= p || gq >= q) return;
   const double* src = part + (int64_t)tile * nchunk * (DOT_TP * DOT_TQ) + e;
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += src[(int64_t)c * (DOT_TP * DOT_TQ)];
-  C[gp + (int64_t)gq * ldc] = s;
+  for (int c = lane; c < nchunk; c += 64) s += src[(int64_t)c * (DOT_TP * DOT_TQ)];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) C[gp + (int64_t)gq * ldc] = s;
 }
 
 template <typename TA, typename TB>
@@ -339,8 +358,11 @@ hipError_t launch_dot_tn(int64_t N, int p, int q, const TA* A, int64_t lda, cons
   const int tq = (q + DOT_TQ - 1) / DOT_TQ, tp = (p + DOT_TP - 1) / DOT_TP;
   hipLaunchKernelGGL((k_dot_tn<TA, TB>), dim3(nchunk, tp * tq), dim3(256), 0, s, N, p, q, A, lda, B,
                      ldb, rc, tq, partial);
-  hipLaunchKernelGGL(k_dot_reduce, dim3((DOT_TP * DOT_TQ + 255) / 256, tp * tq), dim3(256), 0, s, p,
-                     q, nchunk, tq, partial, C, ldc);
+  // Only the elements of the tile inside p x q are reduced; with the tile's
+  // column-major element order that is the first min(q, 32) columns.
+  const int qcols = q < DOT_TQ ? q : DOT_TQ;
+  hipLaunchKernelGGL(k_dot_reduce, dim3((qcols * DOT_TP + 3) / 4, tp * tq), dim3(256), 0, s, p, q,
+                     nchunk, tq, partial, C, ldc);
   return hipGetLastError();
 }
 
@@ -459,14 +481,17 @@ __global__ __launch_bounds__(256) void k_bdot_diag(int64_t N, int b, int nb, con
   }
 }
 
-__global__ void k_bdot_reduce(int b, int nb, int nchunk, const double* __restrict__ part,
-                              double* __restrict__ H, int hld) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_bdot_reduce(int b, int nb, int nchunk,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ H, int hld) {
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (e >= b * nb) return;
   const int j = e / nb, i = e % nb;
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[((int64_t)c * b + j) * BD_MAXNB + i];
-  H[(int64_t)j * hld + i] = s;
+  for (int c = lane; c < nchunk; c += 64) s += part[((int64_t)c * b + j) * BD_MAXNB + i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) H[(int64_t)j * hld + i] = s;
 }
 
 template <typename T>
@@ -478,8 +503,8 @@ hipError_t launch_bdot_diag(int64_t N, int b, int nb, const T* V, int64_t bs, co
   const int nchunk = (int)((N + rows - 1) / rows);
   hipLaunchKernelGGL((k_bdot_diag<T>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W, rows,
                      partial);
-  hipLaunchKernelGGL(k_bdot_reduce, dim3((b * nb + 255) / 256), dim3(256), 0, s, b, nb, nchunk,
-                     partial, H, hld);
+  hipLaunchKernelGGL(k_bdot_reduce, dim3((b * nb + 3) / 4), dim3(256), 0, s, b, nb, nchunk, partial,
+                     H, hld);
   return hipGetLastError();
 }
 template hipError_t launch_bdot_diag<double>(int64_t, int, int, const double*, int64_t,
