@@ -177,6 +177,18 @@ tp3b_status tp3b_jdqr_solve(tp3b_op op, const tp3b_jdqr_opts* opts, const double
                             double* evals, double* Q, double* R, double* resnorm,
                             tp3b_jdqr_stats* stats);
 
+/* Mode-product tile shape used by this operator's applies: 0 = 32x32,
+ * 1 = 64x64, 2 = 128x128, 3 = 64x128 output tile per 256-thread workgroup;
+ * -1 restores the built-in choice (or the autotuned one, see below). */
+tp3b_status tp3b_set_tile(tp3b_op op, int32_t tile);
+
+/* Autotuner: times every tile shape for the Hamiltonian apply and the
+ * preconditioner of this operator at `nvec` vectors in precision `prec` on
+ * scratch blocks (HIP events, `reps` repetitions each) and keeps the fastest
+ * per (precision, apply kind).  Synchronous; allocates and frees its scratch
+ * blocks.  best_ms (optional, host 2 doubles) receives the winning times. */
+tp3b_status tp3b_autotune(tp3b_op op, int32_t prec, int32_t nvec, int32_t reps, double* best_ms);
+
 /* Library-internal dense host routine exposed for host-side testing: real Schur
  * form of a small n x n row-major matrix A (overwritten by T), Schur vectors Z
  * (row-major, may be NULL), eigenvalue real/imaginary parts wr, wi. */

@@ -69,7 +69,8 @@ class JdqrStats(ctypes.Structure):
 
 EXPORTS = ["tp3b_create", "tp3b_destroy", "tp3b_op_info", "tp3b_get_D2", "tp3b_get_V",
            "tp3b_apply_H", "tp3b_apply_H_shifted", "tp3b_apply_prec", "tp3b_block_orth",
-           "tp3b_jdqr_default_opts", "tp3b_jdqr_solve", "tp3b_host_schur", "tp3b_last_error"]
+           "tp3b_jdqr_default_opts", "tp3b_jdqr_solve", "tp3b_host_schur", "tp3b_last_error",
+           "tp3b_set_tile", "tp3b_autotune"]
 
 _lib = None
 
@@ -96,6 +97,8 @@ def lib():
         L.tp3b_jdqr_solve.argtypes = [vp, ctypes.POINTER(JdqrOpts), vp, i32, dp, vp, dp, dp,
                                       ctypes.POINTER(JdqrStats)]
         L.tp3b_host_schur.argtypes = [i32, dp, dp, dp, dp]
+        L.tp3b_set_tile.argtypes = [vp, i32]
+        L.tp3b_autotune.argtypes = [vp, i32, i32, i32, dp]
         L.tp3b_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
             if name != "tp3b_last_error":
@@ -198,6 +201,19 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+    def set_tile(self, tile):
+        """Force a mode-product tile shape (0: 32x32, 1: 64x64, 2: 128x128,
+        3: 64x128; -1: automatic)."""
+        _check(lib().tp3b_set_tile(self.handle, int(tile)))
+
+    def autotune(self, prec=FP64, nvec=1, reps=5):
+        """Time every tile shape for this operator's applies and keep the fastest.
+        Returns the best (H apply, preconditioner) times in ms."""
+        import numpy as np
+        best = np.full(2, np.nan)
+        _check(lib().tp3b_autotune(self.handle, prec, nvec, reps, _dbl_ptr(best)))
+        return best
 
     def D2(self, mode):
         import numpy as np

@@ -1,0 +1,80 @@
+"""Times the Hamiltonian and preconditioner applies of a workload on the GPU for
+every mode-product tile shape (HIP events), then runs the autotuner.
+
+    python -m paper_2111_02534_amd.apply_bench c3 [c2 ...] [--reps 20]
+
+Reports microseconds per apply of the workload's block and the algorithmic
+throughput against the MFMA peak of the precision (FP64 78.6, FP32 157.3
+TFLOP/s).  1D flops per vector: 4n^3 + 3n^2 (H), 8n^3 + n^2 (preconditioner);
+2D: 8n^5 + 3n^4 (H)."""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"float64": 78.6, "float32": 157.3}
+
+
+def flops(ndim, n, nvec, kind):
+    if ndim == 2:
+        return nvec * (8.0 * n ** 5 + 3.0 * n ** 4)
+    return nvec * ((4.0 * n ** 3 + 3.0 * n ** 2) if kind == "H" else (8.0 * n ** 3 + n ** 2))
+
+
+def main():
+    import torch
+
+    import paper_2111_02534_amd as t3
+    from workloads import config
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("names", nargs="+")
+    ap.add_argument("--reps", type=int, default=20)
+    args = ap.parse_args()
+    for name in args.names:
+        cfg = config(name)
+        n, b, ndim = cfg["n"], cfg["block"], cfg["ndim"]
+        t0 = time.time()
+        op = t3.Operator.from_config(cfg)
+        print(f"== {name}: ndim={ndim} n={n} N={op.N} block={b} (create {time.time() - t0:.1f} s)",
+              flush=True)
+        for dt, pk in [(torch.float64, t3.FP64), (torch.float32, t3.FP32)]:
+            X = torch.randn((b, op.N), dtype=dt, device="cuda")
+            Y = torch.empty_like(X)
+            kinds = ("H", "P") if ndim == 1 else ("H",)
+            for tile in range(4):
+                tm, tn = [(32, 32), (64, 64), (128, 128), (64, 128)][tile]
+                if tile and (tm > n or tn > n) and ndim == 1:
+                    continue
+                op.set_tile(tile)
+                for kind in kinds:
+                    f = op.apply_H if kind == "H" else op.apply_prec
+                    f(X, Y)
+                    torch.cuda.synchronize()
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(args.reps):
+                        f(X, Y)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / args.reps
+                    tf = flops(ndim, n, b, kind) / ms / 1e9
+                    name_dt = str(dt).replace("torch.", "")
+                    print(f"  {name_dt} tile {tm}x{tn} {kind}: {1e3 * ms:10.1f} us  {tf:7.2f} TFLOP/s"
+                          f"  {100 * tf / PEAK[name_dt]:5.1f}% of peak", flush=True)
+            op.set_tile(-1)
+            if ndim == 1:
+                best = op.autotune(pk, b, 5)
+                print(f"  autotuned best: H {1e3 * best[0]:.1f} us, P {1e3 * best[1]:.1f} us", flush=True)
+        op.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -48,8 +48,9 @@ struct tp3b_op_s {
   tp3b::DevOps<double> d64;
   tp3b::DevOps<float> d32;
   int work_vecs = 0;
-  // tile choice per (precision, kernel role); -1 = heuristic
+  // tile choice: explicit override, else autotuned [prec][0 = H, 1 = prec], else heuristic
   int tile_override = -1;
+  int tuned[2][2] = {{-1, -1}, {-1, -1}};
 };
 
 namespace tp3b {

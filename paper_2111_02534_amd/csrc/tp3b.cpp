@@ -161,6 +161,13 @@ static tp3b_status upload_ops(tp3b_op op, tp3b::DevOps<T>& d, const std::vector<
 }
 
 // -------------------------------------------------------------- applies
+static int tile_for(tp3b_op op, bool f64, int kind, int M, int Nc, int64_t nbatch) {
+  if (op->tile_override >= 0) return op->tile_override;
+  const int t = op->tuned[f64 ? 0 : 1][kind];
+  if (t >= 0) return t;
+  return choose_tile(M, Nc, nbatch, f64);
+}
+
 template <typename T>
 static tp3b::DevOps<T>& ops_for(tp3b_op op);
 template <>
@@ -192,8 +199,7 @@ tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, in
     a.shifts = shifts;
     a.epi = EPI_V;
     a.acc = 0;
-    int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, nvec, f64);
-    TP3B_HIP(launch_modeprod(a, tile, s));
+    TP3B_HIP(launch_modeprod(a, tile_for(op, f64, 0, a.M, a.Nc, nvec), s));
     return TP3B_OK;
   }
   // 2D (eq. (11)): pass A applies the two y modes and the potential on every
@@ -282,7 +288,7 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
     a.per_vec = 1;
     a.nbatch = nv;
     a.sigma = op->sigma;
-    int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(nx, ny, nv, f64);
+    const int tile = tile_for(op, f64, 1, nx, ny, nv);
     // 1: W = Sx^{-1} B
     a.X = Xc; a.ldx = ldx; a.Y = d.work; a.ldy = N;
     a.L = d.Sxi; a.R = nullptr; a.epi = EPI_NONE;
@@ -417,6 +423,63 @@ tp3b_status block_orth_impl(int64_t N, int nq, const double* Q, int64_t ldq, int
     TP3B_HIP(hipMemcpy(C_qx, C.data(), sizeof(double) * nq * nx, hipMemcpyHostToDevice));
   }
   return TP3B_OK;
+}
+
+template <typename T>
+static tp3b_status autotune_impl(tp3b_op op, int nvec, int reps, double* best_ms) {
+  const int pi = sizeof(T) == 8 ? 0 : 1;
+  T *X = nullptr, *Y = nullptr;
+  hipEvent_t e0, e1;
+  TP3B_HIP(hipMalloc((void**)&X, sizeof(T) * op->N * nvec));
+  if (hipMalloc((void**)&Y, sizeof(T) * op->N * nvec) != hipSuccess) {
+    (void)hipFree(X);
+    return fail(TP3B_ENOMEM, "autotune: scratch allocation failed");
+  }
+  tp3b_status st = TP3B_OK;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  for (int kind = 0; kind < 2 && st == TP3B_OK; ++kind) {
+    if (kind == 1 && (op->ndim != 1 || !op->have_prec)) break;
+    double best = 1e300;
+    int best_tile = -1;
+    // The timing does not depend on the values; a zero block avoids any
+    // overflow in the preconditioner's divide.
+    (void)hipMemset(X, 0, sizeof(T) * op->N * nvec);
+    const int saved = op->tile_override;
+    for (int tile = 0; tile < NUM_TILE_CFGS; ++tile) {
+      const int tm = (tile == TILE_32) ? 32 : (tile == TILE_128 ? 128 : 64);
+      const int tn = (tile == TILE_32) ? 32 : ((tile == TILE_64) ? 64 : 128);
+      if (tile != TILE_32 && (tm > op->n[op->ndim == 1 ? 0 : 2] || tn > op->n[op->ndim == 1 ? 1 : 3])) continue;
+      op->tile_override = tile;
+      auto run = [&]() -> tp3b_status {
+        return kind == 0 ? apply_H_impl<T>(op, nvec, X, op->N, Y, op->N, nullptr, nullptr)
+                         : apply_prec_impl<T>(op, nvec, X, op->N, Y, op->N, nullptr);
+      };
+      st = run();  // warm-up
+      if (st != TP3B_OK) break;
+      (void)hipEventRecord(e0, nullptr);
+      for (int r = 0; r < reps && st == TP3B_OK; ++r) st = run();
+      (void)hipEventRecord(e1, nullptr);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double per = ms / reps;
+      if (per < best) {
+        best = per;
+        best_tile = tile;
+      }
+    }
+    op->tile_override = saved;
+    if (st == TP3B_OK) {
+      op->tuned[pi][kind] = best_tile;
+      if (best_ms) best_ms[kind] = best;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(X);
+  (void)hipFree(Y);
+  return st;
 }
 
 }  // namespace tp3b
@@ -647,6 +710,24 @@ tp3b_status tp3b_block_orth(int64_t N, int32_t nq, const double* Q, int64_t ldq,
   if (ldx < N || (nq > 0 && ldq < N)) return fail(TP3B_EINVAL, "leading dimension smaller than N");
   if (N < nq + nx) return fail(TP3B_EINVAL, "N must be >= nq + nx");
   return block_orth_impl(N, nq, Q, ldq, nx, X, ldx, C_qx, R_xx, rank, seed, (hipStream_t)stream);
+}
+
+tp3b_status tp3b_set_tile(tp3b_op op, int32_t tile) {
+  if (!op) return fail(TP3B_EINVAL, "null operator");
+  if (tile < -1 || tile >= NUM_TILE_CFGS) return fail(TP3B_EINVAL, "unknown tile shape");
+  op->tile_override = tile;
+  return TP3B_OK;
+}
+
+tp3b_status tp3b_autotune(tp3b_op op, int32_t prec, int32_t nvec, int32_t reps, double* best_ms) {
+  if (!op) return fail(TP3B_EINVAL, "null operator");
+  if (nvec < 1 || reps < 1) return fail(TP3B_EINVAL, "nvec and reps must be >= 1");
+  if (prec == TP3B_BF16X3) return fail(TP3B_ENOTSUP, "BF16x3 mode products are not built");
+  if (prec != TP3B_FP64 && prec != TP3B_FP32) return fail(TP3B_EINVAL, "unknown precision");
+  TP3B_HIP(hipSetDevice(op->device));
+  if (best_ms) best_ms[0] = best_ms[1] = NAN;
+  return prec == TP3B_FP64 ? autotune_impl<double>(op, nvec, reps, best_ms)
+                           : autotune_impl<float>(op, nvec, reps, best_ms);
 }
 
 tp3b_status tp3b_host_schur(int32_t n, double* A, double* Z, double* wr, double* wi) {
