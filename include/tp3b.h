@@ -49,7 +49,10 @@ typedef enum {
 
 /* Compute precision of the mode products.  FP64: MFMA f64.  FP32: MFMA f32 with
  * FP32 accumulation.  BF16X3: each FP32 operand split into bf16 hi + lo, the
- * product formed as hi*hi + hi*lo + lo*hi on bf16 MFMA with FP32 accumulation. */
+ * product formed as hi*hi + hi*lo + lo*hi on bf16 MFMA with FP32 accumulation
+ * (about 16 significant bits per product; the potential term and the
+ * preconditioner's divide stay FP32).  Mode products with an output tile of
+ * 32 x 32 run as 64 x 64 in BF16X3. */
 typedef enum { TP3B_FP64 = 0, TP3B_FP32 = 1, TP3B_BF16X3 = 2 } tp3b_prec;
 
 /* Pair potential u(r) between the light particle and one heavy particle; the

@@ -245,9 +245,17 @@ class Operator:
             return 1, self.N, self.N
         return X.shape[0], X.stride(0), Y.stride(0)
 
+    def _prec(self, X, prec):
+        p = self._prec_of(X)
+        if prec is None:
+            return p
+        if (prec == FP64) != (p == FP64):
+            raise TypeError("FP64 applies take float64 blocks, FP32/BF16X3 applies float32 blocks")
+        return int(prec)
+
     def apply_H(self, X, Y, prec=None, shifts=None, stream=None):
         nvec, ldx, ldy = self._blk(X, Y)
-        p = self._prec_of(X) if prec is None else prec
+        p = self._prec(X, prec)
         if shifts is None:
             _check(lib().tp3b_apply_H(self.handle, p, nvec, _ptr(X), ldx, _ptr(Y), ldy,
                                       _stream(stream)))
@@ -258,7 +266,7 @@ class Operator:
 
     def apply_prec(self, X, Y, prec=None, stream=None):
         nvec, ldx, ldy = self._blk(X, Y)
-        p = self._prec_of(X) if prec is None else prec
+        p = self._prec(X, prec)
         _check(lib().tp3b_apply_prec(self.handle, p, nvec, _ptr(X), ldx, _ptr(Y), ldy,
                                      _stream(stream)))
         return Y

@@ -5,7 +5,9 @@ every mode-product tile shape (HIP events), then runs the autotuner.
 
 Reports microseconds per apply of the workload's block and the algorithmic
 throughput against the MFMA peak of the precision (FP64 78.6, FP32 157.3
-TFLOP/s).  1D flops per vector: 4n^3 + 3n^2 (H), 8n^3 + n^2 (preconditioner);
+TFLOP/s; BF16x3 is reported as FP32-equivalent TFLOP/s and as a fraction of the
+2.5 PFLOP/s dense bf16 peak counting its three bf16 products per FP32 product).
+1D flops per vector: 4n^3 + 3n^2 (H), 8n^3 + n^2 (preconditioner);
 2D: 8n^5 + 3n^4 (H)."""
 from __future__ import annotations
 
@@ -18,7 +20,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"float64": 78.6, "float32": 157.3}
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}
 
 
 def flops(ndim, n, nvec, kind):
@@ -36,6 +38,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("names", nargs="+")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--prec", nargs="*", default=None, help="subset of fp64 fp32 bf16x3")
     args = ap.parse_args()
     for name in args.names:
         cfg = config(name)
@@ -44,7 +47,10 @@ def main():
         op = t3.Operator.from_config(cfg)
         print(f"== {name}: ndim={ndim} n={n} N={op.N} block={b} (create {time.time() - t0:.1f} s)",
               flush=True)
-        for dt, pk in [(torch.float64, t3.FP64), (torch.float32, t3.FP32)]:
+        for dt, pk, pname in [(torch.float64, t3.FP64, "fp64"), (torch.float32, t3.FP32, "fp32"),
+                              (torch.float32, t3.BF16X3, "bf16x3")]:
+            if args.prec and pname not in args.prec:
+                continue
             X = torch.randn((b, op.N), dtype=dt, device="cuda")
             Y = torch.empty_like(X)
             kinds = ("H", "P") if ndim == 1 else ("H",)
@@ -52,9 +58,14 @@ def main():
                 tm, tn = [(32, 32), (64, 64), (128, 128), (64, 128)][tile]
                 if tile and (tm > n or tn > n) and ndim == 1:
                     continue
+                if pk == t3.BF16X3 and tile == 0:
+                    continue
                 op.set_tile(tile)
                 for kind in kinds:
-                    f = op.apply_H if kind == "H" else op.apply_prec
+                    g = op.apply_H if kind == "H" else op.apply_prec
+
+                    def f(X, Y, g=g):
+                        return g(X, Y, prec=pk)
                     f(X, Y)
                     torch.cuda.synchronize()
                     e0 = torch.cuda.Event(enable_timing=True)
@@ -66,9 +77,8 @@ def main():
                     torch.cuda.synchronize()
                     ms = e0.elapsed_time(e1) / args.reps
                     tf = flops(ndim, n, b, kind) / ms / 1e9
-                    name_dt = str(dt).replace("torch.", "")
-                    print(f"  {name_dt} tile {tm}x{tn} {kind}: {1e3 * ms:10.1f} us  {tf:7.2f} TFLOP/s"
-                          f"  {100 * tf / PEAK[name_dt]:5.1f}% of peak", flush=True)
+                    print(f"  {pname} tile {tm}x{tn} {kind}: {1e3 * ms:10.1f} us  {tf:7.2f} TFLOP/s"
+                          f"  {100 * tf / PEAK[pname]:5.1f}% of peak", flush=True)
             op.set_tile(-1)
             if ndim == 1:
                 best = op.autotune(pk, b, 5)

@@ -48,9 +48,10 @@ struct tp3b_op_s {
   tp3b::DevOps<double> d64;
   tp3b::DevOps<float> d32;
   int work_vecs = 0;
-  // tile choice: explicit override, else autotuned [prec][0 = H, 1 = prec], else heuristic
+  // tile choice: explicit override, else autotuned [tp3b_prec][0 = H, 1 = prec],
+  // else heuristic
   int tile_override = -1;
-  int tuned[2][2] = {{-1, -1}, {-1, -1}};
+  int tuned[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
 };
 
 namespace tp3b {
@@ -65,13 +66,14 @@ tp3b_status hip_fail(hipError_t e, const char* where);
     if (_e != hipSuccess) return tp3b::hip_fail(_e, #__VA_ARGS__); \
   } while (0)
 
-// Precision-generic internal applies (no argument validation).
+// Precision-generic internal applies (no argument validation).  With
+// bf3 = true (T = float only) the mode products run as BF16x3 split products.
 template <typename T>
 tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, int64_t ldy,
-                         const double* shifts, hipStream_t s);
+                         const double* shifts, hipStream_t s, bool bf3 = false);
 template <typename T>
 tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, int64_t ldy,
-                            hipStream_t s);
+                            hipStream_t s, bool bf3 = false);
 int choose_tile(int M, int Nc, int64_t nbatch, bool fp64);
 
 // Device scratch for the dot reductions (grows on demand, per device).

@@ -10,7 +10,8 @@
 //   4. b correction equations (eq. (13)) with Q~ = [Q_lock, u_1..u_b] solved by
 //      left-preconditioned GMRES with the skew projection
 //      (I - Y H^{-1} Q~^T) P^{-1}, Y = P^{-1} Q~, H = Q~^T Y, a fixed number of
-//      steps, in the inner working precision (FP64 or FP32);
+//      steps, in the inner working precision (FP64, FP32, or FP32 storage with
+//      BF16x3 split mode products);
 //   5. FP64 block orthogonalisation of the corrections against [Q_lock, V] and
 //      FP64 products with A to extend V and A V.
 // Rayleigh-Ritz, residuals, locking and orthogonalisation are always FP64, so
@@ -97,7 +98,7 @@ double now() {
 template <typename TW>
 static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X0, int b0,
                             double* evals, double* Qout, double* Rout, double* resnorm,
-                            tp3b_jdqr_stats* st) {
+                            tp3b_jdqr_stats* st, bool bf3) {
   const double t_start = now();
   hipStream_t s = nullptr;
   const int64_t N = op->N;
@@ -188,7 +189,7 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     const int kd = low ? 1 : 0;
     (low ? stats.n_apply_H_low : stats.n_apply_H_fp64) += nv;
     TP3B_HIP(kt.mark(kd));
-    tp3b_status r = apply_H_impl<TW>(op, nv, X, N, Y, N, sh, s);
+    tp3b_status r = apply_H_impl<TW>(op, nv, X, N, Y, N, sh, s, bf3);
     TP3B_HIP(kt.mark(kd));
     return r;
   };
@@ -386,7 +387,7 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       stats.n_apply_prec += nb;
       const int kd = low ? 3 : 2;
       TP3B_HIP(kt.mark(kd));
-      tp3b_status r = apply_prec_impl<TW>(op, nb, in, N, out, N, s);
+      tp3b_status r = apply_prec_impl<TW>(op, nb, in, N, out, N, s, bf3);
       TP3B_HIP(kt.mark(kd));
       return r;
     };
@@ -577,11 +578,14 @@ tp3b_status tp3b_jdqr_solve(tp3b_op op, const tp3b_jdqr_opts* opts, const double
     return fail(TP3B_EINVAL, "problem too small for nev + m_max + block basis vectors");
   if (o.precond && (op->ndim != 1 || !op->have_prec))
     return fail(TP3B_ENOTSUP, "the kinetic preconditioner is available for 1D operators only");
-  if (o.inner_prec == TP3B_BF16X3) return fail(TP3B_ENOTSUP, "BF16x3 inner solves are not built");
   if (X0 && b0 < 0) return fail(TP3B_EINVAL, "b0 must be >= 0");
   TP3B_HIP(hipSetDevice(op->device));
-  if (o.inner_prec == TP3B_FP32) return jdqr_run<float>(op, o, X0, b0, evals, Q, R, resnorm, stats);
-  return jdqr_run<double>(op, o, X0, b0, evals, Q, R, resnorm, stats);
+  if (o.inner_prec != TP3B_FP64 && o.inner_prec != TP3B_FP32 && o.inner_prec != TP3B_BF16X3)
+    return fail(TP3B_EINVAL, "unknown inner precision");
+  if (o.inner_prec != TP3B_FP64)
+    return jdqr_run<float>(op, o, X0, b0, evals, Q, R, resnorm, stats,
+                           o.inner_prec == TP3B_BF16X3);
+  return jdqr_run<double>(op, o, X0, b0, evals, Q, R, resnorm, stats, false);
 }
 
 }  // extern "C"

@@ -40,6 +40,9 @@ enum TileCfg { TILE_32 = 0, TILE_64 = 1, TILE_128 = 2, TILE_64x128 = 3, NUM_TILE
 
 template <typename T>
 hipError_t launch_modeprod(const ModeProd<T>& a, int tile, hipStream_t s);
+// The same product on FP32 data with BF16x3 split products on the bf16 matrix
+// cores (FP32 accumulation); tile TILE_32 runs as TILE_64.
+hipError_t launch_modeprod_bf3(const ModeProd<float>& a, int tile, hipStream_t s);
 
 // C (p x q, column-major, ldc) = A^T B, A: N x p (lda), B: N x q (ldb), FP64
 // accumulation; `partial` is device scratch of at least dot_scratch_doubles().

@@ -230,6 +230,233 @@ hipError_t launch_modeprod(const ModeProd<T>& a, int tile, hipStream_t s) {
 template hipError_t launch_modeprod<double>(const ModeProd<double>&, int, hipStream_t);
 template hipError_t launch_modeprod<float>(const ModeProd<float>&, int, hipStream_t);
 
+// ------------------------------------------------------ BF16x3 mode product
+// FP32 data, products on the bf16 matrix cores: every operand element f is
+// split as f = hi + lo + d with hi = bf16(f), lo = bf16(f - hi) (round to
+// nearest, 8 significant bits each), so |lo| <= 2^-8 |f| and |d| <= 2^-16 |f|,
+// and a*b is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b with FP32 accumulation
+// in v_mfma_f32_16x16x32_bf16.  The dropped terms (lo_a lo_b and those with d)
+// are at most about 3 * 2^-16 |a b| per product, so the result carries roughly
+// 16 significant bits, between bf16 and FP32.
+// The split happens while a chunk is staged into LDS, so HBM traffic is that of
+// the FP32 kernel.  LDS holds each operand as [row][k] with k contiguous so that
+// a lane's 8 consecutive k values are one 16-byte read: the A operand of lane l
+// is row l % 16, k = 8 (l / 16) + 0..7 and the B operand column l % 16 with the
+// same k; the 16 x 16 FP32 result has the layout of the f32 instruction (row
+// 4 (l / 16) + r in element r, column l % 16).
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split8(const float* f, bf8& hi, bf8& lo) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const __bf16 h = (__bf16)f[u];
+    hi[u] = h;
+    lo[u] = (__bf16)(f[u] - (float)h);
+  }
+}
+
+// Eight consecutive floats p[0..7] of which the first `valid` exist; vector
+// loads when the address is 16-byte aligned and all eight exist.
+__device__ __forceinline__ void load8_row(const float* __restrict__ p, int valid, bool aligned,
+                                          float* out) {
+  if (aligned && valid >= 8) {
+    const float4 u = *(const float4*)p;
+    const float4 v = *(const float4*)(p + 4);
+    out[0] = u.x; out[1] = u.y; out[2] = u.z; out[3] = u.w;
+    out[4] = v.x; out[5] = v.y; out[6] = v.z; out[7] = v.w;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) out[u] = (u < valid) ? p[u] : 0.f;
+  }
+}
+
+template <int TM, int TN, int KC, int ROLE>
+__global__ __launch_bounds__(256) void k_modeprod_bf3(ModeProd<float> a) {
+  constexpr int WM = TM / 2, WN = TN / 2;
+  constexpr int BM = WM / 16, BN = WN / 16;
+  constexpr int KG = KC / 8;                 // k octets per row
+  constexpr int OA = TM * KG / 256;          // A octets per thread
+  constexpr int OB = TN * KG / 256;          // B octets per thread
+  constexpr int LDK = KC + 8;                // padded row (bf16 elements)
+  static_assert(OA >= 1 && OB >= 1 && (TM * KG) % 256 == 0 && (TN * KG) % 256 == 0, "tile");
+  static_assert(KC % 32 == 0, "K chunk is a multiple of the MFMA depth");
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[TM][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[TM][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[TN][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[TN][LDK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  const int tiles_m = (a.M + TM - 1) / TM, tiles_n = (a.Nc + TN - 1) / TN;
+  const int64_t tiles = (int64_t)tiles_m * tiles_n;
+  const int64_t G = tiles * a.nbatch;
+  const int64_t w = xcd_remap(blockIdx.x, G);
+  const int64_t q = w / tiles;
+  const int64_t t = w - q * tiles;
+  const int i0 = (int)(t / tiles_n) * TM, j0 = (int)(t % tiles_n) * TN;
+  const int64_t vec = q / a.per_vec, item = q - vec * a.per_vec;
+  const float* __restrict__ X = a.X + vec * a.ldx + item * a.bstride;
+  float* __restrict__ Y = a.Y + vec * a.ldy + item * a.bstride;
+  const int64_t rs = a.rs;
+  const int M = a.M, Nc = a.Nc;
+  const bool alL = a.L && ((uintptr_t)a.L % 16 == 0) && (M % 4 == 0);
+  const bool alX = ((uintptr_t)X % 16 == 0) && (rs % 4 == 0);
+
+  f4 acc[BM][BN];
+#pragma unroll
+  for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BN; ++bj) acc[bi][bj] = f4{0, 0, 0, 0};
+
+  const int nL = a.L ? (M + KC - 1) / KC : 0;
+  const int nR = a.R ? (Nc + KC - 1) / KC : 0;
+  const int nchunks = nL + nR;
+  float ra[OA][8], rb[OB][8];
+
+  auto load = [&](int c) {
+    const bool left = c < nL;
+    const int k0 = (left ? c : c - nL) * KC;
+    const int K = left ? M : Nc;
+#pragma unroll
+    for (int s = 0; s < OA; ++s) {
+      // A octet: row m, k = k0 + 8g .. +7, k contiguous in memory
+      const int o = tid + s * 256, m = o / KG, g = o % KG;
+      const int gi = i0 + m, gk = k0 + 8 * g;
+      const int valid = (gi < M) ? min(8, K - gk) : 0;
+      if (left)
+        load8_row(a.L + (int64_t)gi * M + gk, valid, alL, ra[s]);
+      else
+        load8_row(X + (int64_t)gi * rs + gk, valid, alX, ra[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < OB; ++s) {
+      // B octet: column n, k = k0 + 8g .. +7, read down a column (coalesced
+      // across the lanes, which hold consecutive n)
+      const int o = tid + s * 256, n = o % TN, g = o / TN;
+      const int gj = j0 + n, gk = k0 + 8 * g;
+      const bool cv = gj < Nc;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int kk = gk + u;
+        const bool v = cv && kk < K;
+        rb[s][u] = v ? (left ? X[(int64_t)kk * rs + gj] : a.R[(int64_t)kk * Nc + gj]) : 0.f;
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int s = 0; s < OA; ++s) {
+      const int o = tid + s * 256, m = o / KG, g = o % KG;
+      bf8 hi, lo;
+      split8(ra[s], hi, lo);
+      *(bf8*)&Ah[m][8 * g] = hi;
+      *(bf8*)&Al[m][8 * g] = lo;
+    }
+#pragma unroll
+    for (int s = 0; s < OB; ++s) {
+      const int o = tid + s * 256, n = o % TN, g = o / TN;
+      bf8 hi, lo;
+      split8(rb[s], hi, lo);
+      *(bf8*)&Bh[n][8 * g] = hi;
+      *(bf8*)&Bl[n][8 * g] = lo;
+    }
+  };
+
+  if (nchunks > 0) {
+    load(0);
+    store();
+  }
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int c = 0; c < nchunks; ++c) {
+    if (c + 1 < nchunks) load(c + 1);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 32) {
+      bf8 ah[BM], al[BM], bh[BN], bl[BN];
+#pragma unroll
+      for (int bi = 0; bi < BM; ++bi) {
+        ah[bi] = *(const bf8*)&Ah[wm + bi * 16 + lr][kk + 8 * lk];
+        al[bi] = *(const bf8*)&Al[wm + bi * 16 + lr][kk + 8 * lk];
+      }
+#pragma unroll
+      for (int bj = 0; bj < BN; ++bj) {
+        bh[bj] = *(const bf8*)&Bh[wn + bj * 16 + lr][kk + 8 * lk];
+        bl[bj] = *(const bf8*)&Bl[wn + bj * 16 + lr][kk + 8 * lk];
+      }
+#pragma unroll
+      for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < BN; ++bj) {
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+    if (c + 1 < nchunks) {
+      store();
+      __syncthreads();
+    }
+  }
+
+  const double shift = a.shifts ? a.shifts[vec] : 0.0;
+  const float* Vp = a.V ? a.V + item * a.bstride : nullptr;
+#pragma unroll
+  for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BN; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + wm + bi * 16 + 4 * lk + r;
+        const int gj = j0 + wn + bj * 16 + lr;
+        if (gi < M && gj < Nc) {
+          const int64_t off = (int64_t)gi * rs + gj;
+          float v = acc[bi][bj][r];
+          if (a.epi == EPI_V) {
+            const float pot = (Vp ? Vp[off] : 0.f) - (float)shift;
+            v += pot * X[off];
+          } else if (a.epi == EPI_DIV) {
+            v = v / (a.lamL[gi] + a.lamR[gj] - (float)a.sigma);
+          }
+          if (a.acc) v += Y[off];
+          Y[off] = v;
+        }
+      }
+}
+
+template <int ROLE>
+static void launch_role_bf3(const ModeProd<float>& a, int tile, hipStream_t s, unsigned g64,
+                            unsigned g128, unsigned g64x128) {
+  switch (tile) {
+    case TILE_128:
+      hipLaunchKernelGGL((k_modeprod_bf3<128, 128, 32, ROLE>), dim3(g128), dim3(256), 0, s, a);
+      break;
+    case TILE_64x128:
+      hipLaunchKernelGGL((k_modeprod_bf3<64, 128, 32, ROLE>), dim3(g64x128), dim3(256), 0, s, a);
+      break;
+    default:  // TILE_32 and TILE_64: the smallest bf16 tile is 64 x 64
+      hipLaunchKernelGGL((k_modeprod_bf3<64, 64, 32, ROLE>), dim3(g64), dim3(256), 0, s, a);
+      break;
+  }
+}
+
+hipError_t launch_modeprod_bf3(const ModeProd<float>& a, int tile, hipStream_t s) {
+  if (a.M <= 0 || a.Nc <= 0 || a.nbatch <= 0) return hipSuccess;
+  if (tile < 0 || tile >= NUM_TILE_CFGS) return hipErrorInvalidValue;
+  auto grid = [&](int TM, int TN) {
+    int64_t tiles = (int64_t)((a.M + TM - 1) / TM) * ((a.Nc + TN - 1) / TN);
+    return (unsigned)(tiles * a.nbatch);
+  };
+  const unsigned g64 = grid(64, 64), g128 = grid(128, 128), g6412 = grid(64, 128);
+  if (a.L && a.R && a.epi == EPI_V)
+    launch_role_bf3<0>(a, tile, s, g64, g128, g6412);
+  else if (a.acc)
+    launch_role_bf3<2>(a, tile, s, g64, g128, g6412);
+  else
+    launch_role_bf3<1>(a, tile, s, g64, g128, g6412);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- block dot
 // Output tile per workgroup: 64 (p) x 32 (q); each of the 4 waves accumulates
 // the full tile over its share of 16-row groups with FP64 MFMA, the waves are

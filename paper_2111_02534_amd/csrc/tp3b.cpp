@@ -161,11 +161,21 @@ static tp3b_status upload_ops(tp3b_op op, tp3b::DevOps<T>& d, const std::vector<
 }
 
 // -------------------------------------------------------------- applies
-static int tile_for(tp3b_op op, bool f64, int kind, int M, int Nc, int64_t nbatch) {
+static int prec_index(bool f64, bool bf3) { return f64 ? TP3B_FP64 : (bf3 ? TP3B_BF16X3 : TP3B_FP32); }
+
+static int tile_for(tp3b_op op, bool f64, bool bf3, int kind, int M, int Nc, int64_t nbatch) {
   if (op->tile_override >= 0) return op->tile_override;
-  const int t = op->tuned[f64 ? 0 : 1][kind];
+  const int t = op->tuned[prec_index(f64, bf3)][kind];
   if (t >= 0) return t;
   return choose_tile(M, Nc, nbatch, f64);
+}
+
+// One mode-product launch in the requested arithmetic.
+static hipError_t modeprod(const ModeProd<double>& a, int tile, hipStream_t s, bool) {
+  return launch_modeprod(a, tile, s);
+}
+static hipError_t modeprod(const ModeProd<float>& a, int tile, hipStream_t s, bool bf3) {
+  return bf3 ? launch_modeprod_bf3(a, tile, s) : launch_modeprod(a, tile, s);
 }
 
 template <typename T>
@@ -177,7 +187,7 @@ tp3b::DevOps<float>& ops_for<float>(tp3b_op op) { return op->d32; }
 
 template <typename T>
 tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, int64_t ldy,
-                         const double* shifts, hipStream_t s) {
+                         const double* shifts, hipStream_t s, bool bf3) {
   tp3b::DevOps<T>& d = ops_for<T>(op);
   const bool f64 = sizeof(T) == 8;
   if (op->ndim == 1) {
@@ -199,7 +209,7 @@ tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, in
     a.shifts = shifts;
     a.epi = EPI_V;
     a.acc = 0;
-    TP3B_HIP(launch_modeprod(a, tile_for(op, f64, 0, a.M, a.Nc, nvec), s));
+    TP3B_HIP(modeprod(a, tile_for(op, f64, bf3, 0, a.M, a.Nc, nvec), s, bf3));
     return TP3B_OK;
   }
   // 2D (eq. (11)): pass A applies the two y modes and the potential on every
@@ -225,7 +235,7 @@ tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, in
     a.epi = EPI_V;
     a.acc = 0;
     int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, a.nbatch, f64);
-    TP3B_HIP(launch_modeprod(a, tile, s));
+    TP3B_HIP(modeprod(a, tile, s, bf3));
   }
   {
     ModeProd<T> a{};
@@ -244,7 +254,7 @@ tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, in
     a.epi = EPI_NONE;
     a.acc = 1;
     int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, a.nbatch, f64);
-    TP3B_HIP(launch_modeprod(a, tile, s));
+    TP3B_HIP(modeprod(a, tile, s, bf3));
   }
   {
     ModeProd<T> a{};
@@ -263,14 +273,14 @@ tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, in
     a.epi = EPI_NONE;
     a.acc = 1;
     int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, a.nbatch, f64);
-    TP3B_HIP(launch_modeprod(a, tile, s));
+    TP3B_HIP(modeprod(a, tile, s, bf3));
   }
   return TP3B_OK;
 }
 
 template <typename T>
 tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, int64_t ldy,
-                            hipStream_t s) {
+                            hipStream_t s, bool bf3) {
   tp3b::DevOps<T>& d = ops_for<T>(op);
   const bool f64 = sizeof(T) == 8;
   const int nx = op->n[0], ny = op->n[1];
@@ -288,35 +298,35 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
     a.per_vec = 1;
     a.nbatch = nv;
     a.sigma = op->sigma;
-    const int tile = tile_for(op, f64, 1, nx, ny, nv);
+    const int tile = tile_for(op, f64, bf3, 1, nx, ny, nv);
     // 1: W = Sx^{-1} B
     a.X = Xc; a.ldx = ldx; a.Y = d.work; a.ldy = N;
     a.L = d.Sxi; a.R = nullptr; a.epi = EPI_NONE;
-    TP3B_HIP(launch_modeprod(a, tile, s));
+    TP3B_HIP(modeprod(a, tile, s, bf3));
     // 2: Y = (W Sy^{-T}) / (lx_i + ly_j - sigma)
     a.X = d.work; a.ldx = N; a.Y = Yc; a.ldy = ldy;
     a.L = nullptr; a.R = d.SyiT; a.epi = EPI_DIV; a.lamL = d.lx; a.lamR = d.ly;
-    TP3B_HIP(launch_modeprod(a, tile, s));
+    TP3B_HIP(modeprod(a, tile, s, bf3));
     // 3: W = Sx Y
     a.X = Yc; a.ldx = ldy; a.Y = d.work; a.ldy = N;
     a.L = d.Sx; a.R = nullptr; a.epi = EPI_NONE;
-    TP3B_HIP(launch_modeprod(a, tile, s));
+    TP3B_HIP(modeprod(a, tile, s, bf3));
     // 4: Y = W Sy^T
     a.X = d.work; a.ldx = N; a.Y = Yc; a.ldy = ldy;
     a.L = nullptr; a.R = d.SyT; a.epi = EPI_NONE;
-    TP3B_HIP(launch_modeprod(a, tile, s));
+    TP3B_HIP(modeprod(a, tile, s, bf3));
   }
   return TP3B_OK;
 }
 
 template tp3b_status apply_H_impl<double>(tp3b_op, int, const double*, int64_t, double*, int64_t,
-                                          const double*, hipStream_t);
+                                          const double*, hipStream_t, bool);
 template tp3b_status apply_H_impl<float>(tp3b_op, int, const float*, int64_t, float*, int64_t,
-                                         const double*, hipStream_t);
+                                         const double*, hipStream_t, bool);
 template tp3b_status apply_prec_impl<double>(tp3b_op, int, const double*, int64_t, double*,
-                                             int64_t, hipStream_t);
+                                             int64_t, hipStream_t, bool);
 template tp3b_status apply_prec_impl<float>(tp3b_op, int, const float*, int64_t, float*, int64_t,
-                                            hipStream_t);
+                                            hipStream_t, bool);
 
 // ------------------------------------------------------------ block orth
 // A column keeping less than this fraction of its norm after projection counts
@@ -426,8 +436,8 @@ tp3b_status block_orth_impl(int64_t N, int nq, const double* Q, int64_t ldq, int
 }
 
 template <typename T>
-static tp3b_status autotune_impl(tp3b_op op, int nvec, int reps, double* best_ms) {
-  const int pi = sizeof(T) == 8 ? 0 : 1;
+static tp3b_status autotune_impl(tp3b_op op, int nvec, int reps, double* best_ms, bool bf3) {
+  const int pi = prec_index(sizeof(T) == 8, bf3);
   T *X = nullptr, *Y = nullptr;
   hipEvent_t e0, e1;
   TP3B_HIP(hipMalloc((void**)&X, sizeof(T) * op->N * nvec));
@@ -450,10 +460,11 @@ static tp3b_status autotune_impl(tp3b_op op, int nvec, int reps, double* best_ms
       const int tm = (tile == TILE_32) ? 32 : (tile == TILE_128 ? 128 : 64);
       const int tn = (tile == TILE_32) ? 32 : ((tile == TILE_64) ? 64 : 128);
       if (tile != TILE_32 && (tm > op->n[op->ndim == 1 ? 0 : 2] || tn > op->n[op->ndim == 1 ? 1 : 3])) continue;
+      if (bf3 && tile == TILE_32) continue;  // the smallest BF16x3 tile is 64 x 64
       op->tile_override = tile;
       auto run = [&]() -> tp3b_status {
-        return kind == 0 ? apply_H_impl<T>(op, nvec, X, op->N, Y, op->N, nullptr, nullptr)
-                         : apply_prec_impl<T>(op, nvec, X, op->N, Y, op->N, nullptr);
+        return kind == 0 ? apply_H_impl<T>(op, nvec, X, op->N, Y, op->N, nullptr, nullptr, bf3)
+                         : apply_prec_impl<T>(op, nvec, X, op->N, Y, op->N, nullptr, bf3);
       };
       st = run();  // warm-up
       if (st != TP3B_OK) break;
@@ -653,7 +664,6 @@ static tp3b_status check_apply(tp3b_op op, int32_t prec, int32_t nvec, const voi
   if (!op) return fail(TP3B_EINVAL, "null operator");
   if (prec != TP3B_FP64 && prec != TP3B_FP32 && prec != TP3B_BF16X3)
     return fail(TP3B_EINVAL, "unknown precision");
-  if (prec == TP3B_BF16X3) return fail(TP3B_ENOTSUP, "BF16x3 mode products are not built");
   if (nvec < 0) return fail(TP3B_EINVAL, "nvec must be >= 0");
   if (nvec == 0) return TP3B_OK;
   if (!X || !Y) return fail(TP3B_EINVAL, "null X or Y");
@@ -676,7 +686,8 @@ tp3b_status tp3b_apply_H_shifted(tp3b_op op, int32_t prec, int32_t nvec, const v
   hipStream_t s = (hipStream_t)stream;
   if (prec == TP3B_FP64)
     return apply_H_impl<double>(op, nvec, (const double*)X, ldx, (double*)Y, ldy, shifts, s);
-  return apply_H_impl<float>(op, nvec, (const float*)X, ldx, (float*)Y, ldy, shifts, s);
+  return apply_H_impl<float>(op, nvec, (const float*)X, ldx, (float*)Y, ldy, shifts, s,
+                             prec == TP3B_BF16X3);
 }
 
 tp3b_status tp3b_apply_H(tp3b_op op, int32_t prec, int32_t nvec, const void* X, int64_t ldx,
@@ -694,7 +705,8 @@ tp3b_status tp3b_apply_prec(tp3b_op op, int32_t prec, int32_t nvec, const void* 
   hipStream_t s = (hipStream_t)stream;
   if (prec == TP3B_FP64)
     return apply_prec_impl<double>(op, nvec, (const double*)X, ldx, (double*)Y, ldy, s);
-  return apply_prec_impl<float>(op, nvec, (const float*)X, ldx, (float*)Y, ldy, s);
+  return apply_prec_impl<float>(op, nvec, (const float*)X, ldx, (float*)Y, ldy, s,
+                                prec == TP3B_BF16X3);
 }
 
 tp3b_status tp3b_block_orth(int64_t N, int32_t nq, const double* Q, int64_t ldq, int32_t nx,
@@ -722,12 +734,12 @@ tp3b_status tp3b_set_tile(tp3b_op op, int32_t tile) {
 tp3b_status tp3b_autotune(tp3b_op op, int32_t prec, int32_t nvec, int32_t reps, double* best_ms) {
   if (!op) return fail(TP3B_EINVAL, "null operator");
   if (nvec < 1 || reps < 1) return fail(TP3B_EINVAL, "nvec and reps must be >= 1");
-  if (prec == TP3B_BF16X3) return fail(TP3B_ENOTSUP, "BF16x3 mode products are not built");
-  if (prec != TP3B_FP64 && prec != TP3B_FP32) return fail(TP3B_EINVAL, "unknown precision");
+  if (prec != TP3B_FP64 && prec != TP3B_FP32 && prec != TP3B_BF16X3)
+    return fail(TP3B_EINVAL, "unknown precision");
   TP3B_HIP(hipSetDevice(op->device));
   if (best_ms) best_ms[0] = best_ms[1] = NAN;
-  return prec == TP3B_FP64 ? autotune_impl<double>(op, nvec, reps, best_ms)
-                           : autotune_impl<float>(op, nvec, reps, best_ms);
+  return prec == TP3B_FP64 ? autotune_impl<double>(op, nvec, reps, best_ms, false)
+                           : autotune_impl<float>(op, nvec, reps, best_ms, prec == TP3B_BF16X3);
 }
 
 tp3b_status tp3b_host_schur(int32_t n, double* A, double* Z, double* wr, double* wi) {
