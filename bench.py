@@ -12,8 +12,9 @@ block is generated on the device.
 Printed: one JSON line with the solve time (value), the Hamiltonian-apply
 throughput of the dominant kernel measured with HIP events inside the timed
 solves against the FP64 MFMA peak (roofline), the eigenvalue error against the
-CPU oracle's stored values, the same solve with FP32 inner GMRES ("mixed"), and
-the CPU oracle timed on this host (cpu_baseline).
+CPU oracle's stored values, the same solve with FP32 inner GMRES ("mixed"), the
+256-instance batched workload (batched_c4), and the CPU oracle timed on this
+host (cpu_baseline).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
 """
@@ -82,6 +83,56 @@ def cpu_baseline(cfg, name, sample_iters, full_iters):
                        f"NumPy/SciPy FP64, {threads} BLAS threads")}
 
 
+def batched_leg(reps, n_seq):
+    """The 256-instance workload c4: one batched JDQR solve (grouped persistent
+    launches, GMRES iteration replayed as a HIP graph) per repetition, for each
+    inner precision; eigenvalues against the oracle's stored values; and the
+    first `n_seq` instances solved one by one with the single-instance solver
+    (FP32 inner) for comparison."""
+    import numpy as np
+    import torch
+
+    import paper_2111_02534_amd as t3
+    from workloads import c4_instances
+    inst = c4_instances()
+    path = os.path.join(ROOT, "tests", "golden", "c4_evals.txt")
+    gold = np.loadtxt(path)[:, 5:9] if os.path.exists(path) else None
+    t0 = time.perf_counter()
+    ops = [t3.Operator.from_config(c) for c in inst]
+    t_create = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for pk in (t3.FP64, t3.FP32, t3.BF16X3):
+        t3.autotune_batched(ops, pk, nvec=4, reps=2)
+    t_tune = time.perf_counter() - t0
+    res = {"instances": len(ops), "nev": 4, "block": 4, "create_s": t_create, "autotune_s": t_tune}
+    for name, pk in (("fp64", t3.FP64), ("fp32", t3.FP32), ("bf16x3", t3.BF16X3)):
+        t3.jdqr_batched(ops, 4, 4, inner_prec=pk, seed=1000)  # warm-up (graph capture, caches)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            r = t3.jdqr_batched(ops, 4, 4, inner_prec=pk, seed=1000)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / reps
+        err = float(np.max(np.abs(r.evals - gold) / np.abs(gold))) if gold is not None else None
+        res[name] = {"s_per_batch": dt, "instances_per_s": len(ops) / dt,
+                     "outer_iters_max": int(r.n_outer.max()),
+                     "outer_iters_mean": float(r.n_outer.mean()),
+                     "eig_max_rel_err_vs_oracle": err}
+    if n_seq > 0:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for op in ops[:n_seq]:
+            op.jdqr(4, 4, inner_prec=t3.FP32, seed=0, want_Q=False)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t1) / n_seq
+        res["sequential_fp32"] = {"instances": n_seq, "s_per_instance": per,
+                                  "projected_s_for_batch": per * len(ops),
+                                  "batched_speedup": per * len(ops) / res["fp32"]["s_per_batch"]}
+    for op in ops:
+        op.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +142,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=3)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-reps", type=int, default=3)
+    ap.add_argument("--batched-seq", type=int, default=32,
+                    help="instances of the batch solved one by one for comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
@@ -181,6 +236,8 @@ def main():
         out["mixed_vs_fp64"] = {"fp64_s": s_per_solve, "mixed_s": m_s, "speedup": s_per_solve / m_s,
                                 "mixed_outer_iters": mres[-1].stats["n_outer"],
                                 "mixed_eig_max_rel_err_vs_oracle": m_err}
+    if not args.no_batched:
+        out["batched_c4"] = batched_leg(args.batched_reps, args.batched_seq)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.config, args.cpu_sample_iters, ref_iters)
     print(json.dumps(out), flush=True)

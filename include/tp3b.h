@@ -152,6 +152,9 @@ typedef struct {
   int32_t check_finite; /* reject NaN/Inf in X0 */
   int32_t verbose;      /* print one line per outer iteration to stderr */
   int32_t profile;      /* time the mode-product launches with HIP events (stats) */
+  int32_t graph;        /* batched solver: capture the GMRES inner iteration as a
+                           HIP graph once per solve and replay it every outer
+                           iteration (0 = launch eagerly) */
 } tp3b_jdqr_opts;
 
 typedef struct {
@@ -179,6 +182,54 @@ tp3b_status tp3b_jdqr_default_opts(tp3b_jdqr_opts* opts);
 tp3b_status tp3b_jdqr_solve(tp3b_op op, const tp3b_jdqr_opts* opts, const double* X0, int32_t b0,
                             double* evals, double* Q, double* R, double* resnorm,
                             tp3b_jdqr_stats* stats);
+
+/* ---- Batched forms: many independent 1D operators (instances) at once.
+ * Every step of the method runs as one grouped, persistent launch over all
+ * instances (one launch per tile shape in use): a device job table holds one
+ * job per instance, and each workgroup loops over its share of the tiles.
+ * Instances may differ in grid size, coefficients and potential.  All ops must
+ * be 1D and live on the current device; `count` >= 1. */
+
+/* Y_i = H_i X_i (or (H_i - s) X_i with shifts[i] a device array of nvec
+ * doubles, if shifts is not NULL) for i < count.  X[i], Y[i]: device blocks of
+ * nvec vectors of op i (column-major N_i x nvec, leading dimensions ldx[i],
+ * ldy[i] >= N_i); X, Y, ldx, ldy (and shifts) are host arrays of count entries.
+ * Precision and storage as for tp3b_apply_H.  Stream-ordered; the job tables
+ * are staged through the library's pinned buffer, so the call waits for the
+ * previous batched call on the same thread to have consumed its tables. */
+tp3b_status tp3b_apply_H_batched(const tp3b_op* ops, int32_t count, int32_t prec, int32_t nvec,
+                                 const void* const* X, const int64_t* ldx, void* const* Y,
+                                 const int64_t* ldy, const double* const* shifts, void* stream);
+
+/* Y_i = (K_i - sigma_i I)^{-1} X_i for i < count (tp3b_apply_prec per
+ * instance, four grouped mode-product launches).  nvec <= 64. */
+tp3b_status tp3b_apply_prec_batched(const tp3b_op* ops, int32_t count, int32_t prec, int32_t nvec,
+                                    const void* const* X, const int64_t* ldx, void* const* Y,
+                                    const int64_t* ldy, void* stream);
+
+/* Autotuner for a batch: instances are grouped by grid size (n_x, n_y); for
+ * every group and tile shape the grouped Hamiltonian and preconditioner applies
+ * of that group are timed (`reps` repetitions, HIP events), and the fastest
+ * shape is stored in every operator of the group (as tp3b_autotune does for
+ * one operator).  Synchronous; allocates and frees scratch blocks. */
+tp3b_status tp3b_autotune_batched(const tp3b_op* ops, int32_t count, int32_t prec, int32_t nvec,
+                                  int32_t reps);
+
+/* Block JDQR on `count` independent instances at once (tp3b_jdqr_solve per
+ * instance, same options for all).  The instances advance together: each
+ * outer iteration performs the Rayleigh-Ritz step, the residuals, locking and
+ * restart of every unconverged instance, then the correction equations of all
+ * instances that did not lock, every device step as one grouped launch.  Seeds:
+ * instance i starts from the counter-based block of seed opts->seed + i.
+ * evals: host count x nev (row i = instance i, ascending); resnorm: host
+ * count x nev or NULL; n_conv, n_outer: host arrays of count or NULL; Q: NULL
+ * or a host array of count device pointers (each NULL or N_i x nev) receiving
+ * the Schur vectors; stats: totals over the batch (n_outer = the largest).
+ * Synchronous.  ENOCONV if any instance stopped short of nev pairs (its
+ * converged prefix is returned, the rest of its row is NaN). */
+tp3b_status tp3b_jdqr_solve_batched(const tp3b_op* ops, int32_t count, const tp3b_jdqr_opts* opts,
+                                    double* evals, double* resnorm, int32_t* n_conv,
+                                    int32_t* n_outer, double* const* Q, tp3b_jdqr_stats* stats);
 
 /* Mode-product tile shape used by this operator's applies: 0 = 32x32,
  * 1 = 64x64, 2 = 128x128, 3 = 64x128 output tile per 256-thread workgroup;

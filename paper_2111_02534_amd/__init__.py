@@ -47,7 +47,8 @@ class JdqrOpts(ctypes.Structure):
                 ("inner_prec", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("switch_tol", ctypes.c_double), ("target", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("check_finite", ctypes.c_int32),
-                ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
 
 
 class JdqrStats(ctypes.Structure):
@@ -70,7 +71,8 @@ class JdqrStats(ctypes.Structure):
 EXPORTS = ["tp3b_create", "tp3b_destroy", "tp3b_op_info", "tp3b_get_D2", "tp3b_get_V",
            "tp3b_apply_H", "tp3b_apply_H_shifted", "tp3b_apply_prec", "tp3b_block_orth",
            "tp3b_jdqr_default_opts", "tp3b_jdqr_solve", "tp3b_host_schur", "tp3b_last_error",
-           "tp3b_set_tile", "tp3b_autotune"]
+           "tp3b_set_tile", "tp3b_autotune", "tp3b_apply_H_batched", "tp3b_apply_prec_batched",
+           "tp3b_autotune_batched", "tp3b_jdqr_solve_batched"]
 
 _lib = None
 
@@ -99,6 +101,15 @@ def lib():
         L.tp3b_host_schur.argtypes = [i32, dp, dp, dp, dp]
         L.tp3b_set_tile.argtypes = [vp, i32]
         L.tp3b_autotune.argtypes = [vp, i32, i32, i32, dp]
+        pp = ctypes.POINTER(vp)
+        i64p = ctypes.POINTER(i64)
+        L.tp3b_apply_H_batched.argtypes = [pp, i32, i32, i32, pp, i64p, pp, i64p, pp, vp]
+        L.tp3b_apply_prec_batched.argtypes = [pp, i32, i32, i32, pp, i64p, pp, i64p, vp]
+        L.tp3b_autotune_batched.argtypes = [pp, i32, i32, i32, i32]
+        L.tp3b_jdqr_solve_batched.argtypes = [pp, i32, ctypes.POINTER(JdqrOpts), dp, dp,
+                                              ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32), pp,
+                                              ctypes.POINTER(JdqrStats)]
         L.tp3b_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
             if name != "tp3b_last_error":
@@ -326,6 +337,109 @@ def block_orth(Q, X, seed=0, want_factors=True, stream=None):
     Cm = C.T[:nq] if (want_factors and nq) else None
     Rm = R.T if want_factors else None
     return Cm, Rm, rank.value
+
+
+def _ptr_array(items):
+    arr = (ctypes.c_void_p * len(items))()
+    for i, t in enumerate(items):
+        arr[i] = None if t is None else (t if isinstance(t, int) else t.data_ptr())
+    return arr
+
+
+def _batch_blocks(ops, Xs, Ys):
+    if not (len(ops) == len(Xs) == len(Ys)) or not ops:
+        raise ValueError("one X and one Y block per operator")
+    nvec = Xs[0].shape[0]
+    ldx = (ctypes.c_int64 * len(ops))()
+    ldy = (ctypes.c_int64 * len(ops))()
+    for i, (op, X, Y) in enumerate(zip(ops, Xs, Ys)):
+        if X.shape[0] != nvec:
+            raise ValueError("every block has the same number of vectors")
+        _, ldx[i], ldy[i] = op._blk(X, Y)
+    return nvec, ldx, ldy
+
+
+def _batch_prec(Xs, prec):
+    p = Operator._prec_of(Xs[0])
+    if any(Operator._prec_of(X) != p for X in Xs):
+        raise TypeError("all blocks of a batched call have one dtype")
+    if prec is None:
+        return p
+    if (prec == FP64) != (p == FP64):
+        raise TypeError("FP64 applies take float64 blocks, FP32/BF16X3 applies float32 blocks")
+    return int(prec)
+
+
+def apply_H_batched(ops, Xs, Ys, prec=None, shifts=None, stream=None):
+    """Y_i = H_i X_i for every operator of a batch in grouped launches
+    (tp3b_apply_H_batched).  Xs, Ys: lists of (nvec, N_i) tensors."""
+    nvec, ldx, ldy = _batch_blocks(ops, Xs, Ys)
+    p = _batch_prec(Xs, prec)
+    h = _ptr_array([op.handle.value for op in ops])
+    sh = _ptr_array(shifts) if shifts is not None else None
+    _check(lib().tp3b_apply_H_batched(h, len(ops), p, nvec, _ptr_array(Xs), ldx, _ptr_array(Ys),
+                                      ldy, sh, _stream(stream)))
+    return Ys
+
+
+def apply_prec_batched(ops, Xs, Ys, prec=None, stream=None):
+    """Y_i = (K_i - sigma_i)^{-1} X_i for every operator of a batch."""
+    nvec, ldx, ldy = _batch_blocks(ops, Xs, Ys)
+    p = _batch_prec(Xs, prec)
+    h = _ptr_array([op.handle.value for op in ops])
+    _check(lib().tp3b_apply_prec_batched(h, len(ops), p, nvec, _ptr_array(Xs), ldx,
+                                         _ptr_array(Ys), ldy, _stream(stream)))
+    return Ys
+
+
+def autotune_batched(ops, prec=FP64, nvec=1, reps=3):
+    """Choose the mode-product tile shape per grid-size group of a batch."""
+    h = _ptr_array([op.handle.value for op in ops])
+    _check(lib().tp3b_autotune_batched(h, len(ops), int(prec), int(nvec), int(reps)))
+
+
+@dataclass
+class BatchedResult:
+    evals: object      # (count, nev)
+    resnorm: object    # (count, nev)
+    n_conv: object     # (count,)
+    n_outer: object    # (count,)
+    Q: object          # list of (nev, N_i) tensors or None
+    stats: dict
+    status: int
+
+
+def jdqr_batched(ops, nev, block, *, inner_prec=FP64, precond=True, tol=1e-12, gmres_steps=10,
+                 m_min=0, m_max=0, max_outer=1000, seed=0, switch_tol=1e-2, target=None,
+                 graph=True, want_Q=False, verbose=False):
+    """Block JDQR on every operator of a batch at once (tp3b_jdqr_solve_batched)."""
+    import numpy as np
+    import torch
+    o = JdqrOpts()
+    _check(lib().tp3b_jdqr_default_opts(ctypes.byref(o)))
+    o.nev, o.block, o.m_min, o.m_max = nev, block, m_min, m_max
+    o.gmres_steps, o.max_outer, o.precond = gmres_steps, max_outer, int(bool(precond))
+    o.inner_prec, o.tol, o.switch_tol = inner_prec, tol, switch_tol
+    o.target = float("nan") if target is None else float(target)
+    o.seed, o.verbose, o.graph = seed, int(verbose), int(bool(graph))
+    n = len(ops)
+    evals = np.empty((n, nev))
+    res = np.empty((n, nev))
+    nconv = (ctypes.c_int32 * n)()
+    nouter = (ctypes.c_int32 * n)()
+    Q = [torch.empty((nev, op.N), dtype=torch.float64, device="cuda") for op in ops] if want_Q else None
+    qarr = _ptr_array(Q) if want_Q else None
+    st = JdqrStats()
+    h = _ptr_array([op.handle.value for op in ops])
+    code = lib().tp3b_jdqr_solve_batched(h, n, ctypes.byref(o), _dbl_ptr(evals), _dbl_ptr(res),
+                                         nconv, nouter, qarr, ctypes.byref(st))
+    result = BatchedResult(evals, res, np.array(nconv[:]), np.array(nouter[:]), Q, st.as_dict(),
+                           code)
+    if code != TP3B_OK:
+        err = Tp3bError(code, lib().tp3b_last_error().decode())
+        err.result = result
+        raise err
+    return result
 
 
 def host_schur(A):

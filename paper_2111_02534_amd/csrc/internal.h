@@ -75,6 +75,10 @@ template <typename T>
 tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, int64_t ldy,
                             hipStream_t s, bool bf3 = false);
 int choose_tile(int M, int Nc, int64_t nbatch, bool fp64);
+// Tile shape of an operator's 1D applies: kind 0 = Hamiltonian, 1 = preconditioner.
+int op_tile(tp3b_op op, bool f64, bool bf3, int kind, int64_t nbatch);
+template <typename T>
+DevOps<T>& dev_ops(tp3b_op op);
 
 // Device scratch for the dot reductions (grows on demand, per device).
 double* dot_scratch(int64_t doubles);

@@ -170,6 +170,10 @@ static int tile_for(tp3b_op op, bool f64, bool bf3, int kind, int M, int Nc, int
   return choose_tile(M, Nc, nbatch, f64);
 }
 
+int op_tile(tp3b_op op, bool f64, bool bf3, int kind, int64_t nbatch) {
+  return tile_for(op, f64, bf3, kind, op->n[0], op->n[1], nbatch);
+}
+
 // One mode-product launch in the requested arithmetic.
 static hipError_t modeprod(const ModeProd<double>& a, int tile, hipStream_t s, bool) {
   return launch_modeprod(a, tile, s);
@@ -178,12 +182,12 @@ static hipError_t modeprod(const ModeProd<float>& a, int tile, hipStream_t s, bo
   return bf3 ? launch_modeprod_bf3(a, tile, s) : launch_modeprod(a, tile, s);
 }
 
+template <>
+tp3b::DevOps<double>& dev_ops<double>(tp3b_op op) { return op->d64; }
+template <>
+tp3b::DevOps<float>& dev_ops<float>(tp3b_op op) { return op->d32; }
 template <typename T>
-static tp3b::DevOps<T>& ops_for(tp3b_op op);
-template <>
-tp3b::DevOps<double>& ops_for<double>(tp3b_op op) { return op->d64; }
-template <>
-tp3b::DevOps<float>& ops_for<float>(tp3b_op op) { return op->d32; }
+static tp3b::DevOps<T>& ops_for(tp3b_op op) { return dev_ops<T>(op); }
 
 template <typename T>
 tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, int64_t ldy,
