@@ -74,3 +74,70 @@ class KineticSylvester:
         Z = self.solve_matrix(B)
         out = Z.reshape(X.shape[1], -1).T.copy()
         return out[:, 0] if squeeze else out
+
+
+class KineticKronecker2D:
+    """Kinetic preconditioner for the 2D (four-mode) operator: Z with
+    (K - sigma I) Z = B, K = sum over the modes x1, x2, y1, y2 of -c D2_k acting
+    on its own index (the kinetic part of eq. (8)).
+
+    The paper builds this preconditioner for 1D only (Sec. 4.2); here its
+    Bartels-Stewart approach is carried to four modes.  With real Schur forms
+    A_k = U_k T_k U_k^T (T_k upper triangular: the spectra are real), the
+    transformed right-hand side F = B x_1 U_1^T x_2 U_2^T x_3 U_3^T x_4 U_4^T
+    satisfies the triangular system (T_1 + T_2 + T_3 + T_4 - sigma) G = F (each
+    T_k on its own mode), solved by back substitution over the x1 index, then
+    over the x2 index, each remaining (y1, y2) problem being a triangular
+    Sylvester equation (T_3 - s I) G + G T_4^T = R; finally Z = G x_k U_k.
+    """
+
+    def __init__(self, D2, cx, cy, sigma):
+        self.n = tuple(d.shape[0] for d in D2)
+        coef = (cx, cx, cy, cy)
+        self.A = [-c * d for c, d in zip(coef, D2)]
+        self.sigma = float(sigma)
+        self.T, self.U = [], []
+        for A in self.A:
+            T, U = scipy.linalg.schur(A, output="real")
+            if np.any(np.abs(np.diag(T, -1)) > 0.0):
+                raise NotImplementedError("a mode factor has complex eigenvalues")
+            self.T.append(T)
+            self.U.append(U)
+
+    @staticmethod
+    def _modes(W, M):
+        """W x_k M_k for k = 0..3 (M_k acting on index k)."""
+        W = np.einsum("ia,ajkl->ijkl", M[0], W)
+        W = np.einsum("ja,iakl->ijkl", M[1], W)
+        W = np.einsum("ka,ijal->ijkl", M[2], W)
+        return np.einsum("la,ijka->ijkl", M[3], W)
+
+    def _solve_triangular(self, F):
+        T1, T2, T3, T4 = self.T
+        n1, n2 = self.n[0], self.n[1]
+        G = np.zeros_like(F)
+        for i1 in range(n1 - 1, -1, -1):
+            R1 = F[i1] - np.tensordot(T1[i1, i1 + 1:], G[i1 + 1:], axes=(0, 0))
+            H = np.zeros_like(R1)
+            for i2 in range(n2 - 1, -1, -1):
+                R2 = R1[i2] - np.tensordot(T2[i2, i2 + 1:], H[i2 + 1:], axes=(0, 0))
+                s = self.sigma - T1[i1, i1] - T2[i2, i2]
+                H[i2] = scipy.linalg.solve_sylvester(T3 - s * np.eye(T3.shape[0]), T4.T, R2)
+            G[i1] = H
+        return G
+
+    def solve_tensor(self, B):
+        F = self._modes(B, [U.T for U in self.U])
+        G = self._solve_triangular(F)
+        return self._modes(G, self.U)
+
+    def apply(self, X):
+        """P^{-1} X for a block X of shape (N, b) (or a single vector)."""
+        X = np.asarray(X, dtype=np.float64)
+        squeeze = X.ndim == 1
+        if squeeze:
+            X = X[:, None]
+        out = np.empty_like(X)
+        for v in range(X.shape[1]):
+            out[:, v] = self.solve_tensor(np.ascontiguousarray(X[:, v]).reshape(self.n)).ravel()
+        return out[:, 0] if squeeze else out

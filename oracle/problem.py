@@ -51,10 +51,10 @@ class Problem:
                                      self.v0, self.width)
 
     def preconditioner(self, sigma=None):
-        if self.ndim != 1:
-            raise NotImplementedError("the kinetic Sylvester preconditioner is 1D")
         if sigma is None:
             sigma = self.two_body_shift()
+        if self.ndim != 1:
+            return precond.KineticKronecker2D(self.D2, self.cx, self.cy, sigma)
         return precond.KineticSylvester(self.D2[0], self.D2[1], self.cx, self.cy, sigma)
 
 
