@@ -93,7 +93,7 @@ def batched_leg(reps, n_seq):
     import torch
 
     import paper_2111_02534_amd as t3
-    from workloads import c4_instances
+    from workloads import C4_TOL, c4_instances
     inst = c4_instances()
     path = os.path.join(ROOT, "tests", "golden", "c4_evals.txt")
     gold = np.loadtxt(path)[:, 5:9] if os.path.exists(path) else None
@@ -106,11 +106,11 @@ def batched_leg(reps, n_seq):
     t_tune = time.perf_counter() - t0
     res = {"instances": len(ops), "nev": 4, "block": 4, "create_s": t_create, "autotune_s": t_tune}
     for name, pk in (("fp64", t3.FP64), ("fp32", t3.FP32), ("bf16x3", t3.BF16X3)):
-        t3.jdqr_batched(ops, 4, 4, inner_prec=pk, seed=1000)  # warm-up (graph capture, caches)
+        t3.jdqr_batched(ops, 4, 4, inner_prec=pk, seed=1000, tol=C4_TOL)  # warm-up
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(reps):
-            r = t3.jdqr_batched(ops, 4, 4, inner_prec=pk, seed=1000)
+            r = t3.jdqr_batched(ops, 4, 4, inner_prec=pk, seed=1000, tol=C4_TOL)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t1) / reps
         err = float(np.max(np.abs(r.evals - gold) / np.abs(gold))) if gold is not None else None
@@ -122,7 +122,7 @@ def batched_leg(reps, n_seq):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for op in ops[:n_seq]:
-            op.jdqr(4, 4, inner_prec=t3.FP32, seed=0, want_Q=False)
+            op.jdqr(4, 4, inner_prec=t3.FP32, seed=0, want_Q=False, tol=C4_TOL)
         torch.cuda.synchronize()
         per = (time.perf_counter() - t1) / n_seq
         res["sequential_fp32"] = {"instances": n_seq, "s_per_instance": per,

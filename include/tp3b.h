@@ -88,8 +88,8 @@ typedef struct {
 } tp3b_problem_desc;
 
 /* Creates an operator: builds the second-derivative matrices, the potential
- * table, the preconditioner's eigen-factors (1D only) and uploads them to the
- * current HIP device.  Synchronous.  *out receives the handle. */
+ * table, the preconditioner's eigen-factors of every mode and uploads them to
+ * the current HIP device.  Synchronous.  *out receives the handle. */
 tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* out);
 tp3b_status tp3b_destroy(tp3b_op op);
 
@@ -111,12 +111,16 @@ tp3b_status tp3b_apply_H_shifted(tp3b_op op, int32_t prec, int32_t nvec, const v
                                  int64_t ldx, void* Y, int64_t ldy, const double* shifts,
                                  void* stream);
 
-/* Y = (K - sigma I)^{-1} X with K the kinetic Kronecker sum (eq. (14)): per
- * vector the Sylvester equation (K_x - s_x I) Z + Z (K_y - s_y I)^T = B,
- * s_x + s_y = sigma, split in proportion to c_x and c_y.  Solved in the
+/* Y = (K - sigma I)^{-1} X with K the kinetic Kronecker sum (eq. (14)).  1D:
+ * per vector the Sylvester equation (K_x - s_x I) Z + Z (K_y - s_y I)^T = B,
+ * s_x + s_y = sigma, split in proportion to c_x and c_y, solved in the
  * eigenbasis of K_x and K_y (four mode products and a pointwise divide), which
- * is exact, as the paper's Bartels-Stewart solve is.  1D operators only
- * (TP3B_ENOTSUP for 2D).  X and Y may not overlap. */
+ * is exact, as the paper's Bartels-Stewart solve is.  2D (the paper has no 2D
+ * preconditioner; this extends the same construction): the four-mode sum
+ * K_x1 + K_x2 + K_y1 + K_y2 - sigma is inverted in the eigenbases of the four
+ * mode operators (eight mode products and a divide).  TP3B_ENOTSUP if a mode
+ * operator has a complex spectrum or a denominator vanishes.  X and Y may not
+ * overlap. */
 tp3b_status tp3b_apply_prec(tp3b_op op, int32_t prec, int32_t nvec, const void* X, int64_t ldx,
                             void* Y, int64_t ldy, void* stream);
 
@@ -134,7 +138,8 @@ tp3b_status tp3b_block_orth(int64_t N, int32_t nq, const double* Q, int64_t ldq,
                             double* X, int64_t ldx, double* C_qx, double* R_xx, int32_t* rank,
                             uint64_t seed, void* stream);
 
-/* Eigensolver options (Sec. 4.1).  Zero/negative fields select defaults. */
+/* Eigensolver options (Sec. 4.1).  Zero/negative fields select defaults
+ * (except stall_tol; start from tp3b_jdqr_default_opts). */
 typedef struct {
   int32_t nev;          /* wanted eigenpairs (smallest real part) */
   int32_t block;        /* block size b (vectors added per outer iteration) */
@@ -142,7 +147,7 @@ typedef struct {
                            up to a multiple of b, m_min = m_max/2 */
   int32_t gmres_steps;  /* fixed GMRES steps per correction equation, default 10 */
   int32_t max_outer;    /* outer iteration cap, default 1000 */
-  int32_t precond;      /* 0: none, 1: kinetic Sylvester preconditioner (1D) */
+  int32_t precond;      /* 0: none, 1: kinetic preconditioner (tp3b_apply_prec) */
   int32_t inner_prec;   /* tp3b_prec of the GMRES applies; outer work is FP64 */
   double tol;           /* lock when ||r|| <= tol max(|theta|, 1); default 1e-12 */
   double switch_tol;    /* use `target` as the correction shift while
@@ -155,6 +160,11 @@ typedef struct {
   int32_t graph;        /* batched solver: capture the GMRES inner iteration as a
                            HIP graph once per solve and replay it every outer
                            iteration (0 = launch eagerly) */
+  double stall_tol;     /* when nothing locks, lock the leading pair once its
+                           residual is <= stall_tol max(|theta|, 1) and has stayed
+                           within 10% of its previous value for three outer
+                           iterations (the FP64 rounding floor of the residual
+                           grows with ||H||); default 1e-8, <= 0 disables */
 } tp3b_jdqr_opts;
 
 typedef struct {

@@ -19,7 +19,10 @@ leaves to its eigensolver library are marked R):
    are moved from V to Q and R is extended by [Q^T A u_j; T_{1..j, j}].  (The
    criterion is absolute below unit magnitude: the FP64 rounding floor of the
    residual of these stiff operators lies near 1e-13 in absolute terms, so a
-   purely relative 1e-12 is unreachable for eigenvalues of size ~0.1.)
+   purely relative 1e-12 is unreachable for eigenvalues of size ~0.1.)  The
+   floor grows with ||A|| (it reaches ~5e-10 on some 128 x 128 grids with small
+   mass ratios), so a leading pair whose residual stagnates below stall_tol is
+   locked as well (see the jdqr docstring).
 5. (R) Restart: when the basis would grow beyond m_max it is compressed to its
    m_min leading Schur vectors (the paper's "truncated" compression of the
    search space).
@@ -141,14 +144,19 @@ class JDQRResult:
 
 def jdqr(apply_A, N, nev, block, *, tol=1e-12, m_min=None, m_max=None,
          gmres_steps=10, precond=None, apply_inner=None, X0=None, seed=0,
-         max_outer=1000, target=None, switch_tol=1e-2):
+         max_outer=1000, target=None, switch_tol=1e-2, stall_tol=1e-8):
     """Partial Schur form for the nev eigenvalues of smallest real part.
 
     apply_A(X) -> A X for X of shape (N, k), in FP64.  apply_inner, if given,
     is used inside GMRES instead of apply_A (the low-precision form).
     precond(X) -> P^{-1} X or None (no preconditioner).
     target: shift used in the correction equation instead of theta_j while
-    ||r_j|| > switch_tol |theta_j| (None: always theta_j)."""
+    ||r_j|| > switch_tol |theta_j| (None: always theta_j).
+    stall_tol: (R) when nothing locks, the leading pair is locked anyway once
+    its residual is <= stall_tol max(|theta|, 1) and has stayed within 10 % of
+    its previous value in three consecutive outer iterations -- the residual has
+    reached the FP64 rounding floor of the stored images A V, which grows with
+    ||A|| (<= 0 disables)."""
     b = block
     dmin, dmax = default_sizes(nev, b)
     m_min = dmin if m_min is None else m_min
@@ -166,6 +174,7 @@ def jdqr(apply_A, N, nev, block, *, tol=1e-12, m_min=None, m_max=None,
     AV = apply_A(V)
     res.n_apply += V.shape[1]
     outer = 0
+    prev_rn0, stall = np.inf, 0
     while Q.shape[1] < nev and outer < max_outer:
         M = V.T @ AV
         S, T, pair = ordered_schur(M)
@@ -185,7 +194,20 @@ def jdqr(apply_A, N, nev, block, *, tol=1e-12, m_min=None, m_max=None,
             if p + blk > nb or not np.all(rn[p:p + blk] <= tol * np.maximum(np.abs(theta[p:p + blk]), 1.0)):
                 break
             p += blk
+        if p == 0 and stall_tol > 0:
+            # stagnation at the rounding floor (see stall_tol)
+            if (rn[0] <= stall_tol * max(abs(theta[0]), 1.0)
+                    and 0.9 * prev_rn0 <= rn[0] <= 1.1 * prev_rn0):
+                stall += 1
+            else:
+                stall = 0
+            prev_rn0 = rn[0]
+            blk = 2 if pair[0] else 1
+            if stall >= 3 and blk <= nb:
+                p = blk
+                res.history.append(("stall-lock", outer, float(rn[0])))
         if p > 0:
+            prev_rn0, stall = np.inf, 0
             QtAU = Q.T @ AU[:, :p]
             k = Rl.shape[0]
             Rn = np.zeros((k + p, k + p))

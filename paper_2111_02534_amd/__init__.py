@@ -48,7 +48,7 @@ class JdqrOpts(ctypes.Structure):
                 ("switch_tol", ctypes.c_double), ("target", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("check_finite", ctypes.c_int32),
                 ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("graph", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("stall_tol", ctypes.c_double)]
 
 
 class JdqrStats(ctypes.Structure):
@@ -284,7 +284,7 @@ class Operator:
 
     def jdqr(self, nev, block, *, X0=None, inner_prec=FP64, precond=True, tol=1e-12,
              gmres_steps=10, m_min=0, m_max=0, max_outer=1000, seed=0, switch_tol=1e-2,
-             target=None, verbose=False, want_Q=True, profile=False):
+             target=None, verbose=False, want_Q=True, profile=False, stall_tol=1e-8):
         import numpy as np
         import torch
         o = JdqrOpts()
@@ -294,6 +294,7 @@ class Operator:
         o.inner_prec, o.tol, o.switch_tol = inner_prec, tol, switch_tol
         o.target = float("nan") if target is None else float(target)
         o.seed, o.verbose, o.profile = seed, int(verbose), int(profile)
+        o.stall_tol = float(stall_tol)
         evals = np.empty(nev)
         R = np.empty((nev, nev), order="F")
         res = np.empty(nev)
@@ -411,7 +412,7 @@ class BatchedResult:
 
 def jdqr_batched(ops, nev, block, *, inner_prec=FP64, precond=True, tol=1e-12, gmres_steps=10,
                  m_min=0, m_max=0, max_outer=1000, seed=0, switch_tol=1e-2, target=None,
-                 graph=True, want_Q=False, verbose=False):
+                 graph=True, want_Q=False, verbose=False, stall_tol=1e-8):
     """Block JDQR on every operator of a batch at once (tp3b_jdqr_solve_batched)."""
     import numpy as np
     import torch
@@ -422,6 +423,7 @@ def jdqr_batched(ops, nev, block, *, inner_prec=FP64, precond=True, tol=1e-12, g
     o.inner_prec, o.tol, o.switch_tol = inner_prec, tol, switch_tol
     o.target = float("nan") if target is None else float(target)
     o.seed, o.verbose, o.graph = seed, int(verbose), int(bool(graph))
+    o.stall_tol = float(stall_tol)
     n = len(ops)
     evals = np.empty((n, nev))
     res = np.empty((n, nev))

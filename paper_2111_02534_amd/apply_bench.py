@@ -29,6 +29,34 @@ def flops(ndim, n, nvec, kind):
     return nvec * ((4.0 * n ** 3 + 3.0 * n ** 2) if kind == "H" else (8.0 * n ** 3 + n ** 2))
 
 
+def counters(args):
+    import torch
+
+    import paper_2111_02534_amd as t3
+    from workloads import config
+    pname = (args.prec or ["fp64"])[0]
+    pk = {"fp64": t3.FP64, "fp32": t3.FP32, "bf16x3": t3.BF16X3}[pname]
+    dt = torch.float64 if pname == "fp64" else torch.float32
+    for name in args.names:
+        cfg = config(name)
+        op = t3.Operator.from_config(cfg)
+        X = torch.randn((cfg["block"], op.N), dtype=dt, device="cuda")
+        Y = torch.empty_like(X)
+        for _ in range(args.reps):
+            op.apply_H(X, Y, prec=pk)
+        torch.cuda.synchronize()
+        es = X.element_size()
+        print(f"{name} {pname}: {args.reps} applies of {cfg['block']} vectors, N = {op.N}; "
+              f"block {cfg['block'] * op.N * es} bytes", flush=True)
+        op.close()
+    n = args.copy_mb * (1 << 20) // 4
+    A = torch.ones(n, dtype=torch.float32, device="cuda")
+    B = torch.empty_like(A)
+    B.copy_(A)
+    torch.cuda.synchronize()
+    print(f"copy: {n * 4} bytes read, {n * 4} bytes written", flush=True)
+
+
 def main():
     import torch
 
@@ -39,7 +67,15 @@ def main():
     ap.add_argument("names", nargs="+")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--prec", nargs="*", default=None, help="subset of fp64 fp32 bf16x3")
+    ap.add_argument("--counters", action="store_true",
+                    help="for hardware-counter runs: only the workload's Hamiltonian apply in the "
+                         "first listed precision with the built-in tile choice, repeated --reps "
+                         "times, then a device-to-device copy of --copy-mb MiB (the calibration "
+                         "kernel for byte counters)")
+    ap.add_argument("--copy-mb", type=int, default=256)
     args = ap.parse_args()
+    if args.counters:
+        return counters(args)
     for name in args.names:
         cfg = config(name)
         n, b, ndim = cfg["n"], cfg["block"], cfg["ndim"]

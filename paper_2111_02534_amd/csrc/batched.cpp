@@ -145,13 +145,13 @@ ModeProd<T> prec_job(tp3b_op op, int st, int nv, const T* X, int64_t ldx, T* Y, 
   a.epi = EPI_NONE;
   const int64_t N = op->N;
   switch (st) {
-    case 0: a.X = X; a.ldx = ldx; a.Y = d.work; a.ldy = N; a.L = d.Sxi; break;
+    case 0: a.X = X; a.ldx = ldx; a.Y = d.work; a.ldy = N; a.L = d.Si[0]; break;
     case 1:
-      a.X = d.work; a.ldx = N; a.Y = Y; a.ldy = ldy; a.R = d.SyiT;
-      a.epi = EPI_DIV; a.lamL = d.lx; a.lamR = d.ly;
+      a.X = d.work; a.ldx = N; a.Y = Y; a.ldy = ldy; a.R = d.SiT[1];
+      a.epi = EPI_DIV; a.lamL = d.lam[0]; a.lamR = d.lam[1];
       break;
-    case 2: a.X = Y; a.ldx = ldy; a.Y = d.work; a.ldy = N; a.L = d.Sx; break;
-    default: a.X = d.work; a.ldx = N; a.Y = Y; a.ldy = ldy; a.R = d.SyT; break;
+    case 2: a.X = Y; a.ldx = ldy; a.Y = d.work; a.ldy = N; a.L = d.S[0]; break;
+    default: a.X = d.work; a.ldx = N; a.Y = Y; a.ldy = ldy; a.R = d.ST[1]; break;
   }
   return a;
 }
@@ -264,6 +264,8 @@ struct Inst {
   int tH64 = 0, tHW = 0, tP64 = 0, tPW = 0;
   // host state (as in jdqr.cpp)
   int k = 0, m = 0, av0 = 0, outer = 0;
+  double prev_rn0 = INFINITY;
+  int stall = 0;
   bool done = false;
   int status = TP3B_OK;
   std::vector<double> M, Rl, lockres, S, T;
@@ -626,6 +628,7 @@ tp3b_status BatchedJdqr<TW>::orth(const std::vector<int>& list0, const std::vect
       if (!std::isfinite(n0[i][j])) return fail(TP3B_ENONFINITE, "batched orth: non-finite input");
     }
   }
+  std::vector<std::vector<int>> replaced(count_);
   for (int attempt = 0; attempt < 4 && !list.empty(); ++attempt) {
     for (int i : list) std::memcpy(n0_.hat(i), n0[i].data(), sizeof(double) * nxv[i]);
     TP3B_HIP(hipMemcpyAsync(n0_.d, n0_.h.data(), sizeof(double) * n0_.h.size(), hipMemcpyHostToDevice, s_));
@@ -754,9 +757,13 @@ tp3b_status BatchedJdqr<TW>::orth(const std::vector<int>& list0, const std::vect
       const int i = bad_list[b];
       const size_t e = bad_e[b];
       const int* fl = (const int*)FlagsD_.hat(i);
+      if (replaced[i].empty()) replaced[i].assign(nxv[i], 0);
       for (int j = 0; j < nxv[i]; ++j)
-        if (fl[j]) TP3B_HIP(launch_hash_fill(in_[i].N, Xs[e] + (int64_t)j * in_[i].N,
-                                             seed + 7919ull * (uint64_t)i, (uint64_t)(attempt * 64 + j), s_));
+        if (fl[j]) {
+          replaced[i][j] = 1;
+          TP3B_HIP(launch_hash_fill(in_[i].N, Xs[e] + (int64_t)j * in_[i].N,
+                                    seed + 7919ull * (uint64_t)i, (uint64_t)(attempt * 64 + j), s_));
+        }
       nl.push_back(i);
       nqn.push_back(nq[e]);
       nQ.push_back(Qs[e]);
@@ -772,8 +779,11 @@ tp3b_status BatchedJdqr<TW>::orth(const std::vector<int>& list0, const std::vect
       std::vector<const double*> A(Xs.begin(), Xs.end());
       TP3B_TRY(dot_to_host(list, p, p, A, A, G_));
     }
+    // the dependence test of a replaced column refers to its new norm; the
+    // other columns keep their input norms
     for (int i : list)
-      for (int j = 0; j < nxv[i]; ++j) n0[i][j] = G_.hat(i)[j + j * nxv[i]];
+      for (int j = 0; j < nxv[i]; ++j)
+        if (replaced[i][j]) n0[i][j] = G_.hat(i)[j + j * nxv[i]];
   }
   return TP3B_OK;
 }
@@ -1041,7 +1051,21 @@ tp3b_status BatchedJdqr<TW>::iterate() {
       if (!ok) break;
       p += blk;
     }
+    if (p == 0 && o_.stall_tol > 0) {
+      // the leading residual has reached its FP64 rounding floor
+      const double r0 = I.rn[0];
+      if (r0 <= o_.stall_tol * std::max(std::fabs(I.theta[0]), 1.0) && r0 >= 0.9 * I.prev_rn0 &&
+          r0 <= 1.1 * I.prev_rn0)
+        ++I.stall;
+      else
+        I.stall = 0;
+      I.prev_rn0 = r0;
+      const int blk = I.pair[0] ? 2 : 1;
+      if (I.stall >= 3 && blk <= nb) p = blk;
+    }
     if (p > 0) {
+      I.prev_rn0 = INFINITY;
+      I.stall = 0;
       if (I.k + p > nev_) p = nev_ - I.k;
       I.lockp = p;
       locking.push_back(i);

@@ -190,7 +190,7 @@ __device__ __forceinline__ void modeprod_tile(const ModeProd<T>& a, int64_t w,
             T pot = (Vp ? Vp[off] : T(0)) - T(shift);
             v += pot * X[off];
           } else if (a.epi == EPI_DIV) {
-            v = v / (a.lamL[gi] + a.lamR[gj] - T(a.sigma));
+            v = v / (a.lamL[gi] + a.lamR[gj] + (a.lamItem ? a.lamItem[item] : T(0)) - T(a.sigma));
           }
           if (a.acc) v += Y[off];
           Y[off] = v;
@@ -392,7 +392,7 @@ __device__ __forceinline__ void modeprod_bf3_tile(const ModeProd<float>& a, int6
             const float pot = (Vp ? Vp[off] : 0.f) - (float)shift;
             v += pot * X[off];
           } else if (a.epi == EPI_DIV) {
-            v = v / (a.lamL[gi] + a.lamR[gj] - (float)a.sigma);
+            v = v / (a.lamL[gi] + a.lamR[gj] + (a.lamItem ? a.lamItem[item] : 0.f) - (float)a.sigma);
           }
           if (a.acc) v += Y[off];
           Y[off] = v;

@@ -17,13 +17,15 @@ struct DevOps {
   T* K[4] = {nullptr, nullptr, nullptr, nullptr};   // -c D2 of each mode, row-major
   T* KT[4] = {nullptr, nullptr, nullptr, nullptr};  // its transpose (right operand)
   T* V = nullptr;                                   // potential table, vector layout
-  // 1D preconditioner factors: K_x = Sx diag(lx) Sx^{-1}, K_y = Sy diag(ly) Sy^{-1}.
-  T* Sxi = nullptr;   // Sx^{-1}        (left operand)
-  T* Sx = nullptr;    // Sx             (left operand)
-  T* SyiT = nullptr;  // (Sy^{-1})^T    (right operand: Z Sy^{-T})
-  T* SyT = nullptr;   // Sy^T           (right operand: Z Sy^T)
-  T* lx = nullptr;
-  T* ly = nullptr;
+  // Preconditioner factors per mode: K_k = S_k diag(lam_k) S_k^{-1}.  1D uses
+  // modes 0 (x, left operands) and 1 (y, right operands); 2D uses modes 0-2 as
+  // left operands and mode 3 as right operand.
+  T* Si[4] = {nullptr, nullptr, nullptr, nullptr};   // S_k^{-1}      (left operand)
+  T* S[4] = {nullptr, nullptr, nullptr, nullptr};    // S_k           (left operand)
+  T* SiT[4] = {nullptr, nullptr, nullptr, nullptr};  // (S_k^{-1})^T  (right operand)
+  T* ST[4] = {nullptr, nullptr, nullptr, nullptr};   // S_k^T         (right operand)
+  T* lam[4] = {nullptr, nullptr, nullptr, nullptr};
+  T* lamItem = nullptr;  // 2D: lam_x1[i1] + lam_x2[i2] per (x1, x2) plane
   T* work = nullptr;  // preconditioner intermediate, work_vecs vectors
 };
 

@@ -242,6 +242,8 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   std::vector<double> S, T;
   std::vector<int> pair;
   int outer = 0;
+  double prev_rn0 = INFINITY;  // leading residual of the last outer iteration
+  int stall = 0;               // consecutive outer iterations without progress
   while (k < nev && outer < o.max_outer) {
     // ---- 1. ordered Schur form of the projected matrix, rotate V and A V
     double t0 = now();
@@ -307,7 +309,21 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       if (!ok) break;
       p += blk;
     }
+    if (p == 0 && o.stall_tol > 0) {
+      // the leading residual has reached its FP64 rounding floor
+      const double r0 = rn[0];
+      if (r0 <= o.stall_tol * std::max(std::fabs(theta[0]), 1.0) && r0 >= 0.9 * prev_rn0 &&
+          r0 <= 1.1 * prev_rn0)
+        ++stall;
+      else
+        stall = 0;
+      prev_rn0 = r0;
+      const int blk = pair[0] ? 2 : 1;
+      if (stall >= 3 && blk <= nb) p = blk;
+    }
     if (p > 0) {
+      prev_rn0 = INFINITY;
+      stall = 0;
       if (k + p > nev) p = nev - k;  // never split beyond nev (pairs are not expected here)
       const int m_old = m;
       for (int j = 0; j < p; ++j) {
@@ -551,6 +567,7 @@ tp3b_status tp3b_jdqr_default_opts(tp3b_jdqr_opts* o) {
   o->inner_prec = TP3B_FP64;
   o->tol = 1e-12;
   o->switch_tol = 1e-2;
+  o->stall_tol = 1e-8;
   o->target = NAN;
   o->seed = 0;
   return TP3B_OK;
@@ -576,8 +593,8 @@ tp3b_status tp3b_jdqr_solve(tp3b_op op, const tp3b_jdqr_opts* opts, const double
     return fail(TP3B_EINVAL, "need block <= m_min and m_min + block <= m_max");
   if (op->N < (int64_t)(o.nev + o.m_max + o.block))
     return fail(TP3B_EINVAL, "problem too small for nev + m_max + block basis vectors");
-  if (o.precond && (op->ndim != 1 || !op->have_prec))
-    return fail(TP3B_ENOTSUP, "the kinetic preconditioner is available for 1D operators only");
+  if (o.precond && !op->have_prec)
+    return fail(TP3B_ENOTSUP, "the kinetic preconditioner is unavailable for this operator");
   if (X0 && b0 < 0) return fail(TP3B_EINVAL, "b0 must be >= 0");
   TP3B_HIP(hipSetDevice(op->device));
   if (o.inner_prec != TP3B_FP64 && o.inner_prec != TP3B_FP32 && o.inner_prec != TP3B_BF16X3)

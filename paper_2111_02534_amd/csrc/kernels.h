@@ -15,7 +15,7 @@ enum Epi { EPI_NONE = 0, EPI_V = 1, EPI_DIV = 2 };
 // computes   Y = [L Xq] + [Xq R] (+ epilogue)   with L an M x M and R an
 // Nc x Nc row-major operator (either may be absent), and the epilogue
 //   EPI_V:   + (V[item*bstride + i*rs + j] - shift[vec]) * Xq[i, j]
-//   EPI_DIV: / (lamL[i] + lamR[j] - sigma)
+//   EPI_DIV: / (lamL[i] + lamR[j] + lamItem[item] - sigma)   (lamItem optional)
 // optionally accumulated into Y (acc != 0).
 template <typename T>
 struct ModeProd {
@@ -30,6 +30,7 @@ struct ModeProd {
   const double* shifts;
   const T* lamL;
   const T* lamR;
+  const T* lamItem;
   double sigma;
   int epi;
   int acc;

@@ -1,5 +1,6 @@
 // C-ABI entry points: operator set-up, Hamiltonian and preconditioner applies,
 // block orthogonalisation.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -127,7 +128,12 @@ static void free_ops(tp3b::DevOps<T>& d) {
     if (d.K[k]) (void)hipFree(d.K[k]);
     if (d.KT[k]) (void)hipFree(d.KT[k]);
   }
-  T* ps[] = {d.V, d.Sxi, d.Sx, d.SyiT, d.SyT, d.lx, d.ly, d.work};
+  for (int k = 0; k < 4; ++k) {
+    T* ps[] = {d.Si[k], d.S[k], d.SiT[k], d.ST[k], d.lam[k]};
+    for (T* p : ps)
+      if (p) (void)hipFree(p);
+  }
+  T* ps[] = {d.V, d.lamItem, d.work};
   for (T* p : ps)
     if (p) (void)hipFree(p);
   d = tp3b::DevOps<T>();
@@ -140,21 +146,35 @@ static std::vector<double> transpose(const std::vector<double>& A, int n) {
   return B;
 }
 
+// Host eigen-factors of the kinetic mode operators K_k = S_k diag(lam_k) S_k^{-1}.
+struct PrecFactors {
+  std::vector<double> S[4], Si[4], lam[4];
+  std::vector<double> lamItem;  // 2D: lam_0[i1] + lam_1[i2]
+};
+
 template <typename T>
 static tp3b_status upload_ops(tp3b_op op, tp3b::DevOps<T>& d, const std::vector<double>* Kh,
-                              const std::vector<double>* pre) {
+                              const PrecFactors& pf) {
   for (int k = 0; k < op->nmodes; ++k) {
     TP3B_HIP(upload(&d.K[k], Kh[k]));
     TP3B_HIP(upload(&d.KT[k], transpose(Kh[k], op->n[k])));
   }
   TP3B_HIP(upload(&d.V, op->Vh));
   if (op->have_prec) {
-    TP3B_HIP(upload(&d.Sxi, pre[0]));
-    TP3B_HIP(upload(&d.Sx, pre[1]));
-    TP3B_HIP(upload(&d.SyiT, pre[2]));
-    TP3B_HIP(upload(&d.SyT, pre[3]));
-    TP3B_HIP(upload(&d.lx, pre[4]));
-    TP3B_HIP(upload(&d.ly, pre[5]));
+    // the last mode is applied from the right (transposed factors), the others
+    // from the left
+    const int last = op->nmodes - 1;
+    for (int k = 0; k < op->nmodes; ++k) {
+      if (k < last) {
+        TP3B_HIP(upload(&d.Si[k], pf.Si[k]));
+        TP3B_HIP(upload(&d.S[k], pf.S[k]));
+      } else {
+        TP3B_HIP(upload(&d.SiT[k], transpose(pf.Si[k], op->n[k])));
+        TP3B_HIP(upload(&d.ST[k], transpose(pf.S[k], op->n[k])));
+      }
+      TP3B_HIP(upload(&d.lam[k], pf.lam[k]));
+    }
+    if (op->ndim == 2) TP3B_HIP(upload(&d.lamItem, pf.lamItem));
     TP3B_HIP(hipMalloc((void**)&d.work, sizeof(T) * op->N * op->work_vecs));
   }
   return TP3B_OK;
@@ -287,8 +307,55 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
                             hipStream_t s, bool bf3) {
   tp3b::DevOps<T>& d = ops_for<T>(op);
   const bool f64 = sizeof(T) == 8;
-  const int nx = op->n[0], ny = op->n[1];
   const int64_t N = op->N;
+  if (op->ndim == 2) {
+    // (K - sigma)^{-1} = (S_1 x S_2 x S_3 x S_4) diag(1 / (sum_k lam_k - sigma))
+    // (S_1^{-1} x ... x S_4^{-1}): eight single-mode products, the divide fused
+    // into the fourth; the work buffer and Y alternate as intermediates.
+    const int n0 = op->n[0], n1 = op->n[1], n2 = op->n[2], n3 = op->n[3];
+    for (int v0 = 0; v0 < nvec; v0 += op->work_vecs) {
+      const int nv = (nvec - v0 < op->work_vecs) ? nvec - v0 : op->work_vecs;
+      const T* Xc = X + (int64_t)v0 * ldx;
+      T* Yc = Y + (int64_t)v0 * ldy;
+      // mode k, factor F (left operand for k < 3, right operand for k = 3)
+      auto pass = [&](int k, const T* F, const T* in, int64_t ldin, T* out, int64_t ldout,
+                      bool divide) -> tp3b_status {
+        ModeProd<T> a{};
+        a.X = in; a.ldx = ldin; a.Y = out; a.ldy = ldout;
+        a.epi = EPI_NONE;
+        switch (k) {
+          case 0: a.M = n0; a.Nc = n1 * n2 * n3; a.rs = a.Nc; a.bstride = 0; a.per_vec = 1; break;
+          case 1: a.M = n1; a.Nc = n2 * n3; a.rs = a.Nc; a.bstride = (int64_t)n1 * a.Nc; a.per_vec = n0; break;
+          default: a.M = n2; a.Nc = n3; a.rs = n3; a.bstride = (int64_t)n2 * n3; a.per_vec = n0 * n1; break;
+        }
+        a.nbatch = nv * a.per_vec;
+        if (k < 3) a.L = F; else a.R = F;
+        if (divide) {
+          a.epi = EPI_DIV;
+          a.lamL = d.lam[2];
+          a.lamR = d.lam[3];
+          a.lamItem = d.lamItem;
+          a.sigma = op->sigma;
+        }
+        const int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, a.nbatch, f64);
+        TP3B_HIP(modeprod(a, tile, s, bf3));
+        return TP3B_OK;
+      };
+      T* W = d.work;
+      tp3b_status st = TP3B_OK;
+      if (st == TP3B_OK) st = pass(0, d.Si[0], Xc, ldx, W, N, false);
+      if (st == TP3B_OK) st = pass(1, d.Si[1], W, N, Yc, ldy, false);
+      if (st == TP3B_OK) st = pass(2, d.Si[2], Yc, ldy, W, N, false);
+      if (st == TP3B_OK) st = pass(3, d.SiT[3], W, N, Yc, ldy, true);
+      if (st == TP3B_OK) st = pass(3, d.ST[3], Yc, ldy, W, N, false);
+      if (st == TP3B_OK) st = pass(2, d.S[2], W, N, Yc, ldy, false);
+      if (st == TP3B_OK) st = pass(1, d.S[1], Yc, ldy, W, N, false);
+      if (st == TP3B_OK) st = pass(0, d.S[0], W, N, Yc, ldy, false);
+      if (st != TP3B_OK) return st;
+    }
+    return TP3B_OK;
+  }
+  const int nx = op->n[0], ny = op->n[1];
   // Z = Sx [ (Sx^{-1} B Sy^{-T}) / (lx_i + ly_j - sigma) ] Sy^T, four mode
   // products; the work buffer and Y alternate as intermediates.
   for (int v0 = 0; v0 < nvec; v0 += op->work_vecs) {
@@ -305,19 +372,19 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
     const int tile = tile_for(op, f64, bf3, 1, nx, ny, nv);
     // 1: W = Sx^{-1} B
     a.X = Xc; a.ldx = ldx; a.Y = d.work; a.ldy = N;
-    a.L = d.Sxi; a.R = nullptr; a.epi = EPI_NONE;
+    a.L = d.Si[0]; a.R = nullptr; a.epi = EPI_NONE;
     TP3B_HIP(modeprod(a, tile, s, bf3));
     // 2: Y = (W Sy^{-T}) / (lx_i + ly_j - sigma)
     a.X = d.work; a.ldx = N; a.Y = Yc; a.ldy = ldy;
-    a.L = nullptr; a.R = d.SyiT; a.epi = EPI_DIV; a.lamL = d.lx; a.lamR = d.ly;
+    a.L = nullptr; a.R = d.SiT[1]; a.epi = EPI_DIV; a.lamL = d.lam[0]; a.lamR = d.lam[1];
     TP3B_HIP(modeprod(a, tile, s, bf3));
     // 3: W = Sx Y
     a.X = Yc; a.ldx = ldy; a.Y = d.work; a.ldy = N;
-    a.L = d.Sx; a.R = nullptr; a.epi = EPI_NONE;
+    a.L = d.S[0]; a.R = nullptr; a.epi = EPI_NONE;
     TP3B_HIP(modeprod(a, tile, s, bf3));
     // 4: Y = W Sy^T
     a.X = d.work; a.ldx = N; a.Y = Yc; a.ldy = ldy;
-    a.L = nullptr; a.R = d.SyT; a.epi = EPI_NONE;
+    a.L = nullptr; a.R = d.ST[1]; a.epi = EPI_NONE;
     TP3B_HIP(modeprod(a, tile, s, bf3));
   }
   return TP3B_OK;
@@ -597,34 +664,51 @@ tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* ou
   } else {
     op->sigma = desc->sigma;
   }
-  // Fast-diagonalisation factors of the 1D kinetic Sylvester operator.
-  std::vector<double> pre[6];
-  if (op->ndim == 1) {
-    const int nx = op->n[0], ny = op->n[1];
-    std::vector<double> Sx((size_t)nx * nx), Sxi((size_t)nx * nx), lx(nx);
-    std::vector<double> Sy((size_t)ny * ny), Syi((size_t)ny * ny), ly(ny);
-    bool okx = eigen_decompose_real(nx, Kh[0].data(), Sx.data(), Sxi.data(), lx.data());
-    bool oky = eigen_decompose_real(ny, Kh[1].data(), Sy.data(), Syi.data(), ly.data());
-    if (okx && oky) {
-      double mn = 1e300;
-      for (int i = 0; i < nx; ++i)
-        for (int j = 0; j < ny; ++j) mn = std::min(mn, std::fabs(lx[i] + ly[j] - op->sigma));
-      op->lam_min = mn;
-      if (mn > 0) {
-        op->have_prec = true;
-        pre[0] = Sxi;
-        pre[1] = Sx;
-        pre[2] = transpose(Syi, ny);
-        pre[3] = transpose(Sy, ny);
-        pre[4] = lx;
-        pre[5] = ly;
-      }
+  // Fast-diagonalisation factors of the kinetic operator, one per mode: the
+  // shifted Kronecker sum is then inverted exactly by mode products and a
+  // pointwise divide (1D: the Sylvester equation of eq. (14); 2D: the same
+  // construction over four modes).
+  PrecFactors pf;
+  {
+    bool ok = true;
+    for (int k = 0; k < nm && ok; ++k) {
+      const int n = op->n[k];
+      pf.S[k].resize((size_t)n * n);
+      pf.Si[k].resize((size_t)n * n);
+      pf.lam[k].resize(n);
+      ok = eigen_decompose_real(n, Kh[k].data(), pf.S[k].data(), pf.Si[k].data(), pf.lam[k].data());
     }
-    int64_t cap = (int64_t)(1ll << 30) / (N * 8);
+    if (ok) {
+      // smallest |denominator|: sums over the x modes against sums over the y modes
+      std::vector<double> xs, ys;
+      if (op->ndim == 1) {
+        xs = pf.lam[0];
+        ys = pf.lam[1];
+      } else {
+        for (double a : pf.lam[0])
+          for (double b : pf.lam[1]) xs.push_back(a + b);
+        for (double a : pf.lam[2])
+          for (double b : pf.lam[3]) ys.push_back(a + b);
+        pf.lamItem = xs;  // index i1 * n1 + i2
+      }
+      std::vector<double> ysort = ys;
+      std::sort(ysort.begin(), ysort.end());
+      double mn = 1e300;
+      for (double a : xs) {
+        const double want = op->sigma - a;
+        auto it = std::lower_bound(ysort.begin(), ysort.end(), want);
+        if (it != ysort.end()) mn = std::min(mn, std::fabs(a + *it - op->sigma));
+        if (it != ysort.begin()) mn = std::min(mn, std::fabs(a + *(it - 1) - op->sigma));
+      }
+      op->lam_min = mn;
+      op->have_prec = mn > 0;
+    }
+    // preconditioner work buffer: up to 64 vectors, at most 4 GiB (FP64)
+    const int64_t cap = (int64_t)(1ll << 32) / (N * 8);
     op->work_vecs = (int)std::max<int64_t>(1, std::min<int64_t>(64, cap));
   }
-  tp3b_status st = upload_ops<double>(op, op->d64, Kh, pre);
-  if (st == TP3B_OK) st = upload_ops<float>(op, op->d32, Kh, pre);
+  tp3b_status st = upload_ops<double>(op, op->d64, Kh, pf);
+  if (st == TP3B_OK) st = upload_ops<float>(op, op->d32, Kh, pf);
   if (st != TP3B_OK) {
     std::string msg = g_err;
     tp3b_destroy(op);
@@ -703,7 +787,6 @@ tp3b_status tp3b_apply_prec(tp3b_op op, int32_t prec, int32_t nvec, const void* 
                             void* Y, int64_t ldy, void* stream) {
   tp3b_status st = check_apply(op, prec, nvec, X, ldx, Y, ldy);
   if (st != TP3B_OK || nvec == 0) return st;
-  if (op->ndim != 1) return fail(TP3B_ENOTSUP, "the kinetic preconditioner is 1D only");
   if (!op->have_prec) return fail(TP3B_ENOTSUP, "kinetic factors have complex spectrum or K - sigma is singular");
   TP3B_HIP(hipSetDevice(op->device));
   hipStream_t s = (hipStream_t)stream;

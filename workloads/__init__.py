@@ -44,6 +44,10 @@ CONFIGS = {
 }
 
 C4_SIZES = (64, 96, 128, 192, 256)
+# Locking tolerance of the batched workload (relative to max(|theta|, 1)): the
+# FP64 floor of the residual formed from the stored basis images reaches ~6e-11
+# for some of these instances, above the 1e-12 used for the single workloads.
+C4_TOL = 1e-10
 
 
 def config(name: str) -> dict:
@@ -62,7 +66,7 @@ def c4_instances(count: int = 256, seed: int = 2111) -> list[dict]:
         v0 = float(rng.uniform(0.5, 5.0))
         w = float(rng.uniform(0.5, 2.0))
         out.append(dict(ndim=1, n=n, L=L_DEFAULT, alpha=alpha, v0=v0, width=w,
-                        nev=4, block=4, seed_start=1000 + i))
+                        nev=4, block=4, seed_start=1000 + i, tol=C4_TOL))
     return out
 
 
