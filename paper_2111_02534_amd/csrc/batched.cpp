@@ -307,8 +307,17 @@ class BatchedJdqr {
                      double beta, const std::vector<double*>& Y);
   tp3b_status copy64(const std::vector<int>& list, const std::vector<int>& ncol, double alpha,
                      const std::vector<const double*>& X, const std::vector<double*>& Y);
+  // Waits for the stream; every table staged so far has then been consumed, so
+  // the phase arena starts over.
   tp3b_status sync() {
     TP3B_HIP(hipStreamSynchronize(s_));
+    ar_.reset();
+    return TP3B_OK;
+  }
+  // Tables are appended to the phase arena without waiting; only when it runs
+  // low does the stream have to drain first.
+  tp3b_status arena_room() {
+    if (ar_.free_bytes() < ((size_t)4 << 20)) return sync();
     return TP3B_OK;
   }
   // ---- the GMRES phase
@@ -474,8 +483,7 @@ template <typename TW>
 tp3b_status BatchedJdqr<TW>::apply_H64(const std::vector<int>& list, const std::vector<double*>& X,
                                        const std::vector<double*>& Y, const std::vector<int>& nv) {
   if (list.empty()) return TP3B_OK;
-  TP3B_TRY(sync());
-  ar_.reset();
+  TP3B_TRY(arena_room());
   MpTabs<double> t;
   if (!mp_alloc(ar_, tsH64_, (int)list.size(), false, t)) return arena_full();
   for (size_t e = 0; e < list.size(); ++e) {
@@ -495,8 +503,7 @@ tp3b_status BatchedJdqr<TW>::prec64(const std::vector<int>& list,
                                     const std::vector<const double*>& X,
                                     const std::vector<double*>& Y, const std::vector<int>& nv) {
   if (list.empty()) return TP3B_OK;
-  TP3B_TRY(sync());
-  ar_.reset();
+  TP3B_TRY(arena_room());
   MpTabs<double> t[4];
   for (int st = 0; st < 4; ++st)
     if (!mp_alloc(ar_, tsP64_, (int)list.size(), false, t[st])) return arena_full();
@@ -521,8 +528,7 @@ tp3b_status BatchedJdqr<TW>::dot_to_host(const std::vector<int>& list, const std
                                          const std::vector<const double*>& A,
                                          const std::vector<const double*>& B, Small& out) {
   if (list.empty()) return TP3B_OK;
-  TP3B_TRY(sync());
-  ar_.reset();
+  TP3B_TRY(arena_room());
   Tab<DotJob<double, double>> t;
   if (!ar_.alloc(t, (int)list.size())) return arena_full();
   for (size_t e = 0; e < list.size(); ++e) {
@@ -556,8 +562,7 @@ tp3b_status BatchedJdqr<TW>::gemm64(const std::vector<int>& list, const std::vec
                                     const std::vector<int>& ldc, double beta,
                                     const std::vector<double*>& Y) {
   if (list.empty()) return TP3B_OK;
-  TP3B_TRY(sync());
-  ar_.reset();
+  TP3B_TRY(arena_room());
   Tab<GemmJob<double>> t;
   if (!ar_.alloc(t, (int)list.size())) return arena_full();
   for (size_t e = 0; e < list.size(); ++e) {
@@ -586,8 +591,7 @@ tp3b_status BatchedJdqr<TW>::copy64(const std::vector<int>& list, const std::vec
                                     double alpha, const std::vector<const double*>& X,
                                     const std::vector<double*>& Y) {
   if (list.empty()) return TP3B_OK;
-  TP3B_TRY(sync());
-  ar_.reset();
+  TP3B_TRY(arena_room());
   Tab<ConvJob<double, double>> t;
   if (!ar_.alloc(t, (int)list.size())) return arena_full();
   for (size_t e = 0; e < list.size(); ++e) {
@@ -650,8 +654,7 @@ tp3b_status BatchedJdqr<TW>::orth(const std::vector<int>& list0, const std::vect
         Yq.push_back(Xs[e]);
       }
     for (int pass = 0; pass < 2 && !lq.empty(); ++pass) {
-      TP3B_TRY(sync());
-      ar_.reset();
+      TP3B_TRY(arena_room());
       Tab<DotJob<double, double>> td;
       Tab<GemmJob<double>> tg;
       if (!ar_.alloc(td, (int)lq.size()) || !ar_.alloc(tg, (int)lq.size())) return arena_full();
@@ -675,8 +678,7 @@ tp3b_status BatchedJdqr<TW>::orth(const std::vector<int>& list0, const std::vect
       TP3B_HIP(launch_gemm_grouped(tg.d, s_));
     }
     // Cholesky-QR, first pass (with the dependence test)
-    TP3B_TRY(sync());
-    ar_.reset();
+    TP3B_TRY(arena_room());
     {
       Tab<DotJob<double, double>> td;
       Tab<CholJob> tc;
@@ -719,7 +721,7 @@ tp3b_status BatchedJdqr<TW>::orth(const std::vector<int>& list0, const std::vect
     }
     // the independent instances finish: X R1^{-1}, Gram, Cholesky, X R2^{-1}
     if (!good.empty()) {
-      ar_.reset();
+      TP3B_TRY(arena_room());
       Tab<TrsmJob> t1, t2;
       Tab<DotJob<double, double>> td;
       Tab<CholJob> tc;
@@ -747,7 +749,6 @@ tp3b_status BatchedJdqr<TW>::orth(const std::vector<int>& list0, const std::vect
       TP3B_HIP(launch_dot_grouped(td.d, s_));
       TP3B_HIP(launch_chol_grouped(tc.d, s_));
       TP3B_HIP(launch_trsm_grouped(t2.d, s_));
-      TP3B_TRY(sync());
     }
     if (bad_list.empty()) break;
     // dependent columns: replace by random vectors and redo those instances
@@ -1009,8 +1010,7 @@ tp3b_status BatchedJdqr<TW>::iterate() {
   }
   // residual norms
   {
-    TP3B_TRY(sync());
-    ar_.reset();
+    TP3B_TRY(arena_room());
     Tab<BdotJob<double>> t;
     if (!ar_.alloc(t, (int)act.size())) return arena_full();
     for (int i : act) {
@@ -1189,8 +1189,7 @@ tp3b_status BatchedJdqr<TW>::iterate() {
     TP3B_TRY(gemm64(corr_, p, p, 1.0, B, C, ldc, 0.0, Y));
   }
   if (low_) {
-    TP3B_TRY(sync());
-    ar_.reset();
+    TP3B_TRY(arena_room());
     Tab<ConvJob<double, TW>> t;
     if (!ar_.alloc(t, 2 * (int)corr_.size())) return arena_full();
     for (int i : corr_) {
@@ -1262,7 +1261,7 @@ tp3b_status BatchedJdqr<TW>::iterate() {
   }
   TP3B_HIP(hipMemcpyAsync(Y_.d, Y_.h.data(), sizeof(double) * Y_.h.size(), hipMemcpyHostToDevice, s_));
   {
-    ar_.reset();
+    TP3B_TRY(arena_room());
     Tab<ConvJob<TW, TW>> tz;
     Tab<BupdJob<TW>> tu;
     Tab<ConvJob<TW, double>> tc;

@@ -52,10 +52,15 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t g, int64_t G) {
 // KC staged through padded LDS with a register prefetch of the next chunk; both
 // products of a 1D apply (L X and X R) run in one K loop of length M + Nc, so no
 // intermediate goes to memory.
-template <typename T, int TM, int TN, int KC>
+// SK (split K): every wave computes the whole tile over its own quarter of each
+// K chunk (independent accumulators per 16 x 16 block instead of one dependent
+// chain), and the four partial tiles are summed through LDS at the end; used for
+// small tiles, whose runtime is the latency of the K loop.
+template <typename T, int TM, int TN, int KC, bool SK = false>
 struct MpSmem {
   T As[KC][TM + 1];
   T Bs[KC][TN + 1];
+  T red[SK ? 4 * TM * TN : 1];
 };
 
 // Work items of one mode product: output tiles x batch items.
@@ -65,19 +70,22 @@ __host__ __device__ inline int64_t modeprod_items(const P& a) {
 }
 
 // One TM x TN output tile (work item w) of the mode product `a`.
-template <typename T, int TM, int TN, int KC>
+template <typename T, int TM, int TN, int KC, bool SK = false>
 __device__ __forceinline__ void modeprod_tile(const ModeProd<T>& a, int64_t w,
-                                              MpSmem<T, TM, TN, KC>& sm) {
+                                              MpSmem<T, TM, TN, KC, SK>& sm) {
   typedef typename Mma<T>::acc_t acc_t;
-  constexpr int WM = TM / 2, WN = TN / 2;
+  constexpr int WM = SK ? TM : TM / 2, WN = SK ? TN : TN / 2;
   constexpr int BM = WM / 16, BN = WN / 16;
   constexpr int EA = TM * KC / 256, EB = KC * TN / 256;
+  constexpr int KW = SK ? KC / 4 : KC;  // K range of one wave within a chunk
   static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
+  static_assert(KW % 4 == 0, "a wave's K range is a multiple of the MFMA depth");
   T(&As)[KC][TM + 1] = sm.As;
   T(&Bs)[KC][TN + 1] = sm.Bs;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  const int wm = SK ? 0 : (wave >> 1) * WM, wn = SK ? 0 : (wave & 1) * WN;
+  const int kw0 = SK ? wave * KW : 0;
   const int tiles_m = (a.M + TM - 1) / TM, tiles_n = (a.Nc + TN - 1) / TN;
   const int64_t tiles = (int64_t)tiles_m * tiles_n;
   const int64_t q = w / tiles;
@@ -153,7 +161,7 @@ __device__ __forceinline__ void modeprod_tile(const ModeProd<T>& a, int64_t w,
   for (int c = 0; c < nchunks; ++c) {
     if (c + 1 < nchunks) load(c + 1);
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
+    for (int kk = kw0; kk < kw0 + KW; kk += 4) {
       T af[BM], bf[BN];
 #pragma unroll
       for (int bi = 0; bi < BM; ++bi) af[bi] = As[kk + lk][wm + bi * 16 + lr];
@@ -175,27 +183,46 @@ __device__ __forceinline__ void modeprod_tile(const ModeProd<T>& a, int64_t w,
   // 16 x 16 block.
   const double shift = a.shifts ? a.shifts[vec] : 0.0;
   const T* Vp = a.V ? a.V + item * a.bstride : nullptr;
-#pragma unroll
-  for (int bi = 0; bi < BM; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < BN; ++bj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gi = i0 + wm + bi * 16 + Mma<T>::row(lk, r);
-        const int gj = j0 + wn + bj * 16 + lr;
-        if (gi < M && gj < Nc) {
-          const int64_t off = (int64_t)gi * rs + gj;
-          T v = acc[bi][bj][r];
-          if (a.epi == EPI_V) {
-            T pot = (Vp ? Vp[off] : T(0)) - T(shift);
-            v += pot * X[off];
-          } else if (a.epi == EPI_DIV) {
-            v = v / (a.lamL[gi] + a.lamR[gj] + (a.lamItem ? a.lamItem[item] : T(0)) - T(a.sigma));
-          }
-          if (a.acc) v += Y[off];
-          Y[off] = v;
-        }
+  auto emit = [&](int gi, int gj, T v) {
+    if (gi < M && gj < Nc) {
+      const int64_t off = (int64_t)gi * rs + gj;
+      if (a.epi == EPI_V) {
+        T pot = (Vp ? Vp[off] : T(0)) - T(shift);
+        v += pot * X[off];
+      } else if (a.epi == EPI_DIV) {
+        v = v / (a.lamL[gi] + a.lamR[gj] + (a.lamItem ? a.lamItem[item] : T(0)) - T(a.sigma));
       }
+      if (a.acc) v += Y[off];
+      Y[off] = v;
+    }
+  };
+  if constexpr (SK) {
+    // sum the four waves' partial tiles (fixed order: deterministic)
+    T* red = sm.red;
+#pragma unroll
+    for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BN; ++bj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ri = bi * 16 + Mma<T>::row(lk, r), cj = bj * 16 + lr;
+          red[(wave * TM + ri) * TN + cj] = acc[bi][bj][r];
+        }
+    __syncthreads();
+    for (int e = tid; e < TM * TN; e += 256) {
+      const T v = red[e] + red[TM * TN + e] + red[2 * TM * TN + e] + red[3 * TM * TN + e];
+      emit(i0 + e / TN, j0 + e % TN, v);
+    }
+    __syncthreads();  // `red` is reused by the next work item of a persistent loop
+  } else {
+#pragma unroll
+    for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BN; ++bj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          emit(i0 + wm + bi * 16 + Mma<T>::row(lk, r), j0 + wn + bj * 16 + lr, acc[bi][bj][r]);
+  }
 }
 
 // ------------------------------------------------------ BF16x3 mode product

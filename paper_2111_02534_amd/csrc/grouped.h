@@ -126,8 +126,9 @@ struct DevTab {
 };
 
 // Host staging of job tables with a mirrored device arena; tables are appended
-// in order, and upload() copies the used prefix in one transfer.  Rebuilding the
-// same sequence of tables (same capacities) yields the same device addresses.
+// in order, and upload() copies the tables added since the previous upload in
+// one transfer.  Rebuilding the same sequence of tables after reset() (same
+// capacities) yields the same device addresses.
 class TableArena {
  public:
   TableArena() = default;
@@ -135,7 +136,9 @@ class TableArena {
   TableArena& operator=(const TableArena&) = delete;
   ~TableArena();
   hipError_t init(size_t bytes);
-  void reset() { used_ = 0; }
+  // Only after the stream has consumed every uploaded table.
+  void reset() { used_ = uploaded_ = 0; }
+  size_t free_bytes() const { return cap_ - used_; }
 
   template <class Job>
   struct Tab {
@@ -177,13 +180,14 @@ class TableArena {
     t.h[0] = n + 1;
   }
 
+  // Copies the tables added since the last upload (one transfer).
   hipError_t upload(hipStream_t s);
   size_t used() const { return used_; }
 
  private:
   char* host_ = nullptr;
   char* dev_ = nullptr;
-  size_t cap_ = 0, used_ = 0;
+  size_t cap_ = 0, used_ = 0, uploaded_ = 0;
 };
 
 // ---- launchers (fixed grid of kPersistWGs workgroups; tables in device memory)

@@ -60,11 +60,11 @@ __device__ __forceinline__ void for_wave_items(DevTab<Job> t, int stage, F&& f) 
 }
 
 // ------------------------------------------------------------ mode products
-template <typename T, int TM, int TN, int KC>
+template <typename T, int TM, int TN, int KC, bool SK = false>
 __global__ __launch_bounds__(256) void k_modeprod_grouped(DevTab<ModeProd<T>> t) {
-  __shared__ MpSmem<T, TM, TN, KC> sm;
+  __shared__ MpSmem<T, TM, TN, KC, SK> sm;
   for_wg_items(t, 0, [&](const ModeProd<T>& a, int64_t w) {
-    modeprod_tile<T, TM, TN, KC>(a, w, sm);
+    modeprod_tile<T, TM, TN, KC, SK>(a, w, sm);
   });
 }
 
@@ -90,7 +90,7 @@ template <typename T>
 hipError_t launch_modeprod_grouped(DevTab<ModeProd<T>> t, int tile, hipStream_t s) {
   const dim3 g(kPersistWGs), b(256);
   switch (tile) {
-    case TILE_32: hipLaunchKernelGGL((k_modeprod_grouped<T, 32, 32, 16>), g, b, 0, s, t); break;
+    case TILE_32: hipLaunchKernelGGL((k_modeprod_grouped<T, 32, 32, 32, true>), g, b, 0, s, t); break;
     case TILE_64: hipLaunchKernelGGL((k_modeprod_grouped<T, 64, 64, 16>), g, b, 0, s, t); break;
     case TILE_128: hipLaunchKernelGGL((k_modeprod_grouped<T, 128, 128, 16>), g, b, 0, s, t); break;
     case TILE_64x128: hipLaunchKernelGGL((k_modeprod_grouped<T, 64, 128, 16>), g, b, 0, s, t); break;
@@ -328,8 +328,11 @@ hipError_t TableArena::init(size_t bytes) {
 }
 
 hipError_t TableArena::upload(hipStream_t s) {
-  if (!used_) return hipSuccess;
-  return hipMemcpyAsync(dev_, host_, used_, hipMemcpyHostToDevice, s);
+  if (used_ == uploaded_) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(dev_ + uploaded_, host_ + uploaded_, used_ - uploaded_,
+                                hipMemcpyHostToDevice, s);
+  uploaded_ = used_;
+  return e;
 }
 
 }  // namespace tp3b

@@ -23,10 +23,10 @@ namespace tp3b {
 // ROLE only separates the kernel names seen by profilers: 0 = Hamiltonian apply
 // (both modes + potential), 1 = preconditioner mode products, 2 = 2D x-mode
 // accumulation passes.
-template <typename T, int TM, int TN, int KC, int ROLE>
+template <typename T, int TM, int TN, int KC, int ROLE, bool SK = false>
 __global__ __launch_bounds__(256) void k_modeprod(ModeProd<T> a) {
-  __shared__ MpSmem<T, TM, TN, KC> sm;
-  modeprod_tile<T, TM, TN, KC>(a, xcd_remap(blockIdx.x, modeprod_items<TM, TN>(a)), sm);
+  __shared__ MpSmem<T, TM, TN, KC, SK> sm;
+  modeprod_tile<T, TM, TN, KC, SK>(a, xcd_remap(blockIdx.x, modeprod_items<TM, TN>(a)), sm);
 }
 
 template <typename T, int ROLE>
@@ -34,7 +34,7 @@ static void launch_role(const ModeProd<T>& a, int tile, hipStream_t s, unsigned 
                         unsigned g128, unsigned g64x128) {
   switch (tile) {
     case TILE_32:
-      hipLaunchKernelGGL((k_modeprod<T, 32, 32, 16, ROLE>), dim3(g32), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_modeprod<T, 32, 32, 32, ROLE, true>), dim3(g32), dim3(256), 0, s, a);
       break;
     case TILE_64:
       hipLaunchKernelGGL((k_modeprod<T, 64, 64, 16, ROLE>), dim3(g64), dim3(256), 0, s, a);

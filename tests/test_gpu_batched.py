@@ -194,8 +194,17 @@ def test_jdqr_c4_full_batch(inner):
     t0 = time.time()
     r = t3.jdqr_batched(ops, 4, 4, inner_prec=pk, seed=1000, tol=C4_TOL)
     dt = time.time() - t0
-    err = np.max(np.abs(r.evals - gold[:, 5:9]) / np.abs(gold[:, 5:9]))
-    say("c4", inner, f"{dt:.2f} s", "max rel err", err, "outer max", r.n_outer.max(),
+    ref = gold[:, 5:9]
+    diff = np.abs(r.evals - ref)
+    # eigenvalues near zero (states at the continuum threshold, down to |E| ~ 6e-4
+    # here) carry an absolute FP64 floor of ~eps ||H||, so the bar is relative
+    # to max(|E|, 1), as the residual test is; plain relative error for |E| >= 0.01
+    err = np.max(diff / np.maximum(np.abs(ref), 1.0))
+    big = np.abs(ref) >= 0.01
+    err_rel = np.max(diff[big] / np.abs(ref[big]))
+    say("c4", inner, f"{dt:.2f} s", "max err (rel. to max(|E|,1))", err,
+        "max rel err (|E| >= 0.01)", err_rel, "outer max", r.n_outer.max(),
         "mean", r.n_outer.mean())
     assert np.all(r.n_conv == 4)
     assert err <= 1e-10
+    assert err_rel <= 1e-10
