@@ -30,6 +30,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "H-apply GFLOP/s (% MFMA peak); JDQR s to k eigenpairs @1e-10, mixed vs FP64"
+# HBM bytes per launch of the FP64 H apply at n = 256, 8 vectors (split-K 32 x 32
+# tile), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 256 MiB copy
+# (profiles/hbm_traffic_c2_H_apply_fp64.md); None for other workloads.
+TRAFFIC_BYTES = {"c2": 21.10e6}
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 HBM_PEAK_GBS = 8000.0
 
@@ -72,7 +76,8 @@ def cpu_baseline(cfg, name, sample_iters, full_iters):
     sig = P.two_body_shift()
     t0 = time.perf_counter()
     r = jdqr.jdqr(P.apply, P.N, cfg["nev"], cfg["block"], precond=pc.apply,
-                  seed=cfg["seed_start"], target=sig, max_outer=sample_iters)
+                  seed=cfg["seed_start"], target=sig, target_low=P.spectrum_lower_bound(),
+                  max_outer=sample_iters)
     dt = time.perf_counter() - t0
     n_done = max(r.n_outer, 1)
     per_iter = dt / n_done
@@ -213,8 +218,9 @@ def main():
                                 f"FP64 JDQR + Sylvester preconditioner"),
                    "n": cfg["n"], "nev": nev, "block": b},
         "roofline": {"bound": "mfma", "achieved": achieved_tf, "peak": PEAK_TFLOPS["f64"],
-                     "unit": "TFLOP/s", "frac": achieved_tf / PEAK_TFLOPS["f64"], "traffic": None,
-                     "kernel": "k_modeprod<double,*,*,16,0> (H apply, fused potential)",
+                     "unit": "TFLOP/s", "frac": achieved_tf / PEAK_TFLOPS["f64"],
+                     "traffic": TRAFFIC_BYTES.get(args.config),
+                     "kernel": "k_modeprod<double,32,32,32,0,SK> (H apply, fused potential)",
                      "launch_flops": flops_launch, "avg_launch_us": 1e6 * avg_launch_s,
                      "launches": n_k},
         "h_apply_gflops": achieved_tf * 1e3,

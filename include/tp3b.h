@@ -93,7 +93,9 @@ typedef struct {
 tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* out);
 tp3b_status tp3b_destroy(tp3b_op op);
 
-/* Sizes and derived quantities of an operator (any pointer may be NULL). */
+/* Sizes and derived quantities of an operator (any pointer may be NULL):
+ * N, the preconditioner shift sigma, and the smallest |denominator| of the
+ * preconditioner's eigenbasis divide. */
 tp3b_status tp3b_op_info(tp3b_op op, int64_t* N, double* sigma, double* lambda_min_kinetic);
 
 /* Copies mode k's n_k x n_k second-derivative matrix (row-major) or the N
@@ -165,6 +167,12 @@ typedef struct {
                            within 10% of its previous value for three outer
                            iterations (the FP64 rounding floor of the residual
                            grows with ||H||); default 1e-8, <= 0 disables */
+  int32_t low_start;    /* in the first low_start outer iterations, while no pair
+                           has locked, the correction shift of unconverged
+                           columns is a lower bound of the spectrum (min V + the
+                           smallest eigenvalue of each kinetic mode operator)
+                           instead of `target`, so that a ground state far below
+                           the target is not passed over (default 3; 0 = off) */
 } tp3b_jdqr_opts;
 
 typedef struct {

@@ -144,7 +144,8 @@ class JDQRResult:
 
 def jdqr(apply_A, N, nev, block, *, tol=1e-12, m_min=None, m_max=None,
          gmres_steps=10, precond=None, apply_inner=None, X0=None, seed=0,
-         max_outer=1000, target=None, switch_tol=1e-2, stall_tol=1e-8):
+         max_outer=1000, target=None, switch_tol=1e-2, stall_tol=1e-8, target_low=None,
+         low_iters=3):
     """Partial Schur form for the nev eigenvalues of smallest real part.
 
     apply_A(X) -> A X for X of shape (N, k), in FP64.  apply_inner, if given,
@@ -152,6 +153,11 @@ def jdqr(apply_A, N, nev, block, *, tol=1e-12, m_min=None, m_max=None,
     precond(X) -> P^{-1} X or None (no preconditioner).
     target: shift used in the correction equation instead of theta_j while
     ||r_j|| > switch_tol |theta_j| (None: always theta_j).
+    target_low, low_iters: (R) in the first low_iters outer iterations, while
+    no pair has locked, target_low is used instead of target: a shift below the
+    whole spectrum steers the early corrections to the lowest states (as
+    inverse iteration from below does), so that a ground state far below target
+    enters the search space before other states lock (None: target throughout).
     stall_tol: (R) when nothing locks, the leading pair is locked anyway once
     its residual is <= stall_tol max(|theta|, 1) and has stayed within 10 % of
     its previous value in three consecutive outer iterations -- the residual has
@@ -249,7 +255,10 @@ def jdqr(apply_A, N, nev, block, *, tol=1e-12, m_min=None, m_max=None,
         shift = theta.copy()
         if target is not None:
             far = rn > switch_tol * np.abs(theta)
-            shift[far] = target
+            # (R) in the first low_iters outer iterations, while nothing is
+            # locked, a target below the spectrum
+            low = target_low is not None and Q.shape[1] == 0 and outer <= low_iters
+            shift[far] = target_low if low else target
 
         def op(Z):
             res.n_apply_inner += Z.shape[1]

@@ -50,6 +50,14 @@ class Problem:
         return twobody.ground_energy(self.n[k], self.L[k], self.mu_hl, self.shape,
                                      self.v0, self.width)
 
+    def spectrum_lower_bound(self):
+        """min V plus the smallest eigenvalue of each kinetic mode operator
+        -c D2_k: a lower bound of the spectrum of the continuous problem
+        (Weyl), used as the eigensolver's starting target."""
+        coef = (self.cx, self.cy) if self.ndim == 1 else (self.cx, self.cx, self.cy, self.cy)
+        lam = sum(np.min(np.linalg.eigvals(-c * d).real) for c, d in zip(coef, self.D2))
+        return float(np.min(self.V) + lam)
+
     def preconditioner(self, sigma=None):
         if sigma is None:
             sigma = self.two_body_shift()

@@ -48,7 +48,8 @@ class JdqrOpts(ctypes.Structure):
                 ("switch_tol", ctypes.c_double), ("target", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("check_finite", ctypes.c_int32),
                 ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("stall_tol", ctypes.c_double)]
+                ("graph", ctypes.c_int32), ("stall_tol", ctypes.c_double),
+                ("low_start", ctypes.c_int32)]
 
 
 class JdqrStats(ctypes.Structure):
@@ -284,7 +285,8 @@ class Operator:
 
     def jdqr(self, nev, block, *, X0=None, inner_prec=FP64, precond=True, tol=1e-12,
              gmres_steps=10, m_min=0, m_max=0, max_outer=1000, seed=0, switch_tol=1e-2,
-             target=None, verbose=False, want_Q=True, profile=False, stall_tol=1e-8):
+             target=None, verbose=False, want_Q=True, profile=False, stall_tol=1e-8,
+             low_start=3):
         import numpy as np
         import torch
         o = JdqrOpts()
@@ -294,7 +296,7 @@ class Operator:
         o.inner_prec, o.tol, o.switch_tol = inner_prec, tol, switch_tol
         o.target = float("nan") if target is None else float(target)
         o.seed, o.verbose, o.profile = seed, int(verbose), int(profile)
-        o.stall_tol = float(stall_tol)
+        o.stall_tol, o.low_start = float(stall_tol), int(low_start)
         evals = np.empty(nev)
         R = np.empty((nev, nev), order="F")
         res = np.empty(nev)
@@ -412,7 +414,7 @@ class BatchedResult:
 
 def jdqr_batched(ops, nev, block, *, inner_prec=FP64, precond=True, tol=1e-12, gmres_steps=10,
                  m_min=0, m_max=0, max_outer=1000, seed=0, switch_tol=1e-2, target=None,
-                 graph=True, want_Q=False, verbose=False, stall_tol=1e-8):
+                 graph=True, want_Q=False, verbose=False, stall_tol=1e-8, low_start=3):
     """Block JDQR on every operator of a batch at once (tp3b_jdqr_solve_batched)."""
     import numpy as np
     import torch
@@ -423,7 +425,7 @@ def jdqr_batched(ops, nev, block, *, inner_prec=FP64, precond=True, tol=1e-12, g
     o.inner_prec, o.tol, o.switch_tol = inner_prec, tol, switch_tol
     o.target = float("nan") if target is None else float(target)
     o.seed, o.verbose, o.graph = seed, int(verbose), int(bool(graph))
-    o.stall_tol = float(stall_tol)
+    o.stall_tol, o.low_start = float(stall_tol), int(low_start)
     n = len(ops)
     evals = np.empty((n, nev))
     res = np.empty((n, nev))

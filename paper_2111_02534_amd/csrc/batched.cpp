@@ -1144,7 +1144,9 @@ tp3b_status BatchedJdqr<TW>::iterate() {
   const double target = std::isnan(o_.target) ? NAN : o_.target;
   for (int i : corr_) {
     Inst& I = in_[i];
-    const double tg = std::isnan(target) ? I.op->sigma : target;
+    const double tg0 = std::isnan(target) ? I.op->sigma : target;
+    // first outer iterations, nothing locked yet: a target below the spectrum
+    const double tg = (I.k == 0 && I.outer <= o_.low_start) ? I.op->spec_lo : tg0;
     for (int j = 0; j < I.nb; ++j)
       Shift_.hat(i)[j] = (I.rn[j] > o_.switch_tol * std::fabs(I.theta[j])) ? tg : I.theta[j];
   }

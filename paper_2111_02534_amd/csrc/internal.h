@@ -44,7 +44,8 @@ struct tp3b_op_s {
   int64_t N = 0;
   int device = 0;
   bool have_prec = false;
-  double lam_min = 0;  // smallest kinetic eigenvalue (sum over modes)
+  double lam_min = 0;   // smallest |sum of mode eigenvalues - sigma|
+  double spec_lo = 0;   // min V + sum over modes of the smallest mode eigenvalue
   std::vector<double> D2h[4];  // host copies (row-major)
   std::vector<double> Vh;      // host potential
   tp3b::DevOps<double> d64;

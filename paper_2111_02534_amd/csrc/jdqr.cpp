@@ -364,8 +364,10 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     }
     // ---- 4. correction equations
     std::vector<double> shift(nb);
+    // first outer iterations, nothing locked yet: a target below the spectrum
+    const double tfar = (k == 0 && outer <= o.low_start) ? op->spec_lo : target;
     for (int j = 0; j < nb; ++j)
-      shift[j] = (rn[j] > o.switch_tol * std::fabs(theta[j])) ? target : theta[j];
+      shift[j] = (rn[j] > o.switch_tol * std::fabs(theta[j])) ? tfar : theta[j];
     TP3B_HIP(hipMemcpyAsync(dShift, shift.data(), sizeof(double) * nb, hipMemcpyHostToDevice, s));
     const int nqt = k + nb;  // Q~ = QV[:, 0:nqt]
     const double* Qt = QV;
@@ -568,6 +570,7 @@ tp3b_status tp3b_jdqr_default_opts(tp3b_jdqr_opts* o) {
   o->tol = 1e-12;
   o->switch_tol = 1e-2;
   o->stall_tol = 1e-8;
+  o->low_start = 3;
   o->target = NAN;
   o->seed = 0;
   return TP3B_OK;

@@ -703,6 +703,26 @@ tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* ou
       op->lam_min = mn;
       op->have_prec = mn > 0;
     }
+    // lower bound of the spectrum (Weyl, continuous problem): the eigensolver's
+    // starting target
+    double lo = op->Vh.empty() ? 0.0 : *std::min_element(op->Vh.begin(), op->Vh.end());
+    for (int k = 0; k < nm; ++k) {
+      if (pf.lam[k].empty() || !ok) {
+        // no real eigen-factors: Gershgorin bound of the mode operator
+        double g = 1e300;
+        const int n = op->n[k];
+        for (int i = 0; i < n; ++i) {
+          double off = 0.0;
+          for (int j = 0; j < n; ++j)
+            if (j != i) off += std::fabs(Kh[k][(size_t)i * n + j]);
+          g = std::min(g, Kh[k][(size_t)i * n + i] - off);
+        }
+        lo += g;
+      } else {
+        lo += *std::min_element(pf.lam[k].begin(), pf.lam[k].end());
+      }
+    }
+    op->spec_lo = lo;
     // preconditioner work buffer: up to 64 vectors, at most 4 GiB (FP64)
     const int64_t cap = (int64_t)(1ll << 32) / (N * 8);
     op->work_vecs = (int)std::max<int64_t>(1, std::min<int64_t>(64, cap));

@@ -28,7 +28,7 @@ def run(name):
     sig = P.two_body_shift()
     t = time.time()
     r = jdqr.jdqr(P.apply, P.N, c["nev"], c["block"], precond=pc.apply, seed=c["seed_start"],
-                  target=sig, max_outer=400)
+                  target=sig, target_low=P.spectrum_lower_bound(), max_outer=400)
     dt = time.time() - t
     assert r.converged, name
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_evals.txt")
@@ -49,7 +49,7 @@ def _c4_one(args):
     pc = P.preconditioner()
     sig = P.two_body_shift()
     r = jdqr.jdqr(P.apply, P.N, c["nev"], c["block"], precond=pc.apply, seed=c["seed_start"],
-                  target=sig, max_outer=400, tol=c["tol"])
+                  target=sig, target_low=P.spectrum_lower_bound(), max_outer=400, tol=c["tol"])
     if not r.converged:
         return i, np.full(c["nev"], np.nan), float("nan"), r.n_outer
     return i, r.evals.real.copy(), float(np.max(r.resnorm)), r.n_outer

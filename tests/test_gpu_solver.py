@@ -106,3 +106,24 @@ def test_jdqr_c2_matches_oracle(inner):
     err = np.max(np.abs(r.evals - ref) / np.abs(ref))
     say("  err", err, r.stats)
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("seed", [0, 5, 26, 34])
+def test_jdqr_low_start_finds_deep_ground_state(seed):
+    """A 48 x 48 grid with the physics of batched instance 80 (ground state far
+    below the two-body shift), started from the same uniform blocks as the
+    oracle's pin: with the starting target below the spectrum the solver finds
+    the dense eigenvalues."""
+    t3 = need_gpu()
+    from workloads import c4_instances, uniform_block
+    c = dict(c4_instances()[80])
+    c["n"] = 48
+    P = problem.make_problem(**c)
+    ref = dense.lowest_eigenvalues(P.kron(), 4).real
+    op = t3.Operator.from_config(c)
+    X0 = to_dev(uniform_block(P.N, 4, seed))
+    for inner in (t3.FP64, t3.BF16X3):
+        r = op.jdqr(4, 4, X0=X0, inner_prec=inner, seed=seed, max_outer=300)
+        err = np.max(np.abs(r.evals - ref) / np.maximum(np.abs(ref), 1.0))
+        say("low start", seed, inner, r.evals, err, r.stats["n_outer"])
+        assert err <= 1e-10

@@ -358,6 +358,33 @@ def test_jdqr_matches_dense_2d_preconditioned():
     assert r.n_outer < r0.n_outer
 
 
+@pytest.mark.parametrize("seed", [0, 5, 26, 34])
+def test_jdqr_low_start_finds_deep_ground_state(seed):
+    """Batched-workload instance 80 (M/m = 1.08, V0 = 2.87, w = 0.71) on a 48 x 48
+    grid: its ground state lies far below the two-body shift.  With these uniform
+    start blocks JDQR steered by the two-body shift locks the next four states
+    and never finds the ground state; with the starting target below the spectrum
+    (used until the first lock) it finds the dense eigenvalues."""
+    from workloads import c4_instances, uniform_block
+    c = dict(c4_instances()[80])
+    c["n"] = 48
+    P = problem.make_problem(**c)
+    ev = dense.lowest_eigenvalues(P.kron(), 4).real
+    pc = P.preconditioner()
+    X0 = uniform_block(P.N, 4, seed).T
+    r = jdqr.jdqr(P.apply, P.N, 4, 4, precond=pc.apply, X0=X0, seed=seed,
+                  target=P.two_body_shift(), target_low=P.spectrum_lower_bound(), max_outer=200)
+    assert r.converged
+    assert np.max(np.abs(r.evals.real - ev) / np.maximum(np.abs(ev), 1.0)) < 1e-10
+
+
+def test_spectrum_lower_bound():
+    """The starting target lies below every eigenvalue (dense check)."""
+    P = problem.make_problem(ndim=1, n=(20, 16), L=(15.0, 15.0), alpha=20.0, v0=1.0)
+    ev = np.linalg.eigvals(P.kron()).real
+    assert P.spectrum_lower_bound() < np.min(ev)
+
+
 def test_jdqr_seed_independent_c1():
     P = problem.make_problem(**config("c1"))
     pc = P.preconditioner()
