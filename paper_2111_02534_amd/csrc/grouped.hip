@@ -90,7 +90,7 @@ template <typename T>
 hipError_t launch_modeprod_grouped(DevTab<ModeProd<T>> t, int tile, hipStream_t s) {
   const dim3 g(kPersistWGs), b(256);
   switch (tile) {
-    case TILE_32: hipLaunchKernelGGL((k_modeprod_grouped<T, 32, 32, 32, true>), g, b, 0, s, t); break;
+    case TILE_32: hipLaunchKernelGGL((k_modeprod_grouped<T, 32, 32, 64, true>), g, b, 0, s, t); break;
     case TILE_64: hipLaunchKernelGGL((k_modeprod_grouped<T, 64, 64, 16>), g, b, 0, s, t); break;
     case TILE_128: hipLaunchKernelGGL((k_modeprod_grouped<T, 128, 128, 16>), g, b, 0, s, t); break;
     case TILE_64x128: hipLaunchKernelGGL((k_modeprod_grouped<T, 64, 128, 16>), g, b, 0, s, t); break;

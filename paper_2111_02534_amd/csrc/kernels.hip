@@ -34,7 +34,7 @@ static void launch_role(const ModeProd<T>& a, int tile, hipStream_t s, unsigned 
                         unsigned g128, unsigned g64x128) {
   switch (tile) {
     case TILE_32:
-      hipLaunchKernelGGL((k_modeprod<T, 32, 32, 32, ROLE, true>), dim3(g32), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_modeprod<T, 32, 32, 64, ROLE, true>), dim3(g32), dim3(256), 0, s, a);
       break;
     case TILE_64:
       hipLaunchKernelGGL((k_modeprod<T, 64, 64, 16, ROLE>), dim3(g64), dim3(256), 0, s, a);
