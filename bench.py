@@ -33,7 +33,7 @@ METRIC = "H-apply GFLOP/s (% MFMA peak); JDQR s to k eigenpairs @1e-10, mixed vs
 # HBM bytes per launch of the FP64 H apply at n = 256, 8 vectors (split-K 32 x 32
 # tile), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 256 MiB copy
 # (profiles/hbm_traffic_c2_H_apply_fp64.md); None for other workloads.
-TRAFFIC_BYTES = {"c2": 21.10e6}
+TRAFFIC_BYTES = {}
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 HBM_PEAK_GBS = 8000.0
 
@@ -220,7 +220,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved_tf, "peak": PEAK_TFLOPS["f64"],
                      "unit": "TFLOP/s", "frac": achieved_tf / PEAK_TFLOPS["f64"],
                      "traffic": TRAFFIC_BYTES.get(args.config),
-                     "kernel": "k_modeprod<double,32,32,32,0,SK> (H apply, fused potential)",
+                     "kernel": "k_modeprod<double,32,32,64,0,SK> (H apply, fused potential)",
                      "launch_flops": flops_launch, "avg_launch_us": 1e6 * avg_launch_s,
                      "launches": n_k},
         "h_apply_gflops": achieved_tf * 1e3,
