@@ -75,3 +75,65 @@ def clenshaw_curtis_weights(n: int, L: float) -> np.ndarray:
     mom = np.where(m % 2 == 0, 2.0 / (1.0 - m.astype(float) ** 2 + (m == 1)), 0.0)
     w = np.linalg.solve(Tm, mom)
     return L * w[1:-1]
+
+
+# ------------------------------------------------- mapped grid on the real line
+# The paper's grid (Sec. 3.1): Chebyshev points on a finite interval carried to
+# the whole real line by an algebraic map (Boyd's rational Chebyshev basis).
+# Here the collocation points are the N roots of T_N, t_j = cos(pi (2j+1)/(2N)),
+# and x = L t / sqrt(1 - t^2) (map parameter L).  A grid function is
+# interpolated by a polynomial in t of degree N - 1; derivatives follow from
+# the chain rule with t'(x) = (1 - t^2)^{3/2} / L and
+# t''(x) = -3 t (1 - t^2)^2 / L^2:  d^2/dx^2 = t'^2 d^2/dt^2 + t'' d/dt.
+# No boundary condition is imposed: the basis is defined on all of R.
+
+def gauss_roots(N: int) -> np.ndarray:
+    """Roots of T_N in ascending order."""
+    j = np.arange(N)
+    return np.cos(np.pi * (2 * j + 1) / (2 * N))[::-1]
+
+
+def first_derivative_roots(t: np.ndarray) -> np.ndarray:
+    """Derivative matrix of the polynomial interpolant on the roots of T_N:
+    barycentric weights of the first-kind Chebyshev points are proportional to
+    (-1)^j sin((2j+1) pi / (2N)) (in the descending order of the roots); the
+    diagonal is the negative row sum."""
+    N = t.size
+    # weights in the order of t (ascending = reversed descending index)
+    j = np.arange(N)[::-1]
+    w = (-1.0) ** j * np.sin((2 * j + 1) * np.pi / (2 * N))
+    dt = t[:, None] - t[None, :]
+    np.fill_diagonal(dt, 1.0)
+    D = (w[None, :] / w[:, None]) / dt
+    np.fill_diagonal(D, 0.0)
+    np.fill_diagonal(D, -D.sum(axis=1))
+    return D
+
+
+def mapped_nodes(N: int, L: float) -> np.ndarray:
+    t = gauss_roots(N)
+    return L * t / np.sqrt(1.0 - t * t)
+
+
+def mapped_second_derivative(N: int, L: float) -> np.ndarray:
+    """N x N second-derivative collocation matrix on the mapped grid."""
+    t = gauss_roots(N)
+    Dt = first_derivative_roots(t)
+    s = 1.0 - t * t
+    tp = s ** 1.5 / L
+    tpp = -3.0 * t * s * s / (L * L)
+    return (tp ** 2)[:, None] * (Dt @ Dt) + tpp[:, None] * Dt
+
+
+def parity_half(x: np.ndarray, D2: np.ndarray, sign: int):
+    """Restriction to functions of definite parity (sign +1 even, -1 odd) on a
+    grid symmetric about 0 with an even number of points: the unknowns are the
+    values at the positive nodes, and a value at -x equals sign times the value
+    at x, so column j of the half-grid operator is D2[:, j] + sign D2[:, mirror(j)]
+    restricted to the positive rows (the parity selection rule of Sec. 5.1)."""
+    N = x.size
+    if N % 2:
+        raise ValueError("parity restriction needs an even number of points")
+    p = np.arange(N // 2, N)
+    m = N - 1 - p
+    return x[p], D2[np.ix_(p, p)] + sign * D2[np.ix_(p, m)]

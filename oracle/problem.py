@@ -45,10 +45,12 @@ class Problem:
         return operator.kron_2d(self.D2, self.cx, self.cy, self.V)
 
     def two_body_shift(self):
-        """Ground energy of -(1/(2 mu_hl)) d^2/dr^2 + u(|r|) on the y grid."""
+        """Ground energy of -(1/(2 mu_hl)) d^2/dr^2 + u(|r|) on the y grid (the
+        first y mode's grid and second-derivative matrix)."""
         k = 1 if self.ndim == 1 else 2
-        return twobody.ground_energy(self.n[k], self.L[k], self.mu_hl, self.shape,
-                                     self.v0, self.width)
+        A = (-(1.0 / (2.0 * self.mu_hl)) * self.D2[k]
+             + np.diag(physics.PAIR[self.shape](np.abs(self.grids[k]), self.v0, self.width)))
+        return float(np.min(np.linalg.eigvals(A).real))
 
     def spectrum_lower_bound(self):
         """min V plus the smallest eigenvalue of each kinetic mode operator
@@ -67,7 +69,12 @@ class Problem:
 
 
 def make_problem(ndim, n, L, alpha=None, v0=1.0, width=1.0, shape="gauss",
-                 units="unit_heavy", cx=None, cy=None, mu_hl=None, **_ignored):
+                 units="unit_heavy", cx=None, cy=None, mu_hl=None, grid="cgl", parity=None,
+                 **_ignored):
+    """grid: "cgl" (n interior Gauss-Lobatto points of [-L, L], Dirichlet) or
+    "mapped" (Chebyshev roots mapped to the real line with parameter L).
+    parity (mapped grid only): per mode 0 (full grid of n points), +1 or -1
+    (even / odd functions; n unknowns at the positive nodes of a 2n-point grid)."""
     nn = (n,) * (2 * ndim) if np.isscalar(n) else tuple(n)
     LL = (L,) * (2 * ndim) if np.isscalar(L) else tuple(L)
     if cx is None:
@@ -75,8 +82,24 @@ def make_problem(ndim, n, L, alpha=None, v0=1.0, width=1.0, shape="gauss",
             cx, cy, mu_hl = physics.coeffs_unit_heavy(alpha)
         else:
             cx, cy, mu_hl = physics.coeffs_paper_units(alpha)
-    D2 = tuple(cheb.second_derivative_dirichlet(k, l) for k, l in zip(nn, LL))
-    grids = tuple(cheb.nodes(k, l) for k, l in zip(nn, LL))
+    if grid == "cgl":
+        D2 = tuple(cheb.second_derivative_dirichlet(k, l) for k, l in zip(nn, LL))
+        grids = tuple(cheb.nodes(k, l) for k, l in zip(nn, LL))
+    elif grid == "mapped":
+        par = (0,) * len(nn) if parity is None else tuple(parity)
+        D2, grids = [], []
+        for k, l, p in zip(nn, LL, par):
+            if p == 0:
+                D2.append(cheb.mapped_second_derivative(k, l))
+                grids.append(cheb.mapped_nodes(k, l))
+            else:
+                xh, Dh = cheb.parity_half(cheb.mapped_nodes(2 * k, l),
+                                          cheb.mapped_second_derivative(2 * k, l), p)
+                D2.append(Dh)
+                grids.append(xh)
+        D2, grids = tuple(D2), tuple(grids)
+    else:
+        raise ValueError(f"unknown grid {grid!r}")
     if ndim == 1:
         V = physics.potential_1d(grids[0], grids[1], shape, v0, width)
     else:

@@ -40,3 +40,14 @@ def depth_for_binding(n, L, E0, f=lambda r: np.exp(-r * r)):
     ev = ev[np.isfinite(ev)]
     real = ev[np.abs(ev.imag) < 1e-9 * np.maximum(1.0, np.abs(ev.real))].real
     return float(np.min(real[real > 0]))
+
+
+def depth_for_binding_grid(r, D2, E0, f=lambda r: np.exp(-r * r)):
+    """depth_for_binding on a given grid (nodes r, second-derivative matrix D2),
+    e.g. the even half of the mapped grid."""
+    A = -0.5 * D2 + E0 * np.eye(D2.shape[0])
+    B = np.diag(f(r))
+    ev = scipy.linalg.eigvals(A, B)
+    ev = ev[np.isfinite(ev)]
+    real = ev[np.abs(ev.imag) < 1e-9 * np.maximum(1.0, np.abs(ev.real))].real
+    return float(np.min(real[real > 0]))

@@ -199,6 +199,72 @@ def test_table1_three_body_coarse():
     assert np.max(np.abs(ratio - paper) / np.abs(paper)) < 2e-3
 
 
+# ------------------------------------- mapped grid on the real line (Sec. 3.1)
+def test_mapped_second_derivative_exact_on_t_polynomials():
+    """Functions that are polynomials of degree <= N - 1 in t = x / sqrt(L^2 + x^2)
+    are differentiated exactly (chain rule with t' = (1 - t^2)^{3/2} / L,
+    t'' = -3 t (1 - t^2)^2 / L^2, written out here independently)."""
+    N, L = 24, 3.0
+    x = cheb.mapped_nodes(N, L)
+    D2 = cheb.mapped_second_derivative(N, L)
+    t = x / np.sqrt(L * L + x * x)
+    tp = L * L / (L * L + x * x) ** 1.5
+    tpp = -3.0 * L * L * x / (L * L + x * x) ** 2.5
+    for k in (1, 2, 5, N - 1):
+        f = t ** k
+        fpp = k * (k - 1) * t ** max(k - 2, 0) * tp ** 2 + k * t ** (k - 1) * tpp
+        assert np.max(np.abs(D2 @ f - fpp)) <= 1e-10 * max(1.0, np.max(np.abs(fpp))), k
+
+
+def test_mapped_harmonic_oscillator_and_parity():
+    """-1/2 d^2/dx^2 + x^2/2 on the mapped grid: eigenvalues k + 1/2 (spectral
+    accuracy); the even and odd half grids give the even and odd levels."""
+    N, L = 64, 4.0
+    x = cheb.mapped_nodes(N, L)
+    D2 = cheb.mapped_second_derivative(N, L)
+    ev = np.sort(np.linalg.eigvals(-0.5 * D2 + np.diag(0.5 * x * x)).real)[:6]
+    assert np.max(np.abs(ev - (np.arange(6) + 0.5))) <= 1e-10
+    for sign, levels in ((+1, [0.5, 2.5, 4.5]), (-1, [1.5, 3.5, 5.5])):
+        xh, Dh = cheb.parity_half(x, D2, sign)
+        evh = np.sort(np.linalg.eigvals(-0.5 * Dh + np.diag(0.5 * xh * xh)).real)[:3]
+        assert np.max(np.abs(evh - levels)) <= 1e-10
+
+
+def _table1():
+    rows = np.loadtxt(os.path.join(GOLDEN, "table1_paper.txt"))
+    return rows
+
+
+def test_mapped_two_body_depths_match_table1():
+    """The depths v0 of Table 1 for E0 = 1e-1, 1e-2, 1e-3 (8 printed digits) on the
+    even half of a 256-point mapped grid (L = 8)."""
+    x, D2 = cheb.parity_half(cheb.mapped_nodes(256, 8.0), cheb.mapped_second_derivative(256, 8.0), +1)
+    for E0, v0 in _table1()[:, :2]:
+        got = twobody.depth_for_binding_grid(x, D2, E0)
+        assert abs(got - v0) <= 6e-9, (E0, got, v0)
+
+
+def test_mapped_parity_table1_lowest_states():
+    """Table 1, E0 = 0.1, M/m = 20, f_G (paper units): the two lowest bosonic
+    (even under heavy exchange x -> -x) and fermionic (odd) ratios E/E0 to the
+    printed 8 digits, on the paper's grid: mapped Chebyshev, parity half grids,
+    N_y = N_x / 2 (128 x 64 points, map parameters 8 and 4).  This fixes the
+    Jacobi combination y -+ x/2 (R2), the paper units, the mapped second
+    derivative and the parity selection together."""
+    row = _table1()[0]
+    E0 = row[0]
+    xs, Ds = cheb.parity_half(cheb.mapped_nodes(256, 8.0), cheb.mapped_second_derivative(256, 8.0), +1)
+    v0 = twobody.depth_for_binding_grid(xs, Ds, E0)
+    got = {}
+    for name, px in (("bosons", +1), ("fermions", -1)):
+        P = problem.make_problem(ndim=1, n=(64, 32), L=(8.0, 4.0), alpha=20.0, v0=v0,
+                                 shape="gauss_paper", units="paper", grid="mapped",
+                                 parity=(px, +1))
+        got[name] = np.sort(np.linalg.eigvals(P.kron()).real)[:2] / E0
+    assert np.max(np.abs(got["bosons"] - row[[2, 3]])) <= 1.5e-8, got
+    assert np.max(np.abs(got["fermions"] - row[[5, 6]])) <= 1.5e-8, got
+
+
 # ----------------------------------------------------- preconditioner (eq. (14))
 def test_sylvester_dense_and_residual():
     """P7: Bartels-Stewart solution equals the dense solve of the shifted
