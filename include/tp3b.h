@@ -68,9 +68,18 @@ typedef enum {
 
 typedef struct tp3b_op_s* tp3b_op;
 
+/* Grid of each mode (Sec. 3.1). */
+typedef enum {
+  TP3B_GRID_CGL = 0,    /* n[k] interior Gauss-Lobatto points of [-L[k], L[k]],
+                           homogeneous Dirichlet conditions (end points removed) */
+  TP3B_GRID_MAPPED = 1  /* the paper's grid: roots of T_N carried to the whole real
+                           line by the algebraic map x = L[k] t / sqrt(1 - t^2)
+                           (no boundary condition) */
+} tp3b_grid;
+
 /* Problem descriptor (Sec. 2-3).  H = -c_x Lap_x - c_y Lap_y + V, discretised on
- * n[k] interior Chebyshev-Gauss-Lobatto points of [-L[k], L[k]] per mode with
- * homogeneous Dirichlet conditions (the two end points are removed). */
+ * n[k] unknowns per mode on the grid selected by `grid` (default: Gauss-Lobatto
+ * points of [-L[k], L[k]] with Dirichlet conditions). */
 typedef struct {
   int32_t ndim;            /* 1 (two modes x, y) or 2 (four modes x1, x2, y1, y2) */
   int32_t n[4];            /* points per mode, order x1,(x2),y1,(y2); each >= 2 */
@@ -85,6 +94,13 @@ typedef struct {
   double sigma;            /* preconditioner shift; NaN selects the two-body ground
                               energy on the y grid with reduced mass mu_hl */
   double mu_hl;            /* heavy-light reduced mass for the default shift */
+  int32_t grid;            /* a tp3b_grid value; 0 = Gauss-Lobatto with Dirichlet conditions */
+  int32_t parity[4];       /* TP3B_GRID_MAPPED only, per mode: 0 = full grid of n[k]
+                              points; +1 / -1 = functions even / odd under x -> -x
+                              (the parity selection rule of Sec. 5.1): a 2 n[k]-point
+                              grid of which the n[k] positive nodes carry the
+                              unknowns.  1D: parity[0] = +1 / -1 selects bosonic /
+                              fermionic heavy particles (heavy exchange is x -> -x) */
 } tp3b_problem_desc;
 
 /* Creates an operator: builds the second-derivative matrices, the potential

@@ -23,6 +23,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV", -5:
           -6: "ENONFINITE"}
 FP64, FP32, BF16X3 = 0, 1, 2
 POT = {"gauss": 0, "gauss_paper": 1, "lorentz3": 2, "harmonic": 3, "table": 4}
+GRID = {"cgl": 0, "mapped": 1}
 
 
 class Tp3bError(RuntimeError):
@@ -37,7 +38,8 @@ class ProblemDesc(ctypes.Structure):
                 ("v0", ctypes.c_double), ("width", ctypes.c_double),
                 ("V_table", ctypes.POINTER(ctypes.c_double)),
                 ("D2", ctypes.POINTER(ctypes.c_double) * 4), ("sigma", ctypes.c_double),
-                ("mu_hl", ctypes.c_double)]
+                ("mu_hl", ctypes.c_double), ("grid", ctypes.c_int32),
+                ("parity", ctypes.c_int32 * 4)]
 
 
 class JdqrOpts(ctypes.Structure):
@@ -157,7 +159,7 @@ class Operator:
     current HIP device (a tp3b_op handle)."""
 
     def __init__(self, ndim, n, L, c_x, c_y, pot="gauss", v0=1.0, width=1.0, sigma=None,
-                 mu_hl=1.0, V_table=None, D2=None):
+                 mu_hl=1.0, V_table=None, D2=None, grid="cgl", parity=None):
         import numpy as np
         nm = 2 * ndim
         n = [n] * nm if isinstance(n, int) else list(n)
@@ -172,6 +174,10 @@ class Operator:
         d.v0, d.width = float(v0), float(width)
         d.sigma = float("nan") if sigma is None else float(sigma)
         d.mu_hl = float(mu_hl)
+        d.grid = GRID[grid] if isinstance(grid, str) else int(grid)
+        if parity is not None:
+            for k, p in enumerate(parity):
+                d.parity[k] = int(p)
         self._keep = []
         if V_table is not None:
             arr = np.ascontiguousarray(V_table, dtype=np.float64).ravel()
@@ -200,8 +206,9 @@ class Operator:
             cx, cy, mu = jacobi_coefficients(cfg["alpha"])
         else:
             cx, cy, mu = paper_coefficients(cfg["alpha"])
-        return cls(cfg["ndim"], cfg["n"], cfg["L"], cx, cy, pot=kw.pop("pot", "gauss"),
-                   v0=cfg["v0"], width=cfg.get("width", 1.0), mu_hl=mu, **kw)
+        return cls(cfg["ndim"], cfg["n"], cfg["L"], cx, cy, pot=kw.pop("pot", cfg.get("shape", "gauss")),
+                   v0=cfg["v0"], width=cfg.get("width", 1.0), mu_hl=mu,
+                   grid=cfg.get("grid", "cgl"), parity=cfg.get("parity"), **kw)
 
     def close(self):
         if getattr(self, "handle", None):

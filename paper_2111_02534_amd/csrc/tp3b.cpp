@@ -63,6 +63,65 @@ static void cgl_second_derivative(int n, double L, std::vector<double>& D2,
   for (int i = 1; i <= n; ++i) x[i - 1] = -L * t[i];
 }
 
+// The paper's grid on the whole real line (Sec. 3.1): the N roots of T_N,
+// t_j = cos(pi (2j+1) / (2N)), carried to x = L t / sqrt(1 - t^2).  Grid
+// functions are interpolated by a polynomial in t; d/dt comes from the
+// barycentric formula (weights of first-kind Chebyshev points
+// (-1)^j sin((2j+1) pi / (2N))), and the chain rule gives
+// d^2/dx^2 = t'(x)^2 d^2/dt^2 + t''(x) d/dt with t' = (1 - t^2)^{3/2} / L and
+// t'' = -3 t (1 - t^2)^2 / L^2.  Nodes ascend.
+static void mapped_second_derivative(int N, double L, std::vector<double>& D2,
+                                     std::vector<double>& x) {
+  std::vector<double> t(N), w(N), D((size_t)N * N);
+  for (int i = 0; i < N; ++i) {
+    const int j = N - 1 - i;  // descending root index -> ascending order
+    const double a = M_PI * (2 * j + 1) / (2.0 * N);
+    t[i] = std::cos(a);
+    w[i] = ((j % 2) ? -1.0 : 1.0) * std::sin(a);
+  }
+  for (int i = 0; i < N; ++i) {
+    double rowsum = 0.0;
+    for (int j = 0; j < N; ++j) {
+      if (i == j) continue;
+      const double v = (w[j] / w[i]) / (t[i] - t[j]);
+      D[(size_t)i * N + j] = v;
+      rowsum += v;
+    }
+    D[(size_t)i * N + i] = -rowsum;
+  }
+  D2.assign((size_t)N * N, 0.0);
+  x.resize(N);
+  for (int i = 0; i < N; ++i) {
+    const double s = 1.0 - t[i] * t[i];
+    const double tp = s * std::sqrt(s) / L;
+    const double tpp = -3.0 * t[i] * s * s / (L * L);
+    for (int j = 0; j < N; ++j) {
+      double dd = 0.0;
+      for (int k = 0; k < N; ++k) dd += D[(size_t)i * N + k] * D[(size_t)k * N + j];
+      D2[(size_t)i * N + j] = tp * tp * dd + tpp * D[(size_t)i * N + j];
+    }
+    x[i] = L * t[i] / std::sqrt(s);
+  }
+}
+
+// Restriction of an operator on a grid symmetric about 0 (an even number N of
+// ascending nodes) to functions of parity `sign`: unknowns at the N/2 positive
+// nodes, the value at -x being sign times the value at x.
+static void parity_fold(int N, const std::vector<double>& D2, const std::vector<double>& x,
+                        int sign, std::vector<double>& D2h, std::vector<double>& xh) {
+  const int h = N / 2;
+  D2h.assign((size_t)h * h, 0.0);
+  xh.resize(h);
+  for (int i = 0; i < h; ++i) {
+    const int pi = h + i;
+    xh[i] = x[pi];
+    for (int j = 0; j < h; ++j) {
+      const int pj = h + j, mj = N - 1 - pj;
+      D2h[(size_t)i * h + j] = D2[(size_t)pi * N + pj] + sign * D2[(size_t)pi * N + mj];
+    }
+  }
+}
+
 static double pair_pot(int pot, double r, double v0, double w) {
   switch (pot) {
     case TP3B_POT_GAUSS: return -v0 * std::exp(-(r * r) / (2.0 * w * w));
@@ -590,6 +649,13 @@ tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* ou
   if (desc->pot == TP3B_POT_GAUSS && !(desc->width > 0)) return fail(TP3B_EINVAL, "width must be positive");
   if (desc->ndim == 2 && (desc->n[0] != desc->n[1] || desc->n[2] != desc->n[3]))
     return fail(TP3B_ENOTSUP, "2D operators need n[0] == n[1] and n[2] == n[3]");
+  if (desc->grid != TP3B_GRID_CGL && desc->grid != TP3B_GRID_MAPPED)
+    return fail(TP3B_EINVAL, "unknown grid");
+  for (int k = 0; k < nm; ++k) {
+    if (desc->parity[k] < -1 || desc->parity[k] > 1) return fail(TP3B_EINVAL, "parity must be -1, 0 or +1");
+    if (desc->parity[k] != 0 && desc->grid != TP3B_GRID_MAPPED)
+      return fail(TP3B_EINVAL, "parity half grids need TP3B_GRID_MAPPED");
+  }
 
   tp3b_op op = new tp3b_op_s();
   op->ndim = desc->ndim;
@@ -607,7 +673,17 @@ tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* ou
     op->n[k] = desc->n[k];
     op->L[k] = desc->L[k];
     std::vector<double> D2;
-    cgl_second_derivative(op->n[k], op->L[k], D2, x[k]);
+    if (desc->grid == TP3B_GRID_MAPPED) {
+      if (desc->parity[k] == 0) {
+        mapped_second_derivative(op->n[k], op->L[k], D2, x[k]);
+      } else {
+        std::vector<double> Df, xf;
+        mapped_second_derivative(2 * op->n[k], op->L[k], Df, xf);
+        parity_fold(2 * op->n[k], Df, xf, desc->parity[k] > 0 ? 1 : -1, D2, x[k]);
+      }
+    } else {
+      cgl_second_derivative(op->n[k], op->L[k], D2, x[k]);
+    }
     if (desc->D2[k]) D2.assign(desc->D2[k], desc->D2[k] + (size_t)op->n[k] * op->n[k]);
     op->D2h[k] = D2;
   }
