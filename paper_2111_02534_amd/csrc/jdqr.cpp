@@ -274,20 +274,22 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       TP3B_HIP(launch_gemm_nn<double>(N, m, nb, -1.0, V(), N, dS, m, 1.0, Rres, N, s));
     }
     std::vector<double> Cq((size_t)std::max(k, 1) * nb, 0.0);  // Q^T A U, column-major k x nb
+    std::vector<double> c1((size_t)std::max(k, 1) * nb), c2((size_t)std::max(k, 1) * nb);
     if (k > 0) {
-      for (int pass = 0; pass < 2; ++pass) {
-        TP3B_HIP(launch_dot_tn<double, double>(N, k, nb, QV, N, Rres, N, dC, k, part, s));
-        TP3B_HIP(launch_gemm_nn<double>(N, k, nb, -1.0, QV, N, dC, k, 1.0, Rres, N, s));
-        std::vector<double> c((size_t)k * nb);
-        TP3B_HIP(hipMemcpyAsync(c.data(), dC, sizeof(double) * k * nb, hipMemcpyDeviceToHost, s));
-        TP3B_HIP(hipStreamSynchronize(s));
-        for (size_t e = 0; e < c.size(); ++e) Cq[e] += c[e];
-      }
+      // two projection passes; both coefficient blocks come back with the norms
+      TP3B_HIP(launch_dot_tn<double, double>(N, k, nb, QV, N, Rres, N, dC, k, part, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, k, nb, -1.0, QV, N, dC, k, 1.0, Rres, N, s));
+      TP3B_HIP(launch_dot_tn<double, double>(N, k, nb, QV, N, Rres, N, dC2, k, part, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, k, nb, -1.0, QV, N, dC2, k, 1.0, Rres, N, s));
+      TP3B_HIP(hipMemcpyAsync(c1.data(), dC, sizeof(double) * k * nb, hipMemcpyDeviceToHost, s));
+      TP3B_HIP(hipMemcpyAsync(c2.data(), dC2, sizeof(double) * k * nb, hipMemcpyDeviceToHost, s));
     }
     TP3B_HIP(launch_bdot_diag<double>(N, nb, 1, Rres, 0, Rres, dNrm, 1, part, s));
     std::vector<double> rn(nb);
     TP3B_HIP(hipMemcpyAsync(rn.data(), dNrm, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
     TP3B_HIP(hipStreamSynchronize(s));
+    if (k > 0)
+      for (size_t e = 0; e < (size_t)k * nb; ++e) Cq[e] = c1[e] + c2[e];
     for (int j = 0; j < nb; ++j) rn[j] = std::sqrt(std::max(rn[j], 0.0));
     std::vector<double> theta(nb);
     for (int j = 0; j < nb; ++j) theta[j] = T[(size_t)j * m + j];
@@ -501,11 +503,22 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     double ta = now();
     tp3b_status as = applyA64(nb, Vn, AV() + (int64_t)m * N);
     if (as != TP3B_OK) return as;
-    std::vector<double> top, left;
-    tp3b_status ds = dot(m + nb, nb, V(), AV() + (int64_t)m * N, top, nb);
-    if (ds != TP3B_OK) return ds;
-    ds = dot(nb, m, Vn, AV(), left, m);
-    if (ds != TP3B_OK) return ds;
+    // the new columns (V^T A Vn) and rows (Vn^T A V) of the projected matrix,
+    // read back together
+    std::vector<double> top((size_t)(m + nb) * nb), left((size_t)nb * m);
+    {
+      std::vector<double> ct((size_t)(m + nb) * nb), cl((size_t)nb * m);
+      TP3B_HIP(launch_dot_tn<double, double>(N, m + nb, nb, V(), N, AV() + (int64_t)m * N, N, dM2,
+                                             m + nb, part, s));
+      TP3B_HIP(hipMemcpyAsync(ct.data(), dM2, sizeof(double) * ct.size(), hipMemcpyDeviceToHost, s));
+      TP3B_HIP(launch_dot_tn<double, double>(N, nb, m, Vn, N, AV(), N, dS, nb, part, s));
+      TP3B_HIP(hipMemcpyAsync(cl.data(), dS, sizeof(double) * cl.size(), hipMemcpyDeviceToHost, s));
+      TP3B_HIP(hipStreamSynchronize(s));
+      for (int i = 0; i < m + nb; ++i)
+        for (int j = 0; j < nb; ++j) top[(size_t)i * nb + j] = ct[i + (size_t)j * (m + nb)];
+      for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < m; ++j) left[(size_t)i * m + j] = cl[i + (size_t)j * nb];
+    }
     std::vector<double> Mn((size_t)(m + nb) * (m + nb), 0.0);
     for (int i = 0; i < m; ++i)
       for (int j = 0; j < m; ++j) Mn[(size_t)i * (m + nb) + j] = M[(size_t)i * m + j];

@@ -85,6 +85,9 @@ hipError_t launch_convert(int64_t N, int ncol, double alpha, const TI* X, int64_
 // where the pivot falls below (drop_tol * norm0[j])^2.  Single thread.
 hipError_t launch_chol_small(int nx, const double* G, const double* norm0sq, double drop_tol,
                              double* R, int* flags, hipStream_t s);
+// n0[j] = G[j + j nx] for j < nx (the diagonal of a Gram matrix); flag[0] = 1 if
+// any of them is not finite, 0 otherwise.  Single thread.
+hipError_t launch_gram_diag(int nx, const double* G, double* n0, int* flag, hipStream_t s);
 // X (N x nx) <- X R^{-1} for upper-triangular R (column-major nx x nx).
 hipError_t launch_trsm_right(int64_t N, int nx, const double* R, double* X, int64_t ldx,
                              hipStream_t s);

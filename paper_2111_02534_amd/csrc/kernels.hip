@@ -321,6 +321,23 @@ __global__ void k_chol_small(int nx, const double* __restrict__ G, const double*
   chol_small_serial(nx, G, n0, drop_tol, R, flags);
 }
 
+__global__ void k_gram_diag(int nx, const double* __restrict__ G, double* __restrict__ n0,
+                            int* __restrict__ flag) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int bad = 0;
+  for (int j = 0; j < nx; ++j) {
+    const double v = G[j + j * nx];
+    n0[j] = v;
+    if (!(v - v == 0.0)) bad = 1;
+  }
+  flag[0] = bad;
+}
+
+hipError_t launch_gram_diag(int nx, const double* G, double* n0, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_diag, dim3(1), dim3(64), 0, s, nx, G, n0, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_chol_small(int nx, const double* G, const double* norm0sq, double drop_tol,
                              double* R, int* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, s, nx, G, norm0sq, drop_tol, R, flags);

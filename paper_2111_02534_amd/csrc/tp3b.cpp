@@ -482,6 +482,47 @@ tp3b_status block_orth_impl(int64_t N, int nq, const double* Q, int64_t ldq, int
   std::vector<double> hG((size_t)nx * nx), hR1((size_t)nx * nx), hR2((size_t)nx * nx);
   std::vector<double> hC1((size_t)(nq + 1) * nx, 0.0), hC2((size_t)(nq + 1) * nx, 0.0);
   std::vector<int> hflags(nx + 1, 0);
+  int deficient = 0;
+
+  if (!C_qx && !R_xx) {
+    // Without factors to return, the whole sequence is queued with one host
+    // round trip at the end: the dependence test reads the input norms on the
+    // device, and the first factorisation's flags are read back last.  A
+    // dependent column (rare) is replaced by a random vector and the general
+    // path below runs on the result; span(X) is unchanged by the triangular
+    // transforms (a dependent column only carries directions of earlier ones).
+    int* fl1 = flags;           // first Cholesky: dependence flags
+    int* nonfin = flags + nx;   // non-finite input
+    int* fl2 = flags + nx + 1;  // second Cholesky (no test)
+    TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
+    TP3B_HIP(launch_gram_diag(nx, G, n0, nonfin, s));
+    if (nq > 0) {
+      TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, X, ldx, C1, nq, part, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, nq, nx, -1.0, Q, ldq, C1, nq, 1.0, X, ldx, s));
+      TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, X, ldx, C2, nq, part, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, nq, nx, -1.0, Q, ldq, C2, nq, 1.0, X, ldx, s));
+    }
+    TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
+    TP3B_HIP(launch_chol_small(nx, G, n0, kDropTol, R1, fl1, s));
+    TP3B_HIP(launch_trsm_right(N, nx, R1, X, ldx, s));
+    TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
+    TP3B_HIP(launch_chol_small(nx, G, n0, 0.0, R2, fl2, s));
+    TP3B_HIP(launch_trsm_right(N, nx, R2, X, ldx, s));
+    TP3B_HIP(hipMemcpyAsync(hflags.data(), flags, sizeof(int) * (nx + 1), hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipStreamSynchronize(s));
+    if (hflags[nx]) return fail(TP3B_ENONFINITE, "block_orth: non-finite input");
+    int bad = 0;
+    for (int j = 0; j < nx; ++j) bad += hflags[j];
+    if (!bad) {
+      if (rank) *rank = nx;
+      return TP3B_OK;
+    }
+    for (int j = 0; j < nx; ++j)
+      if (hflags[j]) {
+        ++deficient;
+        TP3B_HIP(launch_hash_fill(N, X + (int64_t)j * ldx, seed, (uint64_t)(1000 + j), s));
+      }
+  }
 
   // Input column norms (for the rank test) and the finiteness check.
   TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
@@ -493,7 +534,6 @@ tp3b_status block_orth_impl(int64_t N, int nq, const double* Q, int64_t ldq, int
     if (!std::isfinite(hn0[j])) return fail(TP3B_ENONFINITE, "block_orth: non-finite input");
   }
   std::vector<int> replaced(nx, 0);
-  int deficient = 0;
   for (int attempt = 0; attempt < 4; ++attempt) {
     TP3B_HIP(hipMemcpyAsync(n0, hn0.data(), sizeof(double) * nx, hipMemcpyHostToDevice, s));
     // Two classical Gram-Schmidt passes against Q.

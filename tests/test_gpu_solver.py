@@ -55,6 +55,29 @@ def test_block_orth_rank_deficient():
         assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(X[:, j])
 
 
+def test_block_orth_rank_deficient_without_factors():
+    """Without factors the orthogonalisation runs queued with one read-back; a
+    dependent column is found at the end, replaced and the block redone."""
+    import torch
+    t3 = need_gpu()
+    rng = np.random.default_rng(4)
+    N = 6000
+    Q = np.linalg.qr(rng.standard_normal((N, 6)))[0]
+    X = rng.standard_normal((N, 5))
+    X[:, 3] = 2 * X[:, 0] + X[:, 4] - Q @ np.arange(6.0)
+    Xd = to_dev(X.T)
+    _, _, rk = t3.block_orth(to_dev(Q.T), Xd, want_factors=False)
+    torch.cuda.synchronize()
+    Xo = Xd.cpu().numpy().T
+    assert rk == 4
+    assert np.max(np.abs(Xo.T @ Xo - np.eye(5))) <= 1e-12
+    assert np.max(np.abs(Q.T @ Xo)) <= 1e-12
+    for j in (0, 1, 2, 4):
+        r = X[:, j] - Q @ (Q.T @ X[:, j])
+        r -= Xo @ (Xo.T @ r)
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(X[:, j])
+
+
 @pytest.mark.parametrize("inner", ["fp64", "fp32"])
 def test_jdqr_c1_matches_dense(inner):
     t3 = need_gpu()
