@@ -175,9 +175,11 @@ typedef struct {
   int32_t check_finite; /* reject NaN/Inf in X0 */
   int32_t verbose;      /* print one line per outer iteration to stderr */
   int32_t profile;      /* time the mode-product launches with HIP events (stats) */
-  int32_t graph;        /* batched solver: capture the GMRES inner iteration as a
-                           HIP graph once per solve and replay it every outer
-                           iteration (0 = launch eagerly) */
+  int32_t graph;        /* capture the GMRES inner iteration (right-hand side and
+                           the fixed steps) as a HIP graph and replay it every
+                           outer iteration; the single-instance solver keeps one
+                           graph per projection width and block width
+                           (0 = launch eagerly) */
   double stall_tol;     /* when nothing locks, lock the leading pair once its
                            residual is <= stall_tol max(|theta|, 1) and has stayed
                            within 10% of its previous value for three outer
@@ -195,11 +197,14 @@ typedef struct {
   int32_t n_conv, n_outer, n_restart, n_lock_events;
   int64_t n_apply_H_fp64, n_apply_H_low, n_apply_prec;
   double t_apply, t_prec, t_orth, t_rr, t_gmres, t_total; /* seconds */
-  /* with opts.profile: device time (s) and launch-group count of
+  /* with opts.profile: device time (s), launch-group count and vectors of the
+     timed launch groups of
      [0] FP64 H applies, [1] low-precision H applies,
-     [2] FP64 preconditioner applies, [3] low-precision preconditioner applies */
+     [2] FP64 preconditioner applies, [3] low-precision preconditioner applies.
+     Launches replayed from a captured graph (opts.graph) are not timed. */
   double t_kernel[4];
   int64_t n_kernel[4];
+  int64_t v_kernel[4];
 } tp3b_jdqr_stats;
 
 tp3b_status tp3b_jdqr_default_opts(tp3b_jdqr_opts* opts);

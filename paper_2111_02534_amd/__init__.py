@@ -61,13 +61,14 @@ class JdqrStats(ctypes.Structure):
                 ("n_apply_prec", ctypes.c_int64), ("t_apply", ctypes.c_double),
                 ("t_prec", ctypes.c_double), ("t_orth", ctypes.c_double), ("t_rr", ctypes.c_double),
                 ("t_gmres", ctypes.c_double), ("t_total", ctypes.c_double),
-                ("t_kernel", ctypes.c_double * 4), ("n_kernel", ctypes.c_int64 * 4)]
+                ("t_kernel", ctypes.c_double * 4), ("n_kernel", ctypes.c_int64 * 4),
+                ("v_kernel", ctypes.c_int64 * 4)]
 
     def as_dict(self):
         out = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
-            out[name] = list(v) if name in ("t_kernel", "n_kernel") else v
+            out[name] = list(v) if name in ("t_kernel", "n_kernel", "v_kernel") else v
         return out
 
 
@@ -293,7 +294,7 @@ class Operator:
     def jdqr(self, nev, block, *, X0=None, inner_prec=FP64, precond=True, tol=1e-12,
              gmres_steps=10, m_min=0, m_max=0, max_outer=1000, seed=0, switch_tol=1e-2,
              target=None, verbose=False, want_Q=True, profile=False, stall_tol=1e-8,
-             low_start=3):
+             low_start=3, graph=True):
         import numpy as np
         import torch
         o = JdqrOpts()
@@ -303,7 +304,7 @@ class Operator:
         o.inner_prec, o.tol, o.switch_tol = inner_prec, tol, switch_tol
         o.target = float("nan") if target is None else float(target)
         o.seed, o.verbose, o.profile = seed, int(verbose), int(profile)
-        o.stall_tol, o.low_start = float(stall_tol), int(low_start)
+        o.stall_tol, o.low_start, o.graph = float(stall_tol), int(low_start), int(bool(graph))
         evals = np.empty(nev)
         R = np.empty((nev, nev), order="F")
         res = np.empty(nev)

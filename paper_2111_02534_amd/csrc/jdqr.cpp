@@ -53,38 +53,51 @@ std::vector<double> colmajor(const std::vector<double>& A, int ld, int r0, int c
   return out;
 }
 
-// Optional HIP-event timing of the mode-product launches inside the solve:
-// kind 0 = FP64 Hamiltonian applies, 1 = low-precision Hamiltonian applies,
-// 2 = FP64 preconditioner applies, 3 = low-precision preconditioner applies.
+// Optional timing of the mode-product launches inside the solve with kernel
+// timestamp events (LaunchTiming): kind 0 = FP64 Hamiltonian applies, 1 =
+// low-precision Hamiltonian applies, 2 = FP64 preconditioner applies, 3 =
+// low-precision preconditioner applies.  Launches inside a captured graph are
+// not timed (paused).
 struct KernelTimer {
-  bool on = false;
-  hipStream_t s = nullptr;
-  std::vector<hipEvent_t> ev;
-  std::vector<int> kind;
+  bool on = false, paused = false;
+  std::vector<hipEvent_t> ev;  // pairs (2i, 2i+1) bracket one launch group
+  std::vector<int> kind, nvec;
   size_t used = 0;
-  hipError_t mark(int k) {
-    if (!on) return hipSuccess;
-    if (used == ev.size()) {
+  LaunchTiming lt;
+  hipError_t begin(int k, int nv) {
+    if (!on || paused) return hipSuccess;
+    while (ev.size() < used + 2) {
       hipEvent_t e;
       hipError_t r = hipEventCreate(&e);
       if (r != hipSuccess) return r;
       ev.push_back(e);
       kind.push_back(-1);
+      nvec.push_back(0);
     }
     kind[used] = k;
-    return hipEventRecord(ev[used++], s);
+    nvec[used] = nv;
+    lt.start = ev[used];
+    lt.stop = ev[used + 1];
+    lt.started = false;
+    launch_timing() = &lt;
+    used += 2;
+    return hipSuccess;
   }
-  // pairs (2i, 2i+1) bracket one launch group
-  void collect(double* t, int64_t* n) {
+  void end() {
+    if (launch_timing() == &lt) launch_timing() = nullptr;
+  }
+  void collect(double* t, int64_t* n, int64_t* v) {
     for (size_t i = 0; i + 1 < used; i += 2) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) {
         t[kind[i]] += 1e-3 * ms;
         n[kind[i]] += 1;
+        v[kind[i]] += nvec[i];
       }
     }
   }
   ~KernelTimer() {
+    end();
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
 };
@@ -93,6 +106,47 @@ double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// The solve's own stream and the GMRES graphs captured on it.  A graph is
+// keyed by what its kernel arguments depend on: the projection width, the
+// number of correction columns and the reduction scratch address (which moves
+// when the scratch grows).
+struct SolveGraphs {
+  struct Entry {
+    int nqt, nb;
+    const double* part;
+    hipGraph_t g;
+    hipGraphExec_t x;
+    int64_t dH64, dHlow, dPrec;  // apply counts of one replay
+  };
+  hipStream_t s = nullptr;
+  std::vector<Entry> e;
+  Entry* find(int nqt, int nb, const double* part) {
+    for (Entry& x : e)
+      if (x.nqt == nqt && x.nb == nb && x.part == part) return &x;
+    return nullptr;
+  }
+  void drop_stale(const double* part) {
+    std::vector<Entry> keep;
+    for (Entry& x : e) {
+      if (x.part == part) {
+        keep.push_back(x);
+      } else {
+        (void)hipGraphExecDestroy(x.x);
+        (void)hipGraphDestroy(x.g);
+      }
+    }
+    e.swap(keep);
+  }
+  ~SolveGraphs() {
+    if (s) (void)hipStreamSynchronize(s);
+    for (Entry& x : e) {
+      (void)hipGraphExecDestroy(x.x);
+      (void)hipGraphDestroy(x.g);
+    }
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
 }  // namespace
 
 template <typename TW>
@@ -100,7 +154,12 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
                             double* evals, double* Qout, double* Rout, double* resnorm,
                             tp3b_jdqr_stats* st, bool bf3) {
   const double t_start = now();
-  hipStream_t s = nullptr;
+  // The solve runs on a stream of its own; the caller's pending work (which
+  // may have produced X0) completes first.
+  SolveGraphs graphs;
+  TP3B_HIP(hipDeviceSynchronize());
+  TP3B_HIP(hipStreamCreateWithFlags(&graphs.s, hipStreamNonBlocking));
+  hipStream_t s = graphs.s;
   const int64_t N = op->N;
   const int nev = o.nev, b = o.block, steps = o.gmres_steps;
   const int m_max = o.m_max, m_min = o.m_min;
@@ -110,7 +169,6 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   tp3b_jdqr_stats stats{};
   KernelTimer kt;
   kt.on = o.profile != 0;
-  kt.s = s;
 
   // ---- device buffers
   const int qv_cols = nev + m_max + b;
@@ -133,6 +191,12 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   TP3B_HIP(dalloc(Wb, sizeof(TW) * N * b));
   TP3B_HIP(dalloc(Zb, sizeof(TW) * N * b));
   TP3B_HIP(dalloc(Tcb, sizeof(double) * N * b));
+  // Declared after the buffers, so destroyed before them: on every return the
+  // solve's stream has finished with them before they are freed.
+  struct StreamDrain {
+    hipStream_t s;
+    ~StreamDrain() { (void)hipStreamSynchronize(s); }
+  } drain{s};
   // small device arrays (doubles)
   const int hld = steps + 2;
   const size_t n_small = (size_t)(m_max + b) * (m_max + b) * 2 + (size_t)qt_max * qt_max +
@@ -180,17 +244,17 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   auto AV = [&]() { return AVbase + (int64_t)av0 * N; };
   auto applyA64 = [&](int nv, const double* X, double* Y) -> tp3b_status {
     stats.n_apply_H_fp64 += nv;
-    TP3B_HIP(kt.mark(0));
+    TP3B_HIP(kt.begin(0, nv));
     tp3b_status r = apply_H_impl<double>(op, nv, X, N, Y, N, nullptr, s);
-    TP3B_HIP(kt.mark(0));
+    kt.end();
     return r;
   };
   auto applyW = [&](int nv, const TW* X, TW* Y, const double* sh) -> tp3b_status {
     const int kd = low ? 1 : 0;
     (low ? stats.n_apply_H_low : stats.n_apply_H_fp64) += nv;
-    TP3B_HIP(kt.mark(kd));
+    TP3B_HIP(kt.begin(kd, nv));
     tp3b_status r = apply_H_impl<TW>(op, nv, X, N, Y, N, sh, s, bf3);
-    TP3B_HIP(kt.mark(kd));
+    kt.end();
     return r;
   };
   auto dot = [&](int p, int q, const double* A, const double* B, std::vector<double>& host,
@@ -406,9 +470,9 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     auto precond_w = [&](const TW* in, TW* out) -> tp3b_status {
       stats.n_apply_prec += nb;
       const int kd = low ? 3 : 2;
-      TP3B_HIP(kt.mark(kd));
+      TP3B_HIP(kt.begin(kd, nb));
       tp3b_status r = apply_prec_impl<TW>(op, nb, in, N, out, N, s, bf3);
-      TP3B_HIP(kt.mark(kd));
+      kt.end();
       return r;
     };
     auto project = [&](TW* Zp) -> tp3b_status {
@@ -416,41 +480,86 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       TP3B_HIP((launch_gemm_nn<TW>(N, nqt, nb, -1.0, Yqw, N, dC2, nqt, 1.0, Zp, N, s)));
       return TP3B_OK;
     };
-    // right-hand side: proj(P^{-1}(-r))
-    TW* rhs = W;
-    if (use_prec) {
-      TP3B_HIP((launch_convert<double, TW>(N, nb, -1.0, Rres, N, Zt, N, s)));
-      tp3b_status ps = precond_w(Zt, rhs);
-      if (ps != TP3B_OK) return ps;
-    } else {
-      TP3B_HIP((launch_convert<double, TW>(N, nb, -1.0, Rres, N, rhs, N, s)));
-    }
-    { tp3b_status ps = project(rhs); if (ps != TP3B_OK) return ps; }
-    TP3B_HIP(launch_bdot_diag<TW>(N, nb, 1, rhs, 0, rhs, dNrm, 1, part, s));
-    TP3B_HIP(launch_normalize_cols<TW>(N, nb, dNrm, rhs, Vg, dBeta, 1, s));
+    // Right-hand side proj(P^{-1}(-r)) and the fixed GMRES steps: kernel
+    // launches only, so the sequence can be captured as a graph.
     const int64_t bs = N * nb;
-    for (int kk = 0; kk < steps; ++kk) {
-      TW* vk = Vg + (int64_t)kk * bs;
-      TW* w = W;
+    auto gmres_launch = [&]() -> tp3b_status {
+      TW* rhs = W;
       if (use_prec) {
-        tp3b_status as = applyW(nb, vk, Zt, dShift);
-        if (as != TP3B_OK) return as;
-        tp3b_status ps = precond_w(Zt, w);
+        TP3B_HIP((launch_convert<double, TW>(N, nb, -1.0, Rres, N, Zt, N, s)));
+        tp3b_status ps = precond_w(Zt, rhs);
         if (ps != TP3B_OK) return ps;
       } else {
-        tp3b_status as = applyW(nb, vk, w, dShift);
-        if (as != TP3B_OK) return as;
+        TP3B_HIP((launch_convert<double, TW>(N, nb, -1.0, Rres, N, rhs, N, s)));
       }
-      { tp3b_status ps = project(w); if (ps != TP3B_OK) return ps; }
-      double* h1 = dH1 + (size_t)kk * b * hld;
-      double* h2 = dH2 + (size_t)kk * b * hld;
-      TP3B_HIP(launch_bdot_diag<TW>(N, nb, kk + 1, Vg, bs, w, h1, hld, part, s));
-      TP3B_HIP(launch_bupdate_diag<TW>(N, nb, kk + 1, -1.0, Vg, bs, h1, hld, w, s));
-      TP3B_HIP(launch_bdot_diag<TW>(N, nb, kk + 1, Vg, bs, w, h2, hld, part, s));
-      TP3B_HIP(launch_bupdate_diag<TW>(N, nb, kk + 1, -1.0, Vg, bs, h2, hld, w, s));
-      TP3B_HIP(launch_bdot_diag<TW>(N, nb, 1, w, 0, w, dNrm, 1, part, s));
-      TP3B_HIP(launch_normalize_cols<TW>(N, nb, dNrm, w, Vg + (int64_t)(kk + 1) * bs,
-                                         dHs + (size_t)kk * b, 1, s));
+      { tp3b_status ps = project(rhs); if (ps != TP3B_OK) return ps; }
+      TP3B_HIP(launch_bdot_diag<TW>(N, nb, 1, rhs, 0, rhs, dNrm, 1, part, s));
+      TP3B_HIP(launch_normalize_cols<TW>(N, nb, dNrm, rhs, Vg, dBeta, 1, s));
+      for (int kk = 0; kk < steps; ++kk) {
+        TW* vk = Vg + (int64_t)kk * bs;
+        TW* w = W;
+        if (use_prec) {
+          tp3b_status as = applyW(nb, vk, Zt, dShift);
+          if (as != TP3B_OK) return as;
+          tp3b_status ps = precond_w(Zt, w);
+          if (ps != TP3B_OK) return ps;
+        } else {
+          tp3b_status as = applyW(nb, vk, w, dShift);
+          if (as != TP3B_OK) return as;
+        }
+        { tp3b_status ps = project(w); if (ps != TP3B_OK) return ps; }
+        double* h1 = dH1 + (size_t)kk * b * hld;
+        double* h2 = dH2 + (size_t)kk * b * hld;
+        TP3B_HIP(launch_bdot_diag<TW>(N, nb, kk + 1, Vg, bs, w, h1, hld, part, s));
+        TP3B_HIP(launch_bupdate_diag<TW>(N, nb, kk + 1, -1.0, Vg, bs, h1, hld, w, s));
+        TP3B_HIP(launch_bdot_diag<TW>(N, nb, kk + 1, Vg, bs, w, h2, hld, part, s));
+        TP3B_HIP(launch_bupdate_diag<TW>(N, nb, kk + 1, -1.0, Vg, bs, h2, hld, w, s));
+        TP3B_HIP(launch_bdot_diag<TW>(N, nb, 1, w, 0, w, dNrm, 1, part, s));
+        TP3B_HIP(launch_normalize_cols<TW>(N, nb, dNrm, w, Vg + (int64_t)(kk + 1) * bs,
+                                           dHs + (size_t)kk * b, 1, s));
+      }
+      return TP3B_OK;
+    };
+    if (o.graph) {
+      graphs.drop_stale(part);
+      SolveGraphs::Entry* ge = graphs.find(nqt, nb, part);
+      if (!ge) {
+        // capture once: the launches are recorded, not run, so the apply
+        // counters they bump are taken back and added per replay instead
+        SolveGraphs::Entry ne{nqt, nb, part, nullptr, nullptr, 0, 0, 0};
+        const int64_t h64 = stats.n_apply_H_fp64, hlow = stats.n_apply_H_low,
+                      pr = stats.n_apply_prec;
+        kt.paused = true;
+        TP3B_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        tp3b_status cs = gmres_launch();
+        hipError_t ce = hipStreamEndCapture(s, &ne.g);
+        kt.paused = false;
+        if (cs != TP3B_OK) {
+          if (ne.g) (void)hipGraphDestroy(ne.g);
+          return cs;
+        }
+        TP3B_HIP(ce);
+        hipError_t ie = hipGraphInstantiate(&ne.x, ne.g, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+          (void)hipGraphDestroy(ne.g);
+          TP3B_HIP(ie);
+        }
+        ne.dH64 = stats.n_apply_H_fp64 - h64;
+        ne.dHlow = stats.n_apply_H_low - hlow;
+        ne.dPrec = stats.n_apply_prec - pr;
+        stats.n_apply_H_fp64 = h64;
+        stats.n_apply_H_low = hlow;
+        stats.n_apply_prec = pr;
+        graphs.e.push_back(ne);
+        ge = &graphs.e.back();
+      }
+      TP3B_HIP(hipGraphLaunch(ge->x, s));
+      stats.n_apply_H_fp64 += ge->dH64;
+      stats.n_apply_H_low += ge->dHlow;
+      stats.n_apply_prec += ge->dPrec;
+    } else {
+      tp3b_status gs = gmres_launch();
+      if (gs != TP3B_OK) return gs;
     }
     std::vector<double> hH1((size_t)steps * b * hld), hH2((size_t)steps * b * hld),
         hHs((size_t)steps * b), hBeta(b);
@@ -549,14 +658,12 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   if (evals)
     for (int i = 0; i < nev; ++i) evals[i] = i < nconv ? evs[i] : NAN;
   if (Qout && nconv > 0)
-    TP3B_HIP(hipMemcpy(Qout, QV, sizeof(double) * N * nconv, hipMemcpyDeviceToDevice));
+    TP3B_HIP(hipMemcpyAsync(Qout, QV, sizeof(double) * N * nconv, hipMemcpyDeviceToDevice, s));
+  TP3B_HIP(hipStreamSynchronize(s));
   if (Rout) std::memcpy(Rout, Rl.data(), sizeof(double) * nev * nev);
   if (resnorm)
     for (int i = 0; i < nev; ++i) resnorm[i] = i < (int)lockres.size() ? lockres[i] : NAN;
-  if (kt.on) {
-    TP3B_HIP(hipStreamSynchronize(s));
-    kt.collect(stats.t_kernel, stats.n_kernel);
-  }
+  if (kt.on) kt.collect(stats.t_kernel, stats.n_kernel, stats.v_kernel);
   stats.n_conv = nconv;
   stats.n_outer = outer;
   stats.t_total = now() - t_start;

@@ -39,6 +39,17 @@ struct ModeProd {
 // Tile configurations (output tile TM x TN per 256-thread workgroup).
 enum TileCfg { TILE_32 = 0, TILE_64 = 1, TILE_128 = 2, TILE_64x128 = 3, NUM_TILE_CFGS = 4 };
 
+// Optional kernel timestamps for the mode-product launches of the calling
+// thread.  While launch_timing() points at a LaunchTiming, the first launch
+// records `start` when it begins and every launch records `stop` when it ends,
+// so the pair spans the launch group without any dispatch gap before it.
+// Launches that are being captured into a graph must not be timed.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool started = false;
+};
+LaunchTiming*& launch_timing();
+
 template <typename T>
 hipError_t launch_modeprod(const ModeProd<T>& a, int tile, hipStream_t s);
 // The same product on FP32 data with BF16x3 split products on the bf16 matrix

@@ -13,6 +13,7 @@
 // deterministic (no atomics).
 #include "kernels.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "device_bodies.h"
@@ -20,6 +21,24 @@
 namespace tp3b {
 
 // ------------------------------------------------------------------ mode product
+LaunchTiming*& launch_timing() {
+  static thread_local LaunchTiming* t = nullptr;
+  return t;
+}
+
+// Launch with the timing events of launch_timing() when it is set.
+#define TP3B_MP_LAUNCH(KERN, GRID, S, ARG)                                                 \
+  do {                                                                                     \
+    LaunchTiming* lt_ = launch_timing();                                                   \
+    if (lt_) {                                                                             \
+      hipEvent_t st_ = lt_->started ? nullptr : lt_->start;                                \
+      lt_->started = true;                                                                 \
+      hipExtLaunchKernelGGL(KERN, dim3(GRID), dim3(256), 0, S, st_, lt_->stop, 0, ARG);    \
+    } else {                                                                               \
+      hipLaunchKernelGGL(KERN, dim3(GRID), dim3(256), 0, S, ARG);                          \
+    }                                                                                      \
+  } while (0)
+
 // ROLE only separates the kernel names seen by profilers: 0 = Hamiltonian apply
 // (both modes + potential), 1 = preconditioner mode products, 2 = 2D x-mode
 // accumulation passes.
@@ -34,16 +53,16 @@ static void launch_role(const ModeProd<T>& a, int tile, hipStream_t s, unsigned 
                         unsigned g128, unsigned g64x128) {
   switch (tile) {
     case TILE_32:
-      hipLaunchKernelGGL((k_modeprod<T, 32, 32, 64, ROLE, true>), dim3(g32), dim3(256), 0, s, a);
+      TP3B_MP_LAUNCH((k_modeprod<T, 32, 32, 64, ROLE, true>), g32, s, a);
       break;
     case TILE_64:
-      hipLaunchKernelGGL((k_modeprod<T, 64, 64, 16, ROLE>), dim3(g64), dim3(256), 0, s, a);
+      TP3B_MP_LAUNCH((k_modeprod<T, 64, 64, 16, ROLE>), g64, s, a);
       break;
     case TILE_128:
-      hipLaunchKernelGGL((k_modeprod<T, 128, 128, 16, ROLE>), dim3(g128), dim3(256), 0, s, a);
+      TP3B_MP_LAUNCH((k_modeprod<T, 128, 128, 16, ROLE>), g128, s, a);
       break;
     default:
-      hipLaunchKernelGGL((k_modeprod<T, 64, 128, 16, ROLE>), dim3(g64x128), dim3(256), 0, s, a);
+      TP3B_MP_LAUNCH((k_modeprod<T, 64, 128, 16, ROLE>), g64x128, s, a);
       break;
   }
 }
@@ -81,13 +100,13 @@ static void launch_role_bf3(const ModeProd<float>& a, int tile, hipStream_t s, u
                             unsigned g128, unsigned g64x128) {
   switch (tile) {
     case TILE_128:
-      hipLaunchKernelGGL((k_modeprod_bf3<128, 128, 32, ROLE>), dim3(g128), dim3(256), 0, s, a);
+      TP3B_MP_LAUNCH((k_modeprod_bf3<128, 128, 32, ROLE>), g128, s, a);
       break;
     case TILE_64x128:
-      hipLaunchKernelGGL((k_modeprod_bf3<64, 128, 32, ROLE>), dim3(g64x128), dim3(256), 0, s, a);
+      TP3B_MP_LAUNCH((k_modeprod_bf3<64, 128, 32, ROLE>), g64x128, s, a);
       break;
     default:  // TILE_32 and TILE_64: the smallest bf16 tile is 64 x 64
-      hipLaunchKernelGGL((k_modeprod_bf3<64, 64, 32, ROLE>), dim3(g64), dim3(256), 0, s, a);
+      TP3B_MP_LAUNCH((k_modeprod_bf3<64, 64, 32, ROLE>), g64, s, a);
       break;
   }
 }

@@ -150,3 +150,43 @@ def test_jdqr_low_start_finds_deep_ground_state(seed):
         err = np.max(np.abs(r.evals - ref) / np.maximum(np.abs(ref), 1.0))
         say("low start", seed, inner, r.evals, err, r.stats["n_outer"])
         assert err <= 1e-10
+
+
+@pytest.mark.parametrize("name,inner", [("c2", "fp64"), ("c2", "fp32"), ("c1", "bf16x3")])
+def test_jdqr_graph_replay_matches_eager(name, inner):
+    """The GMRES iteration replayed from captured graphs (one per projection
+    width, captured again as pairs lock) must give exactly the eager result:
+    the replays run the same kernels in the same order, with eager work and
+    host synchronisations between them."""
+    import torch
+    t3 = need_gpu()
+    pk = {"fp64": t3.FP64, "fp32": t3.FP32, "bf16x3": t3.BF16X3}[inner]
+    cfg = config(name)
+    op = t3.Operator.from_config(cfg)
+    rg = op.jdqr(cfg["nev"], cfg["block"], inner_prec=pk, seed=3, graph=True)
+    re = op.jdqr(cfg["nev"], cfg["block"], inner_prec=pk, seed=3, graph=False)
+    say("graph vs eager", name, inner, rg.evals, rg.stats["n_outer"], rg.stats["n_lock_events"])
+    if name == "c2":
+        assert rg.stats["n_lock_events"] >= 2
+    assert rg.stats["n_outer"] == re.stats["n_outer"]
+    for key in ("n_apply_H_fp64", "n_apply_H_low", "n_apply_prec"):
+        assert rg.stats[key] == re.stats[key], key
+    assert np.array_equal(rg.evals, re.evals)
+    assert np.array_equal(rg.resnorm, re.resnorm)
+    assert torch.equal(rg.Q, re.Q)
+
+
+def test_jdqr_profile_times_kernels_outside_graph():
+    """With profiling on, the Hamiltonian applies that extend the search
+    space are timed by kernel timestamps: each timed group is one launch of at
+    most `block` vectors, and the times are positive and below the solve
+    time."""
+    t3 = need_gpu()
+    cfg = config("c1")
+    op = t3.Operator.from_config(cfg)
+    r = op.jdqr(cfg["nev"], cfg["block"], seed=cfg["seed_start"], profile=True)
+    n, v, t = r.stats["n_kernel"][0], r.stats["v_kernel"][0], r.stats["t_kernel"][0]
+    say("profile", n, v, t, r.stats["t_total"])
+    assert n >= r.stats["n_outer"]
+    assert n <= v <= n * cfg["block"]
+    assert 0 < t < r.stats["t_total"]
