@@ -115,6 +115,13 @@ def mapped_nodes(N: int, L: float) -> np.ndarray:
     return L * t / np.sqrt(1.0 - t * t)
 
 
+def mapped_first_derivative(N: int, L: float) -> np.ndarray:
+    """N x N first-derivative collocation matrix on the mapped grid:
+    d/dx = t'(x) d/dt."""
+    t = gauss_roots(N)
+    return ((1.0 - t * t) ** 1.5 / L)[:, None] * first_derivative_roots(t)
+
+
 def mapped_second_derivative(N: int, L: float) -> np.ndarray:
     """N x N second-derivative collocation matrix on the mapped grid."""
     t = gauss_roots(N)
