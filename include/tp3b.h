@@ -222,6 +222,35 @@ tp3b_status tp3b_jdqr_solve(tp3b_op op, const tp3b_jdqr_opts* opts, const double
                             double* evals, double* Q, double* R, double* resnorm,
                             tp3b_jdqr_stats* stats);
 
+/* ---- The paper's procedure over binding energies (Sec. 2; Sec. 5.1, 5.2).
+ *
+ * Depth v0 of the pair potential -v0 f(|xi|) for which the heavy-light
+ * two-body Hamiltonian -(1/(2 mu_hl)) Lap - v0 f has the eigenvalue -E0
+ * (eq. (1)), i.e. the smallest positive eigenvalue of the generalized problem
+ * (-(1/(2 mu_hl)) Lap + E0) psi = v0 F psi, F = diag f(|xi|).  The relative
+ * coordinate lives on the descriptor's light-particle modes: mode 1 for
+ * ndim = 1 (xi on that grid, |xi| = |y|), modes 2 and 3 for ndim = 2 (their
+ * Cartesian product, |xi| = hypot(y1, y2)), with the descriptor's grid,
+ * parity and D2 overrides; f is the shape of desc->pot (TP3B_POT_GAUSS with
+ * desc->width, TP3B_POT_GAUSS_PAPER or TP3B_POT_LORENTZ3; others: ENOTSUP);
+ * desc->v0 and the heavy-particle modes are ignored.  E0 > 0.  Light-particle
+ * mode sizes at most 1024.  Host computation (no device work, no stream);
+ * ENOCONV if the iteration does not settle or no bound state exists. */
+tp3b_status tp3b_two_body_depth(const tp3b_problem_desc* desc, double E0, double* v0);
+
+/* The whole procedure for count binding energies E0[0], E0[1], ... (in the
+ * paper: decreasing): for each, v0[i] = tp3b_two_body_depth(two_body or, if
+ * NULL, desc; E0[i]); the three-body operator of desc with depth v0[i] and, if
+ * desc->sigma is NaN, the preconditioner shift -E0[i] (the two-body
+ * threshold); and tp3b_jdqr_solve with opts.  Every solve after the first
+ * starts from the previous solve's nev Schur vectors (homotopy, Sec. 5.2).
+ * Outputs are host arrays, each may be NULL: v0[count], evals[count * nev] and
+ * resnorm[count * nev] (row i for E0[i]), n_outer[count].  Synchronous; stops
+ * at the first failing step and returns its status (earlier rows are valid). */
+tp3b_status tp3b_homotopy_solve(const tp3b_problem_desc* desc, const tp3b_problem_desc* two_body,
+                                const tp3b_jdqr_opts* opts, int32_t count, const double* E0,
+                                double* v0, double* evals, double* resnorm, int32_t* n_outer);
+
 /* ---- Batched forms: many independent 1D operators (instances) at once.
  * Every step of the method runs as one grouped, persistent launch over all
  * instances (one launch per tile shape in use): a device job table holds one

@@ -76,7 +76,8 @@ EXPORTS = ["tp3b_create", "tp3b_destroy", "tp3b_op_info", "tp3b_get_D2", "tp3b_g
            "tp3b_apply_H", "tp3b_apply_H_shifted", "tp3b_apply_prec", "tp3b_block_orth",
            "tp3b_jdqr_default_opts", "tp3b_jdqr_solve", "tp3b_host_schur", "tp3b_last_error",
            "tp3b_set_tile", "tp3b_autotune", "tp3b_apply_H_batched", "tp3b_apply_prec_batched",
-           "tp3b_autotune_batched", "tp3b_jdqr_solve_batched"]
+           "tp3b_autotune_batched", "tp3b_jdqr_solve_batched", "tp3b_two_body_depth",
+           "tp3b_homotopy_solve"]
 
 _lib = None
 
@@ -114,6 +115,10 @@ def lib():
                                               ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_int32), pp,
                                               ctypes.POINTER(JdqrStats)]
+        L.tp3b_two_body_depth.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_double, dp]
+        L.tp3b_homotopy_solve.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(ProblemDesc),
+                                          ctypes.POINTER(JdqrOpts), i32, dp, dp, dp, dp,
+                                          ctypes.POINTER(ctypes.c_int32)]
         L.tp3b_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
             if name != "tp3b_last_error":
@@ -155,42 +160,102 @@ def paper_coefficients(alpha):
     return 1.0 / (1.0 + alpha), (1.0 + 2.0 * alpha) / (4.0 * (1.0 + alpha)), 1.0
 
 
+def make_desc(ndim, n, L, c_x=1.0, c_y=1.0, pot="gauss", v0=1.0, width=1.0, sigma=None,
+              mu_hl=1.0, V_table=None, D2=None, grid="cgl", parity=None):
+    """A tp3b_problem_desc and the host arrays it points to (keep them alive
+    while the descriptor is used)."""
+    import numpy as np
+    nm = 2 * ndim
+    n = [n] * nm if isinstance(n, int) else list(n)
+    L = [L] * nm if isinstance(L, (int, float)) else list(L)
+    d = ProblemDesc()
+    d.ndim = ndim
+    for k in range(nm):
+        d.n[k] = int(n[k])
+        d.L[k] = float(L[k])
+    d.c_x, d.c_y = float(c_x), float(c_y)
+    d.pot = POT[pot] if isinstance(pot, str) else int(pot)
+    d.v0, d.width = float(v0), float(width)
+    d.sigma = float("nan") if sigma is None else float(sigma)
+    d.mu_hl = float(mu_hl)
+    d.grid = GRID[grid] if isinstance(grid, str) else int(grid)
+    if parity is not None:
+        for k, p in enumerate(parity):
+            d.parity[k] = int(p)
+    keep = []
+    if V_table is not None:
+        arr = np.ascontiguousarray(V_table, dtype=np.float64).ravel()
+        keep.append(arr)
+        d.V_table = _dbl_ptr(arr)
+        d.pot = POT["table"]
+    if D2 is not None:
+        for k, m in enumerate(D2):
+            if m is not None:
+                arr = np.ascontiguousarray(m, dtype=np.float64)
+                keep.append(arr)
+                d.D2[k] = _dbl_ptr(arr)
+    return d, keep
+
+
+def two_body_depth(E0, ndim, n, L, pot="gauss", width=1.0, mu_hl=1.0, grid="cgl", parity=None,
+                   D2=None):
+    """Depth v0 giving the two-body binding energy E0 on the light-particle
+    modes of the described grid (tp3b_two_body_depth; host computation)."""
+    d, keep = make_desc(ndim, n, L, pot=pot, width=width, mu_hl=mu_hl, grid=grid, parity=parity,
+                        D2=D2)
+    v = ctypes.c_double()
+    _check(lib().tp3b_two_body_depth(ctypes.byref(d), float(E0), ctypes.byref(v)))
+    del keep
+    return v.value
+
+
+def homotopy(E0s, nev, block, ndim, n, L, c_x, c_y, pot="gauss", width=1.0, mu_hl=1.0,
+             grid="cgl", parity=None, sigma=None, two_body=None, inner_prec=FP64, tol=1e-12,
+             seed=0, max_outer=1000, gmres_steps=10, graph=True):
+    """The paper's procedure over binding energies (tp3b_homotopy_solve):
+    depth per E0, three-body solve, each solve started from the previous
+    one.  two_body: optional dict of make_desc arguments for the two-body grid.
+    Returns dict(v0, evals, resnorm, n_outer) with one row per E0."""
+    import numpy as np
+    d, keep = make_desc(ndim, n, L, c_x, c_y, pot=pot, width=width, sigma=sigma, mu_hl=mu_hl,
+                        grid=grid, parity=parity)
+    tb = None
+    if two_body is not None:
+        tb, keep2 = make_desc(**two_body)
+        keep += keep2
+    o = JdqrOpts()
+    _check(lib().tp3b_jdqr_default_opts(ctypes.byref(o)))
+    o.nev, o.block, o.gmres_steps, o.max_outer = nev, block, gmres_steps, max_outer
+    o.inner_prec, o.tol, o.seed, o.graph = inner_prec, tol, seed, int(bool(graph))
+    E = np.ascontiguousarray(E0s, dtype=np.float64)
+    cnt = E.size
+    v0 = np.full(cnt, np.nan)
+    ev = np.full((cnt, nev), np.nan)
+    rn = np.full((cnt, nev), np.nan)
+    no = (ctypes.c_int32 * cnt)()
+    code = lib().tp3b_homotopy_solve(ctypes.byref(d), ctypes.byref(tb) if tb is not None else None,
+                                     ctypes.byref(o), cnt, _dbl_ptr(E), _dbl_ptr(v0), _dbl_ptr(ev),
+                                     _dbl_ptr(rn), no)
+    del keep
+    out = {"v0": v0, "evals": ev, "resnorm": rn, "n_outer": np.array(list(no))}
+    if code != TP3B_OK:
+        err = Tp3bError(code, lib().tp3b_last_error().decode())
+        err.result = out
+        raise err
+    return out
+
+
 class Operator:
     """A discretised three-body Hamiltonian and its preconditioner on the
     current HIP device (a tp3b_op handle)."""
 
     def __init__(self, ndim, n, L, c_x, c_y, pot="gauss", v0=1.0, width=1.0, sigma=None,
                  mu_hl=1.0, V_table=None, D2=None, grid="cgl", parity=None):
-        import numpy as np
+        d, self._keep = make_desc(ndim, n, L, c_x, c_y, pot=pot, v0=v0, width=width, sigma=sigma,
+                                  mu_hl=mu_hl, V_table=V_table, D2=D2, grid=grid, parity=parity)
         nm = 2 * ndim
         n = [n] * nm if isinstance(n, int) else list(n)
         L = [L] * nm if isinstance(L, (int, float)) else list(L)
-        d = ProblemDesc()
-        d.ndim = ndim
-        for k in range(nm):
-            d.n[k] = int(n[k])
-            d.L[k] = float(L[k])
-        d.c_x, d.c_y = float(c_x), float(c_y)
-        d.pot = POT[pot] if isinstance(pot, str) else int(pot)
-        d.v0, d.width = float(v0), float(width)
-        d.sigma = float("nan") if sigma is None else float(sigma)
-        d.mu_hl = float(mu_hl)
-        d.grid = GRID[grid] if isinstance(grid, str) else int(grid)
-        if parity is not None:
-            for k, p in enumerate(parity):
-                d.parity[k] = int(p)
-        self._keep = []
-        if V_table is not None:
-            arr = np.ascontiguousarray(V_table, dtype=np.float64).ravel()
-            self._keep.append(arr)
-            d.V_table = _dbl_ptr(arr)
-            d.pot = POT["table"]
-        if D2 is not None:
-            for k, m in enumerate(D2):
-                if m is not None:
-                    arr = np.ascontiguousarray(m, dtype=np.float64)
-                    self._keep.append(arr)
-                    d.D2[k] = _dbl_ptr(arr)
         h = ctypes.c_void_p()
         _check(lib().tp3b_create(ctypes.byref(d), None, ctypes.byref(h)))
         self.handle = h

@@ -78,6 +78,11 @@ template <typename T>
 tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, int64_t ldy,
                             hipStream_t s, bool bf3 = false);
 int choose_tile(int M, int Nc, int64_t nbatch, bool fp64);
+// Second-derivative matrix (row-major, desc->D2[k] when given) and ascending
+// nodes of mode k of a descriptor.
+void mode_grid(const tp3b_problem_desc* d, int k, std::vector<double>& D2, std::vector<double>& x);
+// u(r) of the descriptor's pair-potential shape with depth v0 and width w.
+double pair_potential(int pot, double r, double v0, double w);
 // Tile shape of an operator's 1D applies: kind 0 = Hamiltonian, 1 = preconditioner.
 int op_tile(tp3b_op op, bool f64, bool bf3, int kind, int64_t nbatch);
 template <typename T>

@@ -135,6 +135,24 @@ static double pair_pot(int pot, double r, double v0, double w) {
   }
 }
 
+double pair_potential(int pot, double r, double v0, double w) { return pair_pot(pot, r, v0, w); }
+
+void mode_grid(const tp3b_problem_desc* d, int k, std::vector<double>& D2, std::vector<double>& x) {
+  const int n = d->n[k];
+  if (d->grid == TP3B_GRID_MAPPED) {
+    if (d->parity[k] == 0) {
+      mapped_second_derivative(n, d->L[k], D2, x);
+    } else {
+      std::vector<double> Df, xf;
+      mapped_second_derivative(2 * n, d->L[k], Df, xf);
+      parity_fold(2 * n, Df, xf, d->parity[k] > 0 ? 1 : -1, D2, x);
+    }
+  } else {
+    cgl_second_derivative(n, d->L[k], D2, x);
+  }
+  if (d->D2[k]) D2.assign(d->D2[k], d->D2[k] + (size_t)n * n);
+}
+
 int choose_tile(int M, int Nc, int64_t nbatch, bool fp64) {
   // Largest tile that still gives >= 1024 workgroups (4 per CU); otherwise the
   // one giving the most parallelism without mostly-empty tiles.
@@ -712,20 +730,7 @@ tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* ou
   for (int k = 0; k < nm; ++k) {
     op->n[k] = desc->n[k];
     op->L[k] = desc->L[k];
-    std::vector<double> D2;
-    if (desc->grid == TP3B_GRID_MAPPED) {
-      if (desc->parity[k] == 0) {
-        mapped_second_derivative(op->n[k], op->L[k], D2, x[k]);
-      } else {
-        std::vector<double> Df, xf;
-        mapped_second_derivative(2 * op->n[k], op->L[k], Df, xf);
-        parity_fold(2 * op->n[k], Df, xf, desc->parity[k] > 0 ? 1 : -1, D2, x[k]);
-      }
-    } else {
-      cgl_second_derivative(op->n[k], op->L[k], D2, x[k]);
-    }
-    if (desc->D2[k]) D2.assign(desc->D2[k], desc->D2[k] + (size_t)op->n[k] * op->n[k]);
-    op->D2h[k] = D2;
+    mode_grid(desc, k, op->D2h[k], x[k]);
   }
   // Potential V = u(|y - x/2|) + u(|y + x/2|) on the tensor grid (eq. (3)).
   op->Vh.resize(N);
