@@ -96,7 +96,7 @@ def cpu_baseline(cfg, name, sample_iters, full_iters, gmres_steps):
                        f"NumPy/SciPy FP64, {threads} BLAS threads")}
 
 
-def batched_leg(reps, n_seq):
+def batched_leg(reps, n_seq, gmres_steps):
     """The 256-instance workload c4: one batched JDQR solve (grouped persistent
     launches, GMRES iteration replayed as a HIP graph) per repetition, for each
     inner precision; eigenvalues against the oracle's stored values; and the
@@ -117,13 +117,15 @@ def batched_leg(reps, n_seq):
     for pk in (t3.FP64, t3.FP32, t3.BF16X3):
         t3.autotune_batched(ops, pk, nvec=4, reps=2)
     t_tune = time.perf_counter() - t0
-    res = {"instances": len(ops), "nev": 4, "block": 4, "create_s": t_create, "autotune_s": t_tune}
+    res = {"instances": len(ops), "nev": 4, "block": 4, "gmres_steps": gmres_steps,
+           "create_s": t_create, "autotune_s": t_tune}
+    kw = dict(seed=1000, tol=C4_TOL, gmres_steps=gmres_steps)
     for name, pk in (("fp64", t3.FP64), ("fp32", t3.FP32), ("bf16x3", t3.BF16X3)):
-        t3.jdqr_batched(ops, 4, 4, inner_prec=pk, seed=1000, tol=C4_TOL)  # warm-up
+        t3.jdqr_batched(ops, 4, 4, inner_prec=pk, **kw)  # warm-up
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(reps):
-            r = t3.jdqr_batched(ops, 4, 4, inner_prec=pk, seed=1000, tol=C4_TOL)
+            r = t3.jdqr_batched(ops, 4, 4, inner_prec=pk, **kw)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t1) / reps
         err = (float(np.max(np.abs(r.evals - gold) / np.maximum(np.abs(gold), 1.0)))
@@ -136,7 +138,8 @@ def batched_leg(reps, n_seq):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for op in ops[:n_seq]:
-            op.jdqr(4, 4, inner_prec=t3.FP32, seed=0, want_Q=False, tol=C4_TOL)
+            op.jdqr(4, 4, inner_prec=t3.FP32, seed=0, want_Q=False, tol=C4_TOL,
+                    gmres_steps=gmres_steps)
         torch.cuda.synchronize()
         per = (time.perf_counter() - t1) / n_seq
         res["sequential_fp32"] = {"instances": n_seq, "s_per_instance": per,
@@ -258,7 +261,7 @@ def main():
                                 "mixed_outer_iters": mres[-1].stats["n_outer"],
                                 "mixed_eig_max_rel_err_vs_oracle": m_err}
     if not args.no_batched:
-        out["batched_c4"] = batched_leg(args.batched_reps, args.batched_seq)
+        out["batched_c4"] = batched_leg(args.batched_reps, args.batched_seq, args.gmres_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.config, args.cpu_sample_iters,
                                            res[-1].stats["n_outer"], args.gmres_steps)
