@@ -191,6 +191,33 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   TP3B_HIP(dalloc(Wb, sizeof(TW) * N * b));
   TP3B_HIP(dalloc(Zb, sizeof(TW) * N * b));
   TP3B_HIP(dalloc(Tcb, sizeof(double) * N * b));
+  // Pinned host staging for the small transfers of an outer iteration: copies
+  // to and from pinned memory are asynchronous, so uploads do not wait for the
+  // stream and a group of read-backs costs one synchronisation.  Every transfer
+  // site has a region of its own, rewritten only after a stream
+  // synchronisation that follows its previous copy.
+  struct PinnedHost {
+    double* p = nullptr;
+    ~PinnedHost() {
+      if (p) (void)hipHostFree(p);
+    }
+  } pin;
+  size_t pin_used = 0;
+  auto region = [&](size_t n) {
+    const size_t o = pin_used;
+    pin_used += (n + 7) & ~(size_t)7;
+    return o;
+  };
+  const size_t mb = (size_t)(m_max + b), big = (size_t)(qt_max + m_max + b);
+  const size_t r_upS = region(mb * mb), r_upT = region(mb * b), r_upShift = region(b),
+               r_upHinv = region((size_t)qt_max * qt_max), r_upY = region((size_t)b * (steps + 2)),
+               r_dnM = region(big * big), r_dnC1 = region((size_t)nev * b),
+               r_dnC2 = region((size_t)nev * b), r_dnRn = region(b),
+               r_dnH1 = region((size_t)steps * b * (steps + 2)),
+               r_dnH2 = region((size_t)steps * b * (steps + 2)), r_dnHs = region((size_t)steps * b),
+               r_dnBeta = region(b), r_dnTop = region(mb * b), r_dnLeft = region(mb * b);
+  TP3B_HIP(hipHostMalloc((void**)&pin.p, sizeof(double) * pin_used, hipHostMallocDefault));
+  auto P = [&](size_t r) { return pin.p + r; };
   // Declared after the buffers, so destroyed before them: on every return the
   // solve's stream has finished with them before they are freed.
   struct StreamDrain {
@@ -262,8 +289,9 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     // host (row-major p x q) = A^T B
     TP3B_HIP(launch_dot_tn<double, double>(N, p, q, A, N, B, N, dM2, p, part, s));
     std::vector<double> cm((size_t)p * q);
-    TP3B_HIP(hipMemcpyAsync(cm.data(), dM2, sizeof(double) * p * q, hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipMemcpyAsync(P(r_dnM), dM2, sizeof(double) * p * q, hipMemcpyDeviceToHost, s));
     TP3B_HIP(hipStreamSynchronize(s));
+    std::memcpy(cm.data(), P(r_dnM), sizeof(double) * p * q);
     host.assign((size_t)p * ldc, 0.0);
     for (int i = 0; i < p; ++i)
       for (int j = 0; j < q; ++j) host[(size_t)i * ldc + j] = cm[i + (size_t)j * p];
@@ -322,7 +350,8 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
         if (S[(size_t)i * m + j] != (i == j ? 1.0 : 0.0)) { ident = false; break; }
     if (!ident) {
       std::vector<double> Sc = colmajor(S, m, 0, 0, m, m);
-      TP3B_HIP(hipMemcpyAsync(dS, Sc.data(), sizeof(double) * m * m, hipMemcpyHostToDevice, s));
+      std::memcpy(P(r_upS), Sc.data(), sizeof(double) * m * m);
+      TP3B_HIP(hipMemcpyAsync(dS, P(r_upS), sizeof(double) * m * m, hipMemcpyHostToDevice, s));
       TP3B_HIP(launch_gemm_nn<double>(N, m, m, 1.0, V(), N, dS, m, 0.0, TMP, N, s));
       TP3B_HIP(hipMemcpyAsync(V(), TMP, sizeof(double) * N * m, hipMemcpyDeviceToDevice, s));
       TP3B_HIP(launch_gemm_nn<double>(N, m, m, 1.0, AV(), N, dS, m, 0.0, TMP, N, s));
@@ -334,7 +363,8 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     TP3B_HIP(hipMemcpyAsync(Rres, AV(), sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
     {
       std::vector<double> Tc_ = colmajor(T, m, 0, 0, m, nb);
-      TP3B_HIP(hipMemcpyAsync(dS, Tc_.data(), sizeof(double) * m * nb, hipMemcpyHostToDevice, s));
+      std::memcpy(P(r_upT), Tc_.data(), sizeof(double) * m * nb);
+      TP3B_HIP(hipMemcpyAsync(dS, P(r_upT), sizeof(double) * m * nb, hipMemcpyHostToDevice, s));
       TP3B_HIP(launch_gemm_nn<double>(N, m, nb, -1.0, V(), N, dS, m, 1.0, Rres, N, s));
     }
     std::vector<double> Cq((size_t)std::max(k, 1) * nb, 0.0);  // Q^T A U, column-major k x nb
@@ -345,13 +375,18 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       TP3B_HIP(launch_gemm_nn<double>(N, k, nb, -1.0, QV, N, dC, k, 1.0, Rres, N, s));
       TP3B_HIP(launch_dot_tn<double, double>(N, k, nb, QV, N, Rres, N, dC2, k, part, s));
       TP3B_HIP(launch_gemm_nn<double>(N, k, nb, -1.0, QV, N, dC2, k, 1.0, Rres, N, s));
-      TP3B_HIP(hipMemcpyAsync(c1.data(), dC, sizeof(double) * k * nb, hipMemcpyDeviceToHost, s));
-      TP3B_HIP(hipMemcpyAsync(c2.data(), dC2, sizeof(double) * k * nb, hipMemcpyDeviceToHost, s));
+      TP3B_HIP(hipMemcpyAsync(P(r_dnC1), dC, sizeof(double) * k * nb, hipMemcpyDeviceToHost, s));
+      TP3B_HIP(hipMemcpyAsync(P(r_dnC2), dC2, sizeof(double) * k * nb, hipMemcpyDeviceToHost, s));
     }
     TP3B_HIP(launch_bdot_diag<double>(N, nb, 1, Rres, 0, Rres, dNrm, 1, part, s));
     std::vector<double> rn(nb);
-    TP3B_HIP(hipMemcpyAsync(rn.data(), dNrm, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipMemcpyAsync(P(r_dnRn), dNrm, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
     TP3B_HIP(hipStreamSynchronize(s));
+    std::memcpy(rn.data(), P(r_dnRn), sizeof(double) * nb);
+    if (k > 0) {
+      std::memcpy(c1.data(), P(r_dnC1), sizeof(double) * k * nb);
+      std::memcpy(c2.data(), P(r_dnC2), sizeof(double) * k * nb);
+    }
     if (k > 0)
       for (size_t e = 0; e < (size_t)k * nb; ++e) Cq[e] = c1[e] + c2[e];
     for (int j = 0; j < nb; ++j) rn[j] = std::sqrt(std::max(rn[j], 0.0));
@@ -434,7 +469,8 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     const double tfar = (k == 0 && outer <= o.low_start) ? op->spec_lo : target;
     for (int j = 0; j < nb; ++j)
       shift[j] = (rn[j] > o.switch_tol * std::fabs(theta[j])) ? tfar : theta[j];
-    TP3B_HIP(hipMemcpyAsync(dShift, shift.data(), sizeof(double) * nb, hipMemcpyHostToDevice, s));
+    std::memcpy(P(r_upShift), shift.data(), sizeof(double) * nb);
+    TP3B_HIP(hipMemcpyAsync(dShift, P(r_upShift), sizeof(double) * nb, hipMemcpyHostToDevice, s));
     const int nqt = k + nb;  // Q~ = QV[:, 0:nqt]
     const double* Qt = QV;
     const double* Yq = Qt;   // P^{-1} Q~ H^{-1} (or Q~ without preconditioner)
@@ -451,7 +487,8 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       if (!lu_inverse(nqt, Hh.data(), Hi.data()))
         return fail(TP3B_ENOCONV, "jdqr: singular projected preconditioner");
       std::vector<double> Hic = colmajor(Hi, nqt, 0, 0, nqt, nqt);
-      TP3B_HIP(hipMemcpyAsync(dHinv, Hic.data(), sizeof(double) * nqt * nqt, hipMemcpyHostToDevice, s));
+      std::memcpy(P(r_upHinv), Hic.data(), sizeof(double) * nqt * nqt);
+      TP3B_HIP(hipMemcpyAsync(dHinv, P(r_upHinv), sizeof(double) * nqt * nqt, hipMemcpyHostToDevice, s));
       TP3B_HIP(launch_gemm_nn<double>(N, nqt, nqt, 1.0, PQ, N, dHinv, nqt, 0.0, Yp, N, s));
       Yq = Yp;
     }
@@ -563,11 +600,15 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     }
     std::vector<double> hH1((size_t)steps * b * hld), hH2((size_t)steps * b * hld),
         hHs((size_t)steps * b), hBeta(b);
-    TP3B_HIP(hipMemcpyAsync(hH1.data(), dH1, sizeof(double) * hH1.size(), hipMemcpyDeviceToHost, s));
-    TP3B_HIP(hipMemcpyAsync(hH2.data(), dH2, sizeof(double) * hH2.size(), hipMemcpyDeviceToHost, s));
-    TP3B_HIP(hipMemcpyAsync(hHs.data(), dHs, sizeof(double) * hHs.size(), hipMemcpyDeviceToHost, s));
-    TP3B_HIP(hipMemcpyAsync(hBeta.data(), dBeta, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipMemcpyAsync(P(r_dnH1), dH1, sizeof(double) * hH1.size(), hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipMemcpyAsync(P(r_dnH2), dH2, sizeof(double) * hH2.size(), hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipMemcpyAsync(P(r_dnHs), dHs, sizeof(double) * hHs.size(), hipMemcpyDeviceToHost, s));
+    TP3B_HIP(hipMemcpyAsync(P(r_dnBeta), dBeta, sizeof(double) * b, hipMemcpyDeviceToHost, s));
     TP3B_HIP(hipStreamSynchronize(s));
+    std::memcpy(hH1.data(), P(r_dnH1), sizeof(double) * hH1.size());
+    std::memcpy(hH2.data(), P(r_dnH2), sizeof(double) * hH2.size());
+    std::memcpy(hHs.data(), P(r_dnHs), sizeof(double) * hHs.size());
+    std::memcpy(hBeta.data(), P(r_dnBeta), sizeof(double) * b);
     // Least squares per column; y stored as H-like layout yv[j*hld + i].
     std::vector<double> yv((size_t)b * hld, 0.0);
     int ksteps_max = 0;
@@ -591,12 +632,12 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       for (int i = 0; i < ks; ++i) yv[(size_t)j * hld + i] = y[i];
       ksteps_max = std::max(ksteps_max, ks);
     }
-    TP3B_HIP(hipMemcpyAsync(dY, yv.data(), sizeof(double) * b * hld, hipMemcpyHostToDevice, s));
+    std::memcpy(P(r_upY), yv.data(), sizeof(double) * b * hld);
+    TP3B_HIP(hipMemcpyAsync(dY, P(r_upY), sizeof(double) * b * hld, hipMemcpyHostToDevice, s));
     TP3B_HIP(hipMemsetAsync(W, 0, sizeof(TW) * N * nb, s));
     TP3B_HIP(launch_bupdate_diag<TW>(N, nb, ksteps_max, 1.0, Vg, bs, dY, hld, W, s));
     TP3B_HIP((launch_convert<TW, double>(N, nb, 1.0, W, N, Tc, N, s)));
-    TP3B_HIP(hipStreamSynchronize(s));
-    stats.t_gmres += now() - tg0;
+    stats.t_gmres += now() - tg0;  // host time; the device work is still queued
 
     // ---- 5. expand the basis
     double to = now();
@@ -619,10 +660,12 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       std::vector<double> ct((size_t)(m + nb) * nb), cl((size_t)nb * m);
       TP3B_HIP(launch_dot_tn<double, double>(N, m + nb, nb, V(), N, AV() + (int64_t)m * N, N, dM2,
                                              m + nb, part, s));
-      TP3B_HIP(hipMemcpyAsync(ct.data(), dM2, sizeof(double) * ct.size(), hipMemcpyDeviceToHost, s));
+      TP3B_HIP(hipMemcpyAsync(P(r_dnTop), dM2, sizeof(double) * ct.size(), hipMemcpyDeviceToHost, s));
       TP3B_HIP(launch_dot_tn<double, double>(N, nb, m, Vn, N, AV(), N, dS, nb, part, s));
-      TP3B_HIP(hipMemcpyAsync(cl.data(), dS, sizeof(double) * cl.size(), hipMemcpyDeviceToHost, s));
+      TP3B_HIP(hipMemcpyAsync(P(r_dnLeft), dS, sizeof(double) * cl.size(), hipMemcpyDeviceToHost, s));
       TP3B_HIP(hipStreamSynchronize(s));
+      std::memcpy(ct.data(), P(r_dnTop), sizeof(double) * ct.size());
+      std::memcpy(cl.data(), P(r_dnLeft), sizeof(double) * cl.size());
       for (int i = 0; i < m + nb; ++i)
         for (int j = 0; j < nb; ++j) top[(size_t)i * nb + j] = ct[i + (size_t)j * (m + nb)];
       for (int i = 0; i < nb; ++i)
