@@ -656,8 +656,12 @@ __device__ __forceinline__ void bupdate_row(int64_t N, int nb, double alpha,
                                             T* __restrict__ W, int64_t r, int j) {
   if (r >= N) return;
   double s = 0.0;
-  for (int i = 0; i < nb; ++i)
-    s += (double)V[(int64_t)i * bs + (int64_t)j * N + r] * H[(int64_t)j * hld + i];
+  for (int i = 0; i < nb; ++i) {
+    // an exactly zero coefficient (past a GMRES breakdown) contributes nothing,
+    // whatever the basis vector holds
+    const double h = H[(int64_t)j * hld + i];
+    if (h != 0.0) s += (double)V[(int64_t)i * bs + (int64_t)j * N + r] * h;
+  }
   T* w = W + (int64_t)j * N + r;
   *w = (T)((double)(*w) + alpha * s);
 }

@@ -210,12 +210,10 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   };
   const size_t mb = (size_t)(m_max + b), big = (size_t)(qt_max + m_max + b);
   const size_t r_upS = region(mb * mb), r_upT = region(mb * b), r_upShift = region(b),
-               r_upHinv = region((size_t)qt_max * qt_max), r_upY = region((size_t)b * (steps + 2)),
-               r_dnM = region(big * big), r_dnC1 = region((size_t)nev * b),
-               r_dnC2 = region((size_t)nev * b), r_dnRn = region(b),
-               r_dnH1 = region((size_t)steps * b * (steps + 2)),
-               r_dnH2 = region((size_t)steps * b * (steps + 2)), r_dnHs = region((size_t)steps * b),
-               r_dnBeta = region(b), r_dnTop = region(mb * b), r_dnLeft = region(mb * b);
+               r_upHinv = region((size_t)qt_max * qt_max), r_dnM = region(big * big),
+               r_dnC1 = region((size_t)nev * b), r_dnC2 = region((size_t)nev * b),
+               r_dnRn = region(b), r_dnTop = region(mb * b), r_dnLeft = region(mb * b),
+               r_dnFlag = region(1);
   TP3B_HIP(hipHostMalloc((void**)&pin.p, sizeof(double) * pin_used, hipHostMallocDefault));
   auto P = [&](size_t r) { return pin.p + r; };
   // Declared after the buffers, so destroyed before them: on every return the
@@ -228,7 +226,7 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   const int hld = steps + 2;
   const size_t n_small = (size_t)(m_max + b) * (m_max + b) * 2 + (size_t)qt_max * qt_max +
                          (size_t)qt_max * b * 2 + (size_t)steps * b * hld * 2 + (size_t)steps * b +
-                         (size_t)b * 4 + (size_t)(steps + 1) * b + 64;
+                         (size_t)b * 4 + (size_t)hld * b + 64;
   TP3B_HIP(dalloc(smallb, sizeof(double) * n_small));
   double* QV = QVb.as<double>();
   double* AVbase = AVb.as<double>();
@@ -251,7 +249,9 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   double* dShift = dHs + (size_t)steps * b;                          // b
   double* dNrm = dShift + b;                                         // b
   double* dBeta = dNrm + b;                                          // b
-  double* dY = dBeta + 2 * b;                                        // (steps+1)*b
+  double* dY = dBeta + 2 * b;                                        // b*hld
+  int* dFlag = (int*)(dY + (size_t)b * hld);  // singular projected preconditioner
+  TP3B_HIP(hipMemsetAsync(dFlag, 0, sizeof(int), s));
   const int64_t dscr = dot_scratch_doubles(N, qt_max + m_max + b, qt_max + m_max + b) +
                        bdot_scratch_doubles(N, b, steps + 2) + 8 * (int64_t)(qv_cols + 1) * b +
                        8 * (int64_t)b * b + 1024;
@@ -480,15 +480,22 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       if (ps != TP3B_OK) return ps;
       stats.n_apply_prec += nb;
       stats.t_prec += now() - tp;
-      std::vector<double> Hh;
-      tp3b_status ds = dot(nqt, nqt, Qt, PQ, Hh, nqt);
-      if (ds != TP3B_OK) return ds;
-      std::vector<double> Hi((size_t)nqt * nqt);
-      if (!lu_inverse(nqt, Hh.data(), Hi.data()))
-        return fail(TP3B_ENOCONV, "jdqr: singular projected preconditioner");
-      std::vector<double> Hic = colmajor(Hi, nqt, 0, 0, nqt, nqt);
-      std::memcpy(P(r_upHinv), Hic.data(), sizeof(double) * nqt * nqt);
-      TP3B_HIP(hipMemcpyAsync(dHinv, P(r_upHinv), sizeof(double) * nqt * nqt, hipMemcpyHostToDevice, s));
+      if (nqt <= SI_MAXN) {
+        // H = Q~^T P^{-1} Q~ inverted on the device (no host round trip); a
+        // singular H is reported by dFlag at the end of the outer iteration
+        TP3B_HIP((launch_dot_tn<double, double>(N, nqt, nqt, Qt, N, PQ, N, dM2, nqt, part, s)));
+        TP3B_HIP(launch_small_inverse(nqt, dM2, dHinv, dFlag, s));
+      } else {
+        std::vector<double> Hh;
+        tp3b_status ds = dot(nqt, nqt, Qt, PQ, Hh, nqt);
+        if (ds != TP3B_OK) return ds;
+        std::vector<double> Hi((size_t)nqt * nqt);
+        if (!lu_inverse(nqt, Hh.data(), Hi.data()))
+          return fail(TP3B_ENOCONV, "jdqr: singular projected preconditioner");
+        std::vector<double> Hic = colmajor(Hi, nqt, 0, 0, nqt, nqt);
+        std::memcpy(P(r_upHinv), Hic.data(), sizeof(double) * nqt * nqt);
+        TP3B_HIP(hipMemcpyAsync(dHinv, P(r_upHinv), sizeof(double) * nqt * nqt, hipMemcpyHostToDevice, s));
+      }
       TP3B_HIP(launch_gemm_nn<double>(N, nqt, nqt, 1.0, PQ, N, dHinv, nqt, 0.0, Yp, N, s));
       Yq = Yp;
     }
@@ -555,6 +562,11 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
         TP3B_HIP(launch_normalize_cols<TW>(N, nb, dNrm, w, Vg + (int64_t)(kk + 1) * bs,
                                            dHs + (size_t)kk * b, 1, s));
       }
+      // least squares on the device, then t_j = V_j y_j (FP64 copy in Tc)
+      TP3B_HIP(launch_gmres_lstsq(nb, b, steps, hld, dH1, dH2, dHs, dBeta, dY, s));
+      TP3B_HIP((launch_convert<TW, TW>(N, nb, 0.0, (const TW*)nullptr, N, W, N, s)));
+      TP3B_HIP(launch_bupdate_diag<TW>(N, nb, steps, 1.0, Vg, bs, dY, hld, W, s));
+      TP3B_HIP((launch_convert<TW, double>(N, nb, 1.0, W, N, Tc, N, s)));
       return TP3B_OK;
     };
     if (o.graph) {
@@ -598,45 +610,6 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       tp3b_status gs = gmres_launch();
       if (gs != TP3B_OK) return gs;
     }
-    std::vector<double> hH1((size_t)steps * b * hld), hH2((size_t)steps * b * hld),
-        hHs((size_t)steps * b), hBeta(b);
-    TP3B_HIP(hipMemcpyAsync(P(r_dnH1), dH1, sizeof(double) * hH1.size(), hipMemcpyDeviceToHost, s));
-    TP3B_HIP(hipMemcpyAsync(P(r_dnH2), dH2, sizeof(double) * hH2.size(), hipMemcpyDeviceToHost, s));
-    TP3B_HIP(hipMemcpyAsync(P(r_dnHs), dHs, sizeof(double) * hHs.size(), hipMemcpyDeviceToHost, s));
-    TP3B_HIP(hipMemcpyAsync(P(r_dnBeta), dBeta, sizeof(double) * b, hipMemcpyDeviceToHost, s));
-    TP3B_HIP(hipStreamSynchronize(s));
-    std::memcpy(hH1.data(), P(r_dnH1), sizeof(double) * hH1.size());
-    std::memcpy(hH2.data(), P(r_dnH2), sizeof(double) * hH2.size());
-    std::memcpy(hHs.data(), P(r_dnHs), sizeof(double) * hHs.size());
-    std::memcpy(hBeta.data(), P(r_dnBeta), sizeof(double) * b);
-    // Least squares per column; y stored as H-like layout yv[j*hld + i].
-    std::vector<double> yv((size_t)b * hld, 0.0);
-    int ksteps_max = 0;
-    for (int j = 0; j < nb; ++j) {
-      const double beta = hBeta[j];
-      if (!(beta > 0)) continue;
-      int ks = 0;
-      for (int kk = 0; kk < steps; ++kk) {
-        ks = kk + 1;
-        if (!(hHs[(size_t)kk * b + j] > 1e-14 * beta)) break;
-      }
-      std::vector<double> Hm((size_t)(ks + 1) * ks, 0.0);
-      for (int kk = 0; kk < ks; ++kk) {
-        const double* a1 = hH1.data() + (size_t)kk * b * hld + (size_t)j * hld;
-        const double* a2 = hH2.data() + (size_t)kk * b * hld + (size_t)j * hld;
-        for (int i = 0; i <= kk; ++i) Hm[(size_t)i * ks + kk] = a1[i] + a2[i];
-        Hm[(size_t)(kk + 1) * ks + kk] = hHs[(size_t)kk * b + j];
-      }
-      std::vector<double> y(ks);
-      hessenberg_lstsq(ks, Hm.data(), ks, beta, y.data());
-      for (int i = 0; i < ks; ++i) yv[(size_t)j * hld + i] = y[i];
-      ksteps_max = std::max(ksteps_max, ks);
-    }
-    std::memcpy(P(r_upY), yv.data(), sizeof(double) * b * hld);
-    TP3B_HIP(hipMemcpyAsync(dY, P(r_upY), sizeof(double) * b * hld, hipMemcpyHostToDevice, s));
-    TP3B_HIP(hipMemsetAsync(W, 0, sizeof(TW) * N * nb, s));
-    TP3B_HIP(launch_bupdate_diag<TW>(N, nb, ksteps_max, 1.0, Vg, bs, dY, hld, W, s));
-    TP3B_HIP((launch_convert<TW, double>(N, nb, 1.0, W, N, Tc, N, s)));
     stats.t_gmres += now() - tg0;  // host time; the device work is still queued
 
     // ---- 5. expand the basis
@@ -663,7 +636,9 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       TP3B_HIP(hipMemcpyAsync(P(r_dnTop), dM2, sizeof(double) * ct.size(), hipMemcpyDeviceToHost, s));
       TP3B_HIP(launch_dot_tn<double, double>(N, nb, m, Vn, N, AV(), N, dS, nb, part, s));
       TP3B_HIP(hipMemcpyAsync(P(r_dnLeft), dS, sizeof(double) * cl.size(), hipMemcpyDeviceToHost, s));
+      TP3B_HIP(hipMemcpyAsync(P(r_dnFlag), dFlag, sizeof(int), hipMemcpyDeviceToHost, s));
       TP3B_HIP(hipStreamSynchronize(s));
+      if (*(const int*)P(r_dnFlag)) return fail(TP3B_ENOCONV, "jdqr: singular projected preconditioner");
       std::memcpy(ct.data(), P(r_dnTop), sizeof(double) * ct.size());
       std::memcpy(cl.data(), P(r_dnLeft), sizeof(double) * cl.size());
       for (int i = 0; i < m + nb; ++i)

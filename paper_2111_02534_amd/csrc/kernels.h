@@ -77,6 +77,18 @@ template <typename T>
 hipError_t launch_bdot_diag(int64_t N, int b, int nb, const T* V, int64_t bs, const T* W,
                             double* H, int hld, double* partial, hipStream_t s);
 int64_t bdot_scratch_doubles(int64_t N, int b, int nb);
+// GMRES least squares for nb correction columns on the device: from the
+// Arnoldi coefficients H1, H2 ([kk*b*hld + j*hld + i], two Gram-Schmidt
+// passes), the subdiagonal norms Hs[kk*b + j] and the initial norms Beta[j],
+// Y[j*hld + i] = argmin || Beta_j e1 - H_j y || (zero past the first
+// breakdown).  steps <= GL_MAXSTEPS.
+constexpr int GL_MAXSTEPS = 38;
+hipError_t launch_gmres_lstsq(int nb, int b, int steps, int hld, const double* H1, const double* H2,
+                              const double* Hs, const double* Beta, double* Y, hipStream_t s);
+// Ainv = A^{-1} for an n x n column-major matrix, n <= SI_MAXN (Gauss-Jordan
+// with partial pivoting, one wavefront); *singular = 1 on an exactly zero pivot.
+constexpr int SI_MAXN = 48;
+hipError_t launch_small_inverse(int n, const double* A, double* Ainv, int* singular, hipStream_t s);
 // W[r, j] += alpha * sum_{i<nb} Vb[i][r, j] H[j*hld + i]
 template <typename T>
 hipError_t launch_bupdate_diag(int64_t N, int b, int nb, double alpha, const T* V, int64_t bs,
@@ -87,7 +99,7 @@ template <typename T>
 hipError_t launch_normalize_cols(int64_t N, int b, const double* nrm2, const T* W, T* Vout,
                                  double* hout, int hld, hipStream_t s);
 
-// Y[:, j] = alpha * X[:, j] (type conversion included).
+// Y[:, j] = alpha * X[:, j] (type conversion included); X == nullptr: Y = 0.
 template <typename TI, typename TO>
 hipError_t launch_convert(int64_t N, int ncol, double alpha, const TI* X, int64_t ldx, TO* Y,
                           int64_t ldy, hipStream_t s);

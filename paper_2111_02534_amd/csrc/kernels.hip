@@ -313,7 +313,7 @@ __global__ void k_convert(int64_t N, double alpha, const TI* __restrict__ X, int
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int j = blockIdx.y;
   if (r >= N) return;
-  Y[r + (int64_t)j * ldy] = (TO)(alpha * (double)X[r + (int64_t)j * ldx]);
+  Y[r + (int64_t)j * ldy] = X ? (TO)(alpha * (double)X[r + (int64_t)j * ldx]) : (TO)0;
 }
 
 template <typename TI, typename TO>
@@ -414,5 +414,140 @@ template hipError_t launch_check_finite<double>(int64_t, int, const double*, int
                                                 hipStream_t);
 template hipError_t launch_check_finite<float>(int64_t, int, const float*, int64_t, int*,
                                                hipStream_t);
+
+// ------------------------------------------------ small dense steps on the device
+// GMRES least squares, one workgroup per correction column j: ks is the number
+// of steps before the first breakdown (subdiagonal <= 1e-14 beta), the
+// (ks + 1) x ks Hessenberg matrix (sum of the two Gram-Schmidt passes, then the
+// subdiagonal norms) is assembled in LDS, and one thread minimises
+// || beta e1 - H y || by Givens rotations and back substitution.
+// Y[j*hld + i] = y_i for i < ks, 0 up to hld; beta == 0 gives y = 0.
+__global__ __launch_bounds__(64) void k_gmres_lstsq(int b, int steps, int hld,
+                                                    const double* __restrict__ H1,
+                                                    const double* __restrict__ H2,
+                                                    const double* __restrict__ Hs,
+                                                    const double* __restrict__ Beta,
+                                                    double* __restrict__ Y) {
+  __shared__ double R[(GL_MAXSTEPS + 1) * GL_MAXSTEPS];
+  __shared__ double g[GL_MAXSTEPS + 1];
+  __shared__ double y[GL_MAXSTEPS];
+  __shared__ int ks_s;
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const double beta = Beta[j];
+  if (tid == 0) {
+    int ks = 0;
+    if (beta > 0)
+      for (int kk = 0; kk < steps; ++kk) {
+        ks = kk + 1;
+        if (!(Hs[(int64_t)kk * b + j] > 1e-14 * beta)) break;
+      }
+    ks_s = ks;
+  }
+  __syncthreads();
+  const int ks = ks_s;
+  for (int e = tid; e < (ks + 1) * ks; e += 64) {
+    const int i = e / ks, kk = e % ks;
+    double v = 0.0;
+    if (i <= kk) {
+      const int64_t o = (int64_t)kk * b * hld + (int64_t)j * hld + i;
+      v = H1[o] + H2[o];
+    } else if (i == kk + 1) {
+      v = Hs[(int64_t)kk * b + j];
+    }
+    R[e] = v;
+  }
+  __syncthreads();
+  if (tid == 0 && ks > 0) {
+    for (int i = 0; i <= ks; ++i) g[i] = 0.0;
+    g[0] = beta;
+    for (int c = 0; c < ks; ++c) {
+      const double a = R[c * ks + c], d = R[(c + 1) * ks + c];
+      const double r = hypot(a, d);
+      const double cs = (r == 0) ? 1.0 : a / r, sn = (r == 0) ? 0.0 : d / r;
+      for (int cc = c; cc < ks; ++cc) {
+        const double u = R[c * ks + cc], v = R[(c + 1) * ks + cc];
+        R[c * ks + cc] = cs * u + sn * v;
+        R[(c + 1) * ks + cc] = -sn * u + cs * v;
+      }
+      const double u = g[c], v = g[c + 1];
+      g[c] = cs * u + sn * v;
+      g[c + 1] = -sn * u + cs * v;
+    }
+    for (int i = ks - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int c = i + 1; c < ks; ++c) acc -= R[i * ks + c] * y[c];
+      const double dd = R[i * ks + i];
+      y[i] = (dd != 0.0) ? acc / dd : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < hld; i += 64) Y[(int64_t)j * hld + i] = (i < ks) ? y[i] : 0.0;
+}
+
+hipError_t launch_gmres_lstsq(int nb, int b, int steps, int hld, const double* H1, const double* H2,
+                              const double* Hs, const double* Beta, double* Y, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  if (steps < 1 || steps > GL_MAXSTEPS || hld < steps) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gmres_lstsq, dim3(nb), dim3(64), 0, s, b, steps, hld, H1, H2, Hs, Beta, Y);
+  return hipGetLastError();
+}
+
+// Inverse of an n x n column-major matrix, n <= SI_MAXN, by Gauss-Jordan
+// elimination with partial pivoting on [A | I] in LDS; one wavefront, thread t
+// owns row t in the elimination.  *singular = 1 (else 0) when a pivot column
+// is exactly zero; Ainv is then not meaningful.
+__global__ __launch_bounds__(64) void k_small_inverse(int n, const double* __restrict__ A,
+                                                      double* __restrict__ Ainv,
+                                                      int* __restrict__ singular) {
+  __shared__ double M[SI_MAXN][2 * SI_MAXN + 1];
+  __shared__ int piv;
+  __shared__ int bad;
+  const int t = threadIdx.x, w = 2 * n;
+  if (t == 0) bad = 0;
+  for (int e = t; e < n * w; e += 64) {
+    const int r = e / w, c = e % w;
+    M[r][c] = (c < n) ? A[r + (int64_t)c * n] : (c - n == r ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (t == 0) {
+      int p = k;
+      for (int r = k + 1; r < n; ++r)
+        if (fabs(M[r][k]) > fabs(M[p][k])) p = r;
+      piv = p;
+      if (M[p][k] == 0.0) bad = 1;
+    }
+    __syncthreads();
+    if (bad) break;
+    const int p = piv;
+    if (p != k)
+      for (int c = t; c < w; c += 64) {
+        const double u = M[k][c];
+        M[k][c] = M[p][c];
+        M[p][c] = u;
+      }
+    __syncthreads();
+    const double d = M[k][k];
+    __syncthreads();
+    for (int c = t; c < w; c += 64) M[k][c] /= d;
+    __syncthreads();
+    if (t < n && t != k) {
+      const double f = M[t][k];
+      for (int c = 0; c < w; ++c) M[t][c] -= f * M[k][c];
+    }
+    __syncthreads();
+  }
+  if (t == 0) *singular = bad;
+  for (int e = t; e < n * n; e += 64) {
+    const int r = e % n, c = e / n;
+    Ainv[r + (int64_t)c * n] = M[r][n + c];
+  }
+}
+
+hipError_t launch_small_inverse(int n, const double* A, double* Ainv, int* singular, hipStream_t s) {
+  if (n < 1 || n > SI_MAXN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_small_inverse, dim3(1), dim3(64), 0, s, n, A, Ainv, singular);
+  return hipGetLastError();
+}
 
 }  // namespace tp3b
