@@ -1,0 +1,99 @@
+"""GPU edge cases: empty blocks, the smallest grids, and the degenerate
+physics where the spectrum is known in closed form.
+
+* Empty blocks (no vectors, no columns) are valid calls that do nothing.
+* A 3 x 3 grid (N = 9, just above the nev + m_max + block basis the solver
+  keeps) exercises every kernel on tiles that are almost entirely padding, and
+  a solve whose search space fills the whole space.
+* V0 = 0 (free three-body system): the eigenvalues are c_x (j pi/2L)^2 +
+  c_y (l pi/2L)^2 on the Gauss-Lobatto grid up to its own error (the oracle's
+  pin shows 1e-10 at this grid), and the kinetic preconditioner is then the
+  exact inverse of H - sigma, so the solve needs only a few outer iterations.
+* The separable harmonic potential u(r) = k r^2 / 2 gives V = k y^2 + k x^2/4
+  and E = 2 sqrt(c_x k/4)(j + 1/2) + 2 sqrt(c_y k)(l + 1/2); the swapped
+  coordinate reading would give another spectrum."""
+import numpy as np
+import pytest
+
+from gpu_util import need_gpu, say, to_dev
+from oracle import dense, physics, problem
+from workloads import config, normal_block
+
+pytestmark = pytest.mark.gpu
+
+
+def test_empty_blocks_are_noops():
+    import torch
+    t3 = need_gpu()
+    op = t3.Operator.from_config(config("c1"))
+    for dt in (torch.float64, torch.float32):
+        X = torch.empty((0, op.N), dtype=dt, device="cuda")
+        Y = torch.empty_like(X)
+        op.apply_H(X, Y)
+        op.apply_prec(X, Y)
+        if dt == torch.float64:
+            op.apply_H(X, Y, shifts=torch.empty(0, dtype=torch.float64, device="cuda"))
+    Xo = torch.empty((0, op.N), dtype=torch.float64, device="cuda")
+    Q = to_dev(normal_block(op.N, 2, 3))
+    _, _, rank = t3.block_orth(Q, Xo, want_factors=False)
+    torch.cuda.synchronize()
+    assert rank == 0
+
+
+def test_smallest_grid_apply_prec_and_solve():
+    import torch
+    t3 = need_gpu()
+    cx, cy, mu = physics.coeffs_unit_heavy(20.0)
+    n, L = (3, 3), (4.0, 3.0)
+    P = problem.make_problem(ndim=1, n=n, L=L, alpha=20.0, v0=1.5, width=1.0)
+    op = t3.Operator(1, list(n), list(L), cx, cy, v0=1.5, width=1.0, mu_hl=mu)
+    Xn = normal_block(P.N, 3, 71)
+    X = to_dev(Xn)
+    Y = torch.empty_like(X)
+    op.apply_H(X, Y)
+    torch.cuda.synchronize()
+    Yr = (P.kron() @ Xn.T).T
+    assert np.linalg.norm(Y.cpu().numpy() - Yr) <= 1e-13 * np.linalg.norm(Yr)
+    Z = torch.empty_like(X)
+    op.apply_prec(X, Z)
+    torch.cuda.synchronize()
+    Zr = P.preconditioner(sigma=op.sigma).apply(Xn.T).T
+    assert np.linalg.norm(Z.cpu().numpy() - Zr) <= 1e-11 * np.linalg.norm(Zr)
+    ref = dense.lowest_eigenvalues(P.kron(), 1).real
+    r = op.jdqr(1, 1, seed=4, max_outer=200)
+    say("3x3 grid", r.evals, ref, r.stats["n_outer"])
+    assert abs(r.evals[0] - ref[0]) <= 1e-10 * max(abs(ref[0]), 1.0)
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_free_three_body_closed_form(inner):
+    t3 = need_gpu()
+    cfg = {**config("c1"), "v0": 0.0}
+    op = t3.Operator.from_config(cfg)
+    cx, cy, _ = physics.coeffs_unit_heavy(cfg["alpha"])
+    k = np.arange(1, 8)
+    e = (k * np.pi / (2.0 * cfg["L"])) ** 2
+    exact = np.sort((cx * e[:, None] + cy * e[None, :]).ravel())[:4]
+    pk = t3.FP64 if inner == "fp64" else t3.FP32
+    r = op.jdqr(4, 4, inner_prec=pk, seed=1)
+    r0 = op.jdqr(4, 4, precond=False, seed=1, max_outer=2000)
+    err = np.max(np.abs(r.evals - exact) / exact)
+    say("free", inner, r.evals, exact, err, "outer", r.stats["n_outer"], "without prec",
+        r0.stats["n_outer"])
+    assert err <= 1e-10
+    # the exact inverse of H - sigma: an order of magnitude fewer outer
+    # iterations than without preconditioner (9 against 338 when written)
+    assert 10 * r.stats["n_outer"] < r0.stats["n_outer"]
+
+
+def test_separable_harmonic_closed_form():
+    t3 = need_gpu()
+    alpha, kk = 20.0, 1.0
+    cx, cy, mu = physics.coeffs_unit_heavy(alpha)
+    op = t3.Operator(1, 64, 12.0, cx, cy, pot="harmonic", v0=kk, mu_hl=mu, sigma=0.0)
+    wx, wy = 2 * np.sqrt(cx * kk / 4), 2 * np.sqrt(cy * kk)
+    exact = np.sort((wx * (np.arange(6)[:, None] + 0.5) + wy * (np.arange(6)[None, :] + 0.5)).ravel())[:4]
+    r = op.jdqr(4, 4, seed=3, target=0.0)
+    err = np.max(np.abs(r.evals - exact) / exact)
+    say("harmonic", r.evals, exact, err)
+    assert err <= 1e-10
