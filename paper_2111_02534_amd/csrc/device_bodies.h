@@ -454,6 +454,18 @@ __device__ __forceinline__ double ld_d(const T* p) {
   return (double)(*p);
 }
 
+// Four consecutive elements p[0..3] as doubles with 16-byte vector loads
+// (p must be 16-byte aligned: 32-byte groups for double, 16 for float).
+__device__ __forceinline__ void ld4_d(const double* p, double* out) {
+  const double2 u = *(const double2*)p;
+  const double2 v = *(const double2*)(p + 2);
+  out[0] = u.x; out[1] = u.y; out[2] = v.x; out[3] = v.y;
+}
+__device__ __forceinline__ void ld4_d(const float* p, double* out) {
+  const float4 u = *(const float4*)p;
+  out[0] = u.x; out[1] = u.y; out[2] = u.z; out[3] = u.w;
+}
+
 struct DotSmem {
   double red[DOT_TP * DOT_TQ];
 };
@@ -489,22 +501,53 @@ __device__ __forceinline__ void dot_tile(int64_t N, int p, int q, const TA* __re
     pb[j] = col < q;
     Bc[j] = B + (int64_t)(pb[j] ? col : 0) * ldb;
   }
+  // Each wave takes groups of 16 rows; lane group lk owns rows g + 4 lk .. + 3
+  // of its column and feeds row g + 4 lk + u into K slot lk of the u-th
+  // instruction (A and B use the same assignment, so the sum is A^T B), which
+  // makes a lane's four rows one contiguous vector load when the columns are
+  // 16-byte aligned and the group lies inside the chunk.
+  const bool vec_ok = (((uintptr_t)A | (uintptr_t)B) % 16 == 0) && (lda % 4 == 0) &&
+                      (ldb % 4 == 0) && (rbeg % 16 == 0);
   for (int64_t g = rbeg + wave * 16; g < rend; g += 64) {
+    const int64_t r0 = g + 4 * lk;
+    double av[4][4], bv[2][4];
+    if (vec_ok && g + 16 <= rend) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t r = g + 4 * u + lk;
-      const bool rv = r < rend;
-      double av[4], bv[2];
+      for (int i = 0; i < 4; ++i) {
+        if (pa[i]) {
+          ld4_d(Ac[i] + r0, av[i]);
+        } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = (rv && pa[i]) ? ld_d(Ac[i] + r) : 0.0;
+          for (int u = 0; u < 4; ++u) av[i][u] = 0.0;
+        }
+      }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = (rv && pb[j]) ? ld_d(Bc[j] + r) : 0.0;
+      for (int j = 0; j < 2; ++j) {
+        if (pb[j]) {
+          ld4_d(Bc[j] + r0, bv[j]);
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) bv[j][u] = 0.0;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t r = r0 + u;
+        const bool rv = r < rend;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i][u] = (rv && pa[i]) ? ld_d(Ac[i] + r) : 0.0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bv[j][u] = (rv && pb[j]) ? ld_d(Bc[j] + r) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
-    }
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][u], bv[j][u], acc[i][j], 0, 0, 0);
   }
   // Sum the four waves' tiles in LDS, one wave at a time.
   for (int wv = 0; wv < 4; ++wv) {
