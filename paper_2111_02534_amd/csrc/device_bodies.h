@@ -615,10 +615,20 @@ __device__ __forceinline__ void gemm_block(int64_t N, int p, int q, double alpha
     }
     __syncthreads();
     if (r < N) {
-      for (int i = 0; i < np; ++i) {
-        const double av = (double)A[r + (int64_t)(pb + i) * lda];
+      // eight columns of A per step, fetched before they are used, so that
+      // eight loads are in flight instead of one
+      for (int i0 = 0; i0 < np; i0 += 8) {
+        double av[8];
 #pragma unroll
-        for (int j = 0; j < GEMM_QB; ++j) acc[j] += av * sm.Cs[i][j];
+        for (int u = 0; u < 8; ++u)
+          av[u] = (i0 + u < np) ? (double)A[r + (int64_t)(pb + i0 + u) * lda] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (i0 + u < np) {
+#pragma unroll
+            for (int j = 0; j < GEMM_QB; ++j) acc[j] += av[u] * sm.Cs[i0 + u][j];
+          }
+        }
       }
     }
   }
@@ -699,11 +709,20 @@ __device__ __forceinline__ void bupdate_row(int64_t N, int nb, double alpha,
                                             T* __restrict__ W, int64_t r, int j) {
   if (r >= N) return;
   double s = 0.0;
-  for (int i = 0; i < nb; ++i) {
-    // an exactly zero coefficient (past a GMRES breakdown) contributes nothing,
-    // whatever the basis vector holds
-    const double h = H[(int64_t)j * hld + i];
-    if (h != 0.0) s += (double)V[(int64_t)i * bs + (int64_t)j * N + r] * h;
+  // eight basis vectors per step, fetched before they are used; an exactly
+  // zero coefficient (past a GMRES breakdown) contributes nothing, whatever the
+  // basis vector holds
+  for (int i0 = 0; i0 < nb; i0 += 8) {
+    double v[8], h[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u;
+      h[u] = (i < nb) ? H[(int64_t)j * hld + i] : 0.0;
+      v[u] = (h[u] != 0.0) ? (double)V[(int64_t)i * bs + (int64_t)j * N + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (h[u] != 0.0) s += v[u] * h[u];
   }
   T* w = W + (int64_t)j * N + r;
   *w = (T)((double)(*w) + alpha * s);
