@@ -13,8 +13,9 @@ Printed: one JSON line with the solve time (value), the Hamiltonian-apply
 throughput of the dominant kernel measured with HIP events inside the timed
 solves against the FP64 MFMA peak (roofline), the eigenvalue error against the
 CPU oracle's stored values, the same solve with FP32 inner GMRES ("mixed"), the
-256-instance batched workload (batched_c4), and the CPU oracle timed on this
-host (cpu_baseline).
+H apply at the precision-form grid c3 (h_apply_c3, context: n = 1024 fills the
+matrix cores where c2's n = 256 is latency-bound), the 256-instance batched
+workload (batched_c4), and the CPU oracle timed on this host (cpu_baseline).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2] [--gmres-steps 3]
 
@@ -96,6 +97,43 @@ def cpu_baseline(cfg, name, sample_iters, full_iters, gmres_steps):
                        f"NumPy/SciPy FP64, {threads} BLAS threads")}
 
 
+def apply_c3_leg(reps=20):
+    """Context for the H-apply metric at the precision-form grid c3 (n = 1024,
+    16 vectors): average time of one H apply per precision with the autotuned
+    tile, HIP events around `reps` launches on the stream the library uses,
+    against the MFMA peak of the precision (BF16x3: FP32-equivalent flops
+    against the 2.5 PFLOP/s dense bf16 peak divided by its three bf16 products
+    per FP32 product)."""
+    import torch
+
+    import paper_2111_02534_amd as t3
+    from workloads import config
+    cfg = config("c3")
+    n, b = cfg["n"], cfg["block"]
+    op = t3.Operator.from_config(cfg)
+    out = {"workload": f"c3: 1D, n={n} (N={op.N}), {b} vectors per apply"}
+    for name, pk, dt, peak in (("fp64", t3.FP64, torch.float64, PEAK_TFLOPS["f64"]),
+                               ("fp32", t3.FP32, torch.float32, PEAK_TFLOPS["f32"]),
+                               ("bf16x3", t3.BF16X3, torch.float32, 2500.0 / 3.0)):
+        op.autotune(pk, b, 3)
+        X = torch.randn((b, op.N), dtype=dt, device="cuda")
+        Y = torch.empty_like(X)
+        op.apply_H(X, Y, prec=pk)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            op.apply_H(X, Y, prec=pk)
+        e1.record()
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        tf = b * apply_flops((n, n)) / (us * 1e-6) / 1e12
+        out[name] = {"us_per_apply": us, "tflops": tf, "peak": peak, "frac": tf / peak}
+    op.close()
+    return out
+
+
 def batched_leg(reps, n_seq, gmres_steps):
     """The 256-instance workload c4: one batched JDQR solve (grouped persistent
     launches, GMRES iteration replayed as a HIP graph) per repetition, for each
@@ -162,6 +200,7 @@ def main():
     ap.add_argument("--gmres-steps", type=int, default=3,
                     help="GMRES steps per correction equation in the timed solves")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-c3-apply", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--batched-seq", type=int, default=32,
                     help="instances of the batch solved one by one for comparison")
@@ -260,6 +299,8 @@ def main():
         out["mixed_vs_fp64"] = {"fp64_s": s_per_solve, "mixed_s": m_s, "speedup": s_per_solve / m_s,
                                 "mixed_outer_iters": mres[-1].stats["n_outer"],
                                 "mixed_eig_max_rel_err_vs_oracle": m_err}
+    if not args.no_c3_apply:
+        out["h_apply_c3"] = apply_c3_leg()
     if not args.no_batched:
         out["batched_c4"] = batched_leg(args.batched_reps, args.batched_seq, args.gmres_steps)
     if not args.no_cpu_baseline:

@@ -334,10 +334,23 @@ template hipError_t launch_convert<float, float>(int64_t, int, double, const flo
                                                  float*, int64_t, hipStream_t);
 
 // -------------------------------------------------------- Cholesky-QR pieces
-__global__ void k_chol_small(int nx, const double* __restrict__ G, const double* __restrict__ n0,
-                             double drop_tol, double* __restrict__ R, int* __restrict__ flags) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  chol_small_serial(nx, G, n0, drop_tol, R, flags);
+// The Gram matrix is staged in LDS by the whole wavefront, one thread
+// factorises it there (the serial arithmetic of the grouped form, without a
+// global-memory round trip per element), and the factor is written back in
+// parallel.  nx <= TRSM_MAX.
+__global__ __launch_bounds__(64) void k_chol_small(int nx, const double* __restrict__ G,
+                                                   const double* __restrict__ n0, double drop_tol,
+                                                   double* __restrict__ R, int* __restrict__ flags) {
+  __shared__ double Gs[TRSM_MAX * TRSM_MAX], Rs[TRSM_MAX * TRSM_MAX], ns[TRSM_MAX];
+  __shared__ int fs[TRSM_MAX];
+  const int t = threadIdx.x;
+  for (int e = t; e < nx * nx; e += 64) Gs[e] = G[e];
+  for (int e = t; e < nx; e += 64) ns[e] = n0[e];
+  __syncthreads();
+  if (t == 0) chol_small_serial(nx, Gs, ns, drop_tol, Rs, fs);
+  __syncthreads();
+  for (int e = t; e < nx * nx; e += 64) R[e] = Rs[e];
+  for (int e = t; e < nx; e += 64) flags[e] = fs[e];
 }
 
 __global__ void k_gram_diag(int nx, const double* __restrict__ G, double* __restrict__ n0,
@@ -359,6 +372,7 @@ hipError_t launch_gram_diag(int nx, const double* G, double* n0, int* flag, hipS
 
 hipError_t launch_chol_small(int nx, const double* G, const double* norm0sq, double drop_tol,
                              double* R, int* flags, hipStream_t s) {
+  if (nx < 1 || nx > TRSM_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, s, nx, G, norm0sq, drop_tol, R, flags);
   return hipGetLastError();
 }
