@@ -99,11 +99,11 @@ def cpu_baseline(cfg, name, sample_iters, full_iters, gmres_steps):
 
 def apply_c3_leg(reps=20):
     """Context for the H-apply metric at the precision-form grid c3 (n = 1024,
-    16 vectors): average time of one H apply per precision with the autotuned
-    tile, HIP events around `reps` launches on the stream the library uses,
-    against the MFMA peak of the precision (BF16x3: FP32-equivalent flops
-    against the 2.5 PFLOP/s dense bf16 peak divided by its three bf16 products
-    per FP32 product)."""
+    16 vectors): for each precision every tile shape is timed (HIP events
+    around `reps` launches on the stream the library uses) and the fastest is
+    reported, against the MFMA peak of the precision (BF16x3: FP32-equivalent
+    flops against the 2.5 PFLOP/s dense bf16 peak divided by its three bf16
+    products per FP32 product)."""
     import torch
 
     import paper_2111_02534_amd as t3
@@ -112,24 +112,33 @@ def apply_c3_leg(reps=20):
     n, b = cfg["n"], cfg["block"]
     op = t3.Operator.from_config(cfg)
     out = {"workload": f"c3: 1D, n={n} (N={op.N}), {b} vectors per apply"}
+    tiles = {0: "32x32", 1: "64x64", 2: "128x128", 3: "64x128"}
     for name, pk, dt, peak in (("fp64", t3.FP64, torch.float64, PEAK_TFLOPS["f64"]),
                                ("fp32", t3.FP32, torch.float32, PEAK_TFLOPS["f32"]),
                                ("bf16x3", t3.BF16X3, torch.float32, 2500.0 / 3.0)):
-        op.autotune(pk, b, 3)
         X = torch.randn((b, op.N), dtype=dt, device="cuda")
         Y = torch.empty_like(X)
-        op.apply_H(X, Y, prec=pk)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
+        best = None
+        for tile in tiles:
+            if pk == t3.BF16X3 and tile == 0:
+                continue  # runs as 64 x 64
+            op.set_tile(tile)
             op.apply_H(X, Y, prec=pk)
-        e1.record()
-        torch.cuda.synchronize()
-        us = 1e3 * e0.elapsed_time(e1) / reps
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                op.apply_H(X, Y, prec=pk)
+            e1.record()
+            torch.cuda.synchronize()
+            us = 1e3 * e0.elapsed_time(e1) / reps
+            if best is None or us < best[0]:
+                best = (us, tiles[tile])
+        op.set_tile(-1)
+        us, tile = best
         tf = b * apply_flops((n, n)) / (us * 1e-6) / 1e12
-        out[name] = {"us_per_apply": us, "tflops": tf, "peak": peak, "frac": tf / peak}
+        out[name] = {"us_per_apply": us, "tile": tile, "tflops": tf, "peak": peak, "frac": tf / peak}
     op.close()
     return out
 
