@@ -60,8 +60,10 @@ __device__ __forceinline__ void for_wave_items(DevTab<Job> t, int stage, F&& f) 
 }
 
 // ------------------------------------------------------------ mode products
+// At least two waves per SIMD, as for the single-job mode-product kernel.
 template <typename T, int TM, int TN, int KC, bool SK = false>
-__global__ __launch_bounds__(256) void k_modeprod_grouped(DevTab<ModeProd<T>> t) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_modeprod_grouped(
+    DevTab<ModeProd<T>> t) {
   __shared__ MpSmem<T, TM, TN, KC, SK> sm;
   for_wg_items(t, 0, [&](const ModeProd<T>& a, int64_t w) {
     modeprod_tile<T, TM, TN, KC, SK>(a, w, sm);
