@@ -508,9 +508,8 @@ __device__ __forceinline__ void dot_tile(int64_t N, int p, int q, const TA* __re
   // 16-byte aligned and the group lies inside the chunk.
   const bool vec_ok = (((uintptr_t)A | (uintptr_t)B) % 16 == 0) && (lda % 4 == 0) &&
                       (ldb % 4 == 0) && (rbeg % 16 == 0);
-  for (int64_t g = rbeg + wave * 16; g < rend; g += 64) {
+  auto load = [&](int64_t g, double (&av)[4][4], double (&bv)[2][4]) {
     const int64_t r0 = g + 4 * lk;
-    double av[4][4], bv[2][4];
     if (vec_ok && g + 16 <= rend) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -541,6 +540,8 @@ __device__ __forceinline__ void dot_tile(int64_t N, int p, int q, const TA* __re
         for (int j = 0; j < 2; ++j) bv[j][u] = (rv && pb[j]) ? ld_d(Bc[j] + r) : 0.0;
       }
     }
+  };
+  auto mul = [&](const double (&av)[4][4], const double (&bv)[2][4]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -548,6 +549,19 @@ __device__ __forceinline__ void dot_tile(int64_t N, int p, int q, const TA* __re
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][u], bv[j][u], acc[i][j], 0, 0, 0);
+  };
+  // The next 64-row group is fetched while the current one is multiplied (two
+  // register sets, the loop unrolled by two so that no copy waits early).
+  double a0[4][4], b0[2][4], a1[4][4], b1[2][4];
+  int64_t g = rbeg + wave * 16;
+  if (g < rend) load(g, a0, b0);
+  for (; g < rend; g += 128) {
+    if (g + 64 < rend) load(g + 64, a1, b1);
+    mul(a0, b0);
+    if (g + 64 < rend) {
+      if (g + 128 < rend) load(g + 128, a0, b0);
+      mul(a1, b1);
+    }
   }
   // Sum the four waves' tiles in LDS, one wave at a time.
   for (int wv = 0; wv < 4; ++wv) {

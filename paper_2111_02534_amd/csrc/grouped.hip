@@ -134,7 +134,7 @@ void dot_job_shape(DotJob<TA, TB>& j, int64_t* items1, int64_t* items2) {
 }
 
 template <typename TA, typename TB>
-__global__ __launch_bounds__(256) void k_dot_grouped(DevTab<DotJob<TA, TB>> t) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dot_grouped(DevTab<DotJob<TA, TB>> t) {
   __shared__ DotSmem sm;
   for_wg_items(t, 0, [&](const DotJob<TA, TB>& j, int64_t w) {
     const int chunk = (int)(w % j.nchunk), tile = (int)(w / j.nchunk);

@@ -139,7 +139,7 @@ int64_t dot_scratch_doubles(int64_t N, int p, int q) {
 }
 
 template <typename TA, typename TB>
-__global__ __launch_bounds__(256) void k_dot_tn(int64_t N, int p, int q, const TA* __restrict__ A,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dot_tn(int64_t N, int p, int q, const TA* __restrict__ A,
                                                 int64_t lda, const TB* __restrict__ B, int64_t ldb,
                                                 int rchunk, int tiles_q, double* __restrict__ part) {
   __shared__ DotSmem sm;
