@@ -687,11 +687,24 @@ __device__ __forceinline__ void bdot_chunk(int64_t N, int nb, const T* __restric
 #pragma unroll
   for (int i = 0; i < BD_MAXNB; ++i) acc[i] = 0.0;
   const T* Wj = W + (int64_t)j * N;
-  for (int64_t r = rbeg + tid; r < rend; r += 256) {
-    const double w = (double)Wj[r];
+  // four rows per thread and step, all their loads issued before the
+  // products (each accumulator still adds the thread's rows in row order)
+  for (int64_t r = rbeg + tid; r < rend; r += 1024) {
+    double w[4];
 #pragma unroll
-    for (int i = 0; i < BD_MAXNB; ++i)
-      if (i < nb) acc[i] += (double)V[(int64_t)i * bs + (int64_t)j * N + r] * w;
+    for (int q = 0; q < 4; ++q) w[q] = (r + 256 * q < rend) ? (double)Wj[r + 256 * q] : 0.0;
+#pragma unroll
+    for (int i = 0; i < BD_MAXNB; ++i) {
+      if (i < nb) {
+        const T* Vi = V + (int64_t)i * bs + (int64_t)j * N + r;
+        double v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = (r + 256 * q < rend) ? (double)Vi[256 * q] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (r + 256 * q < rend) acc[i] += v[q] * w[q];
+      }
+    }
   }
 #pragma unroll
   for (int i = 0; i < BD_MAXNB; ++i) {
