@@ -38,9 +38,9 @@ sys.path.insert(0, ROOT)
 METRIC = "H-apply GFLOP/s (% MFMA peak); JDQR s to k eigenpairs @1e-10, mixed vs FP64"
 # HBM bytes per launch of the FP64 H apply at n = 256, 8 vectors (split-K 32 x 32
 # tile, K-chunks of 64), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a
-# 256 MiB copy (profiles/hbm_traffic_c2_H_apply_fp64.md): 16532 KiB read +
+# 256 MiB copy (profiles/hbm_traffic_c2_H_apply_fp64.md): 16541 KiB read +
 # 4096 KiB written.  None for other workloads.
-TRAFFIC_BYTES = {"c2": 16532 * 1024 + 4096 * 1024}
+TRAFFIC_BYTES = {"c2": 16541 * 1024 + 4096 * 1024}
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 HBM_PEAK_GBS = 8000.0
 
