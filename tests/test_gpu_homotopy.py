@@ -70,3 +70,30 @@ def test_lorentz3_matches_oracle():
     say("lorentz3 apply", err, "evals", r.evals, ref, eerr)
     assert err <= 1e-12
     assert eerr <= 1e-10
+
+
+def test_homotopy_2d_small_grid_matches_dense():
+    """The procedure in 2D (M/m = 1, paper units, f_G) on a 6^4 Gauss-Lobatto
+    grid: the depth of each E0 from the 2D two-body problem on the Cartesian
+    product of the two light-particle modes (against the oracle's generalized
+    eigenproblem on the same grid), and the lowest three-body eigenvalue of
+    each step against the dense eigenvalues of the explicit Kronecker matrix
+    at that depth."""
+    t3 = need_gpu()
+    from oracle import cheb, twobody
+    n, L = 6, 6.0
+    E0s = np.array([0.4, 0.2])
+    cx, cy, mu = physics.coeffs_paper_units(1.0)
+    grid = dict(ndim=2, n=[n] * 4, L=L, c_x=cx, c_y=cy, pot="gauss_paper", mu_hl=mu)
+    h = t3.homotopy(E0s, 1, 2, seed=2, max_outer=800, **grid)
+    x = cheb.nodes(n, L)
+    D2 = cheb.second_derivative_dirichlet(n, L)
+    for i, E0 in enumerate(E0s):
+        v0 = twobody.depth_for_binding_2d(x, D2, E0, lambda r: np.exp(-r * r))
+        P = problem.make_problem(ndim=2, n=n, L=L, alpha=1.0, v0=h["v0"][i], shape="gauss_paper",
+                                 units="paper")
+        ref = dense.lowest_eigenvalues(P.kron(), 1).real
+        say("2d homotopy E0", E0, "v0", h["v0"][i], v0, "E", h["evals"][i], ref,
+            "outer", h["n_outer"][i])
+        assert abs(h["v0"][i] - v0) <= 1e-10 * v0
+        assert abs(h["evals"][i][0] - ref[0]) <= 1e-10 * max(abs(ref[0]), 1.0)
