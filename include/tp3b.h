@@ -300,8 +300,10 @@ tp3b_status tp3b_jdqr_solve_batched(const tp3b_op* ops, int32_t count, const tp3
                                     int32_t* n_outer, double* const* Q, tp3b_jdqr_stats* stats);
 
 /* Mode-product tile shape used by this operator's applies: 0 = 32x32,
- * 1 = 64x64, 2 = 128x128, 3 = 64x128 output tile per 256-thread workgroup;
- * -1 restores the built-in choice (or the autotuned one, see below). */
+ * 1 = 64x64, 2 = 128x128, 3 = 64x128 output tile per 256-thread workgroup,
+ * 4 = 32x32 per 512-thread workgroup (the contraction split over eight
+ * wavefronts); -1 restores the built-in choice (or the autotuned one, see
+ * below).  BF16x3 applies run tiles 0 and 4 as tile 1.  EINVAL outside -1..4. */
 tp3b_status tp3b_set_tile(tp3b_op op, int32_t tile);
 
 /* Autotuner: times every tile shape for the Hamiltonian apply and the

@@ -289,7 +289,7 @@ class Operator:
 
     def set_tile(self, tile):
         """Force a mode-product tile shape (0: 32x32, 1: 64x64, 2: 128x128,
-        3: 64x128; -1: automatic)."""
+        3: 64x128, 4: 32x32 over eight wavefronts; -1: automatic)."""
         _check(lib().tp3b_set_tile(self.handle, int(tile)))
 
     def autotune(self, prec=FP64, nvec=1, reps=5):

@@ -90,11 +90,11 @@ def main():
             X = torch.randn((b, op.N), dtype=dt, device="cuda")
             Y = torch.empty_like(X)
             kinds = ("H", "P") if ndim == 1 else ("H",)
-            for tile in range(4):
-                tm, tn = [(32, 32), (64, 64), (128, 128), (64, 128)][tile]
-                if tile and (tm > n or tn > n) and ndim == 1:
+            for tile in range(5):
+                tm, tn = [(32, 32), (64, 64), (128, 128), (64, 128), (32, 32)][tile]
+                if tm > 32 and (tm > n or tn > n) and ndim == 1:
                     continue
-                if pk == t3.BF16X3 and tile == 0:
+                if pk == t3.BF16X3 and tm == 32:
                     continue
                 op.set_tile(tile)
                 for kind in kinds:
@@ -113,7 +113,7 @@ def main():
                     torch.cuda.synchronize()
                     ms = e0.elapsed_time(e1) / args.reps
                     tf = flops(ndim, n, b, kind) / ms / 1e9
-                    print(f"  {pname} tile {tm}x{tn} {kind}: {1e3 * ms:10.1f} us  {tf:7.2f} TFLOP/s"
+                    print(f"  {pname} tile {tm}x{tn}{'w8' if tile == 4 else ''} {kind}: {1e3 * ms:10.1f} us  {tf:7.2f} TFLOP/s"
                           f"  {100 * tf / PEAK[pname]:5.1f}% of peak", flush=True)
             op.set_tile(-1)
             if ndim == 1:

@@ -47,7 +47,7 @@ tp3b_status arena_full() { return fail(TP3B_ENOMEM, "batched: job-table arena ex
 // Tile shapes in use by one kind of mode-product step over a batch.
 struct TileSet {
   int n = 0;
-  int id[NUM_TILE_CFGS] = {0, 0, 0, 0};
+  int id[NUM_TILE_CFGS] = {};
   void add(int t) {
     for (int i = 0; i < n; ++i)
       if (id[i] == t) return;
@@ -59,7 +59,7 @@ struct TileSet {
 template <typename T>
 struct MpTabs {
   int n = 0;
-  int tile[NUM_TILE_CFGS] = {0, 0, 0, 0};
+  int tile[NUM_TILE_CFGS] = {};
   Tab<ModeProd<T>> t[NUM_TILE_CFGS];
   bool bf3 = false;
 };
@@ -1532,10 +1532,9 @@ tp3b_status tp3b_autotune_batched(const tp3b_op* ops, int32_t count, int32_t pre
       std::vector<int> saved;
       for (int i : gi) saved.push_back(ops[i]->tile_override);
       for (int tile = 0; tile < NUM_TILE_CFGS && st == TP3B_OK; ++tile) {
-        const int tm = (tile == TILE_32) ? 32 : (tile == TILE_128 ? 128 : 64);
-        const int tn = (tile == TILE_32) ? 32 : ((tile == TILE_64) ? 64 : 128);
-        if (tile != TILE_32 && (tm > nx || tn > ny)) continue;
-        if (bf3 && tile == TILE_32) continue;
+        const int tm = tile_rows(tile), tn = tile_cols(tile);
+        if (tm > 32 && (tm > nx || tn > ny)) continue;
+        if (bf3 && tm == 32) continue;
         for (int i : gi) ops[i]->tile_override = tile;
         auto run = [&]() -> tp3b_status {
           if (f64)

@@ -56,11 +56,18 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t g, int64_t G) {
 // K chunk (independent accumulators per 16 x 16 block instead of one dependent
 // chain), and the four partial tiles are summed through LDS at the end; used for
 // small tiles, whose runtime is the latency of the K loop.
-template <typename T, int TM, int TN, int KC, bool SK = false>
+// NW waves per workgroup (4 in 2 x 2 without split K; 4 or 8 with it).  The
+// split-K partial tiles reuse the LDS of the operand chunks, which are dead by
+// the time the partials are written.
+template <typename T, int TM, int TN, int KC, bool SK = false, int NW = 4>
 struct MpSmem {
-  T As[KC][TM + 1];
-  T Bs[KC][TN + 1];
-  T red[SK ? 4 * TM * TN : 1];
+  union {
+    struct {
+      T As[KC][TM + 1];
+      T Bs[KC][TN + 1];
+    } ab;
+    T red[SK ? NW * TM * TN : 1];
+  };
 };
 
 // Work items of one mode product: output tiles x batch items.
@@ -70,18 +77,21 @@ __host__ __device__ inline int64_t modeprod_items(const P& a) {
 }
 
 // One TM x TN output tile (work item w) of the mode product `a`.
-template <typename T, int TM, int TN, int KC, bool SK = false>
+template <typename T, int TM, int TN, int KC, bool SK = false, int NW = 4>
 __device__ __forceinline__ void modeprod_tile(const ModeProd<T>& a, int64_t w,
-                                              MpSmem<T, TM, TN, KC, SK>& sm) {
+                                              MpSmem<T, TM, TN, KC, SK, NW>& sm) {
   typedef typename Mma<T>::acc_t acc_t;
+  constexpr int NT = 64 * NW;  // threads per workgroup
   constexpr int WM = SK ? TM : TM / 2, WN = SK ? TN : TN / 2;
   constexpr int BM = WM / 16, BN = WN / 16;
-  constexpr int EA = TM * KC / 256, EB = KC * TN / 256;
-  constexpr int KW = SK ? KC / 4 : KC;  // K range of one wave within a chunk
-  static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
+  constexpr int EA = TM * KC / NT, EB = KC * TN / NT;
+  constexpr int KW = SK ? KC / NW : KC;  // K range of one wave within a chunk
+  static_assert(SK || NW == 4, "without split K the four waves form a 2 x 2 grid");
+  static_assert(EA >= 1 && EB >= 1 && EA * NT == TM * KC && EB * NT == KC * TN,
+                "chunk not divisible among the threads");
   static_assert(KW % 4 == 0, "a wave's K range is a multiple of the MFMA depth");
-  T(&As)[KC][TM + 1] = sm.As;
-  T(&Bs)[KC][TN + 1] = sm.Bs;
+  T(&As)[KC][TM + 1] = sm.ab.As;
+  T(&Bs)[KC][TN + 1] = sm.ab.Bs;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = SK ? 0 : (wave >> 1) * WM, wn = SK ? 0 : (wave & 1) * WN;
@@ -113,13 +123,13 @@ __device__ __forceinline__ void modeprod_tile(const ModeProd<T>& a, int64_t w,
       const int k0 = c * KC;
 #pragma unroll
       for (int s = 0; s < EA; ++s) {
-        const int e = tid + s * 256, m = e / KC, k = e % KC;
+        const int e = tid + s * NT, m = e / KC, k = e % KC;
         const int gi = i0 + m, gk = k0 + k;
         ra[s] = (gi < M && gk < M) ? a.L[(int64_t)gi * M + gk] : T(0);
       }
 #pragma unroll
       for (int s = 0; s < EB; ++s) {
-        const int e = tid + s * 256, k = e / TN, n = e % TN;
+        const int e = tid + s * NT, k = e / TN, n = e % TN;
         const int gk = k0 + k, gj = j0 + n;
         rb[s] = (gk < M && gj < Nc) ? X[(int64_t)gk * rs + gj] : T(0);
       }
@@ -127,13 +137,13 @@ __device__ __forceinline__ void modeprod_tile(const ModeProd<T>& a, int64_t w,
       const int k0 = (c - nL) * KC;
 #pragma unroll
       for (int s = 0; s < EA; ++s) {
-        const int e = tid + s * 256, m = e / KC, k = e % KC;
+        const int e = tid + s * NT, m = e / KC, k = e % KC;
         const int gi = i0 + m, gk = k0 + k;
         ra[s] = (gi < M && gk < Nc) ? X[(int64_t)gi * rs + gk] : T(0);
       }
 #pragma unroll
       for (int s = 0; s < EB; ++s) {
-        const int e = tid + s * 256, k = e / TN, n = e % TN;
+        const int e = tid + s * NT, k = e / TN, n = e % TN;
         const int gk = k0 + k, gj = j0 + n;
         rb[s] = (gk < Nc && gj < Nc) ? a.R[(int64_t)gk * Nc + gj] : T(0);
       }
@@ -142,12 +152,12 @@ __device__ __forceinline__ void modeprod_tile(const ModeProd<T>& a, int64_t w,
   auto store = [&]() {
 #pragma unroll
     for (int s = 0; s < EA; ++s) {
-      const int e = tid + s * 256;
+      const int e = tid + s * NT;
       As[e % KC][e / KC] = ra[s];
     }
 #pragma unroll
     for (int s = 0; s < EB; ++s) {
-      const int e = tid + s * 256;
+      const int e = tid + s * NT;
       Bs[e / TN][e % TN] = rb[s];
     }
   };
@@ -197,7 +207,8 @@ __device__ __forceinline__ void modeprod_tile(const ModeProd<T>& a, int64_t w,
     }
   };
   if constexpr (SK) {
-    // sum the four waves' partial tiles (fixed order: deterministic)
+    // sum the waves' partial tiles (fixed order: deterministic); the operand
+    // chunks are dead here (the K loop ends with a barrier)
     T* red = sm.red;
 #pragma unroll
     for (int bi = 0; bi < BM; ++bi)
@@ -209,8 +220,10 @@ __device__ __forceinline__ void modeprod_tile(const ModeProd<T>& a, int64_t w,
           red[(wave * TM + ri) * TN + cj] = acc[bi][bj][r];
         }
     __syncthreads();
-    for (int e = tid; e < TM * TN; e += 256) {
-      const T v = red[e] + red[TM * TN + e] + red[2 * TM * TN + e] + red[3 * TM * TN + e];
+    for (int e = tid; e < TM * TN; e += NT) {
+      T v = red[e];
+#pragma unroll
+      for (int w2 = 1; w2 < NW; ++w2) v += red[w2 * TM * TN + e];
       emit(i0 + e / TN, j0 + e % TN, v);
     }
     __syncthreads();  // `red` is reused by the next work item of a persistent loop

@@ -70,6 +70,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   });
 }
 
+// The small split-K tile with eight waves (same body as the single-job form).
+template <typename T>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_modeprod_sk8_grouped(
+    DevTab<ModeProd<T>> t) {
+  __shared__ MpSmem<T, 32, 32, 64, true, 8> sm;
+  for_wg_items(t, 0, [&](const ModeProd<T>& a, int64_t w) {
+    modeprod_tile<T, 32, 32, 64, true, 8>(a, w, sm);
+  });
+}
+
 template <int TM, int TN, int KC>
 __global__ __launch_bounds__(256) void k_modeprod_bf3_grouped(DevTab<ModeProd<float>> t) {
   __shared__ Bf3Smem<TM, TN, KC> sm;
@@ -81,7 +91,8 @@ __global__ __launch_bounds__(256) void k_modeprod_bf3_grouped(DevTab<ModeProd<fl
 int64_t modeprod_items_for(int M, int Nc, int nbatch, int tile, bool bf3) {
   struct P { int M, Nc, nbatch; } p{M, Nc, nbatch};
   switch (tile) {
-    case TILE_32: return bf3 ? modeprod_items<64, 64>(p) : modeprod_items<32, 32>(p);
+    case TILE_32:
+    case TILE_32W8: return bf3 ? modeprod_items<64, 64>(p) : modeprod_items<32, 32>(p);
     case TILE_64: return modeprod_items<64, 64>(p);
     case TILE_128: return modeprod_items<128, 128>(p);
     default: return modeprod_items<64, 128>(p);
@@ -93,6 +104,7 @@ hipError_t launch_modeprod_grouped(DevTab<ModeProd<T>> t, int tile, hipStream_t 
   const dim3 g(kPersistWGs), b(256);
   switch (tile) {
     case TILE_32: hipLaunchKernelGGL((k_modeprod_grouped<T, 32, 32, 64, true>), g, b, 0, s, t); break;
+    case TILE_32W8: hipLaunchKernelGGL((k_modeprod_sk8_grouped<T>), g, dim3(512), 0, s, t); break;
     case TILE_64: hipLaunchKernelGGL((k_modeprod_grouped<T, 64, 64, 16>), g, b, 0, s, t); break;
     case TILE_128: hipLaunchKernelGGL((k_modeprod_grouped<T, 128, 128, 16>), g, b, 0, s, t); break;
     case TILE_64x128: hipLaunchKernelGGL((k_modeprod_grouped<T, 64, 128, 16>), g, b, 0, s, t); break;
@@ -107,6 +119,7 @@ hipError_t launch_modeprod_bf3_grouped(DevTab<ModeProd<float>> t, int tile, hipS
   const dim3 g(kPersistWGs), b(256);
   switch (tile) {
     case TILE_32:
+    case TILE_32W8:
     case TILE_64: hipLaunchKernelGGL((k_modeprod_bf3_grouped<64, 64, 32>), g, b, 0, s, t); break;
     case TILE_128: hipLaunchKernelGGL((k_modeprod_bf3_grouped<128, 128, 32>), g, b, 0, s, t); break;
     case TILE_64x128: hipLaunchKernelGGL((k_modeprod_bf3_grouped<64, 128, 32>), g, b, 0, s, t); break;

@@ -36,8 +36,21 @@ struct ModeProd {
   int acc;
 };
 
-// Tile configurations (output tile TM x TN per 256-thread workgroup).
-enum TileCfg { TILE_32 = 0, TILE_64 = 1, TILE_128 = 2, TILE_64x128 = 3, NUM_TILE_CFGS = 4 };
+// Tile configurations (output tile TM x TN per 256-thread workgroup; the
+// 32 x 32 tiles split the K range over their waves, TILE_32W8 over eight waves
+// of a 512-thread workgroup).
+enum TileCfg {
+  TILE_32 = 0,
+  TILE_64 = 1,
+  TILE_128 = 2,
+  TILE_64x128 = 3,
+  TILE_32W8 = 4,
+  NUM_TILE_CFGS = 5
+};
+inline int tile_rows(int tile) { return (tile == TILE_32 || tile == TILE_32W8) ? 32 : (tile == TILE_128 ? 128 : 64); }
+inline int tile_cols(int tile) {
+  return (tile == TILE_32 || tile == TILE_32W8) ? 32 : ((tile == TILE_64) ? 64 : 128);
+}
 
 // Optional kernel timestamps for the mode-product launches of the calling
 // thread.  While launch_timing() points at a LaunchTiming, the first launch
@@ -53,7 +66,7 @@ LaunchTiming*& launch_timing();
 template <typename T>
 hipError_t launch_modeprod(const ModeProd<T>& a, int tile, hipStream_t s);
 // The same product on FP32 data with BF16x3 split products on the bf16 matrix
-// cores (FP32 accumulation); tile TILE_32 runs as TILE_64.
+// cores (FP32 accumulation); tiles TILE_32 and TILE_32W8 run as TILE_64.
 hipError_t launch_modeprod_bf3(const ModeProd<float>& a, int tile, hipStream_t s);
 
 // C (p x q, column-major, ldc) = A^T B, A: N x p (lda), B: N x q (ldb), FP64

@@ -27,15 +27,15 @@ LaunchTiming*& launch_timing() {
 }
 
 // Launch with the timing events of launch_timing() when it is set.
-#define TP3B_MP_LAUNCH(KERN, GRID, S, ARG)                                                 \
+#define TP3B_MP_LAUNCH(KERN, GRID, BLOCK, S, ARG)                                                 \
   do {                                                                                     \
     LaunchTiming* lt_ = launch_timing();                                                   \
     if (lt_) {                                                                             \
       hipEvent_t st_ = lt_->started ? nullptr : lt_->start;                                \
       lt_->started = true;                                                                 \
-      hipExtLaunchKernelGGL(KERN, dim3(GRID), dim3(256), 0, S, st_, lt_->stop, 0, ARG);    \
+      hipExtLaunchKernelGGL(KERN, dim3(GRID), dim3(BLOCK), 0, S, st_, lt_->stop, 0, ARG);  \
     } else {                                                                               \
-      hipLaunchKernelGGL(KERN, dim3(GRID), dim3(256), 0, S, ARG);                          \
+      hipLaunchKernelGGL(KERN, dim3(GRID), dim3(BLOCK), 0, S, ARG);                        \
     }                                                                                      \
   } while (0)
 
@@ -51,21 +51,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   modeprod_tile<T, TM, TN, KC, SK>(a, xcd_remap(blockIdx.x, modeprod_items<TM, TN>(a)), sm);
 }
 
+// Small grids: 32 x 32 output tile split over the K of eight waves (512
+// threads, K-chunks of 64), four waves per SIMD.
+template <typename T, int ROLE>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_modeprod_sk8(
+    ModeProd<T> a) {
+  __shared__ MpSmem<T, 32, 32, 64, true, 8> sm;
+  modeprod_tile<T, 32, 32, 64, true, 8>(a, xcd_remap(blockIdx.x, modeprod_items<32, 32>(a)), sm);
+}
+
 template <typename T, int ROLE>
 static void launch_role(const ModeProd<T>& a, int tile, hipStream_t s, unsigned g32, unsigned g64,
                         unsigned g128, unsigned g64x128) {
   switch (tile) {
     case TILE_32:
-      TP3B_MP_LAUNCH((k_modeprod<T, 32, 32, 64, ROLE, true>), g32, s, a);
+      TP3B_MP_LAUNCH((k_modeprod<T, 32, 32, 64, ROLE, true>), g32, 256, s, a);
+      break;
+    case TILE_32W8:
+      TP3B_MP_LAUNCH((k_modeprod_sk8<T, ROLE>), g32, 512, s, a);
       break;
     case TILE_64:
-      TP3B_MP_LAUNCH((k_modeprod<T, 64, 64, 16, ROLE>), g64, s, a);
+      TP3B_MP_LAUNCH((k_modeprod<T, 64, 64, 16, ROLE>), g64, 256, s, a);
       break;
     case TILE_128:
-      TP3B_MP_LAUNCH((k_modeprod<T, 128, 128, 16, ROLE>), g128, s, a);
+      TP3B_MP_LAUNCH((k_modeprod<T, 128, 128, 16, ROLE>), g128, 256, s, a);
       break;
     default:
-      TP3B_MP_LAUNCH((k_modeprod<T, 64, 128, 16, ROLE>), g64x128, s, a);
+      TP3B_MP_LAUNCH((k_modeprod<T, 64, 128, 16, ROLE>), g64x128, 256, s, a);
       break;
   }
 }
@@ -103,13 +115,13 @@ static void launch_role_bf3(const ModeProd<float>& a, int tile, hipStream_t s, u
                             unsigned g128, unsigned g64x128) {
   switch (tile) {
     case TILE_128:
-      TP3B_MP_LAUNCH((k_modeprod_bf3<128, 128, 32, ROLE>), g128, s, a);
+      TP3B_MP_LAUNCH((k_modeprod_bf3<128, 128, 32, ROLE>), g128, 256, s, a);
       break;
     case TILE_64x128:
-      TP3B_MP_LAUNCH((k_modeprod_bf3<64, 128, 32, ROLE>), g64x128, s, a);
+      TP3B_MP_LAUNCH((k_modeprod_bf3<64, 128, 32, ROLE>), g64x128, 256, s, a);
       break;
-    default:  // TILE_32 and TILE_64: the smallest bf16 tile is 64 x 64
-      TP3B_MP_LAUNCH((k_modeprod_bf3<64, 64, 32, ROLE>), g64, s, a);
+    default:  // TILE_32, TILE_32W8 and TILE_64: the smallest bf16 tile is 64 x 64
+      TP3B_MP_LAUNCH((k_modeprod_bf3<64, 64, 32, ROLE>), g64, 256, s, a);
       break;
   }
 }

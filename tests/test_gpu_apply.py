@@ -82,6 +82,47 @@ def test_apply_fp64_ragged_smooth(nx, ny, nvec):
     assert err <= 4 * (nx + ny + 1) * 2.2e-16
 
 
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_every_tile_shape(tile, prec):
+    """Each mode-product tile shape forced on a ragged grid (130 x 70: several
+    tiles plus a ragged edge in both modes for every shape): the H apply within
+    the componentwise bound of the ragged test, the preconditioner within the
+    FP64 / FP32 bars of the preconditioner tests."""
+    import torch
+    t3 = need_gpu()
+    nx, ny, nvec = 130, 70, 3
+    cx, cy, mu = physics.coeffs_unit_heavy(7.0)
+    P = problem.make_problem(ndim=1, n=(nx, ny), L=(9.0, 6.0), alpha=7.0, v0=1.5, width=0.8)
+    op = t3.Operator(1, [nx, ny], [9.0, 6.0], cx, cy, v0=1.5, width=0.8, mu_hl=mu)
+    op.set_tile(tile)
+    dt, eps = (torch.float64, 2.2e-16) if prec == "fp64" else (torch.float32, 6e-8)
+    Xn = gaussian_bumps_1d(P.grids[0], P.grids[1], nvec, seed=17 + tile).T.copy()
+    if prec == "fp32":
+        Xn = Xn.astype(np.float32).astype(np.float64)
+    say("tile", tile, prec)
+    X = to_dev(Xn.T, dt)
+    Y = torch.empty_like(X)
+    op.apply_H(X, Y)
+    torch.cuda.synchronize()
+    Yr = P.apply(Xn)
+    err = np.max(np.abs(Y.cpu().numpy().astype(np.float64).T - Yr) / np.maximum(_absH_absW(P, Xn), 1e-300))
+    pc = P.preconditioner(sigma=op.sigma)
+    Zn = normal_block(P.N, nvec, 40 + tile)
+    if prec == "fp32":
+        Zn = Zn.astype(np.float32).astype(np.float64)
+    Z = to_dev(Zn, dt)
+    W = torch.empty_like(Z)
+    op.apply_prec(Z, W)
+    torch.cuda.synchronize()
+    Wr = pc.apply(Zn.T).T
+    perr = np.linalg.norm(W.cpu().numpy().astype(np.float64) - Wr) / np.linalg.norm(Wr)
+    say("  componentwise", err, "prec", perr)
+    op.set_tile(-1)
+    assert err <= 4 * (nx + ny + 1) * eps
+    assert perr <= (1e-10 if prec == "fp64" else 1e-4)
+
+
 def test_apply_shifted_fp64():
     import torch
     cfg = config("c1")
