@@ -88,6 +88,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"libtp3b.so not built at {LIB_PATH}; run __graft_entry__.build()")
+        # torch first: it brings its own HIP runtime, and the library must bind
+        # to that one (loaded the other way round, torch finds no device).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
         L.tp3b_create.argtypes = [ctypes.POINTER(ProblemDesc), vp, ctypes.POINTER(vp)]

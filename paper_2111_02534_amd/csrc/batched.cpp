@@ -909,16 +909,18 @@ tp3b_status BatchedJdqr<TW>::iterate() {
     if (!in_[i].done) act.push_back(i);
   if (act.empty()) return TP3B_OK;
   const double t0 = now_s();
-  // 1. ordered Schur forms; rotate V and A V where S is not the identity
+  // 1. ordered Schur forms (independent per instance: on several host
+  // threads); rotate V and A V where S is not the identity
   std::vector<int> rot;
-  for (int i : act) {
+  std::vector<char> schur_ok(act.size(), 0), schur_ident(act.size(), 0);
+  parallel_for((int)act.size(), [&](int a) {
+    const int i = act[a];
     Inst& I = in_[i];
     const int m = I.m;
     I.S.assign((size_t)m * m, 0.0);
     I.T.assign((size_t)m * m, 0.0);
     I.pair.assign(m, 0);
-    if (!ordered_schur(m, I.M.data(), I.S.data(), I.T.data(), I.pair.data()))
-      return fail(TP3B_ENOCONV, "batched jdqr: projected Schur form did not converge");
+    if (!ordered_schur(m, I.M.data(), I.S.data(), I.T.data(), I.pair.data())) return;
     bool ident = true;
     for (int r = 0; r < m && ident; ++r)
       for (int c = 0; c < m; ++c)
@@ -933,8 +935,13 @@ tp3b_status BatchedJdqr<TW>::iterate() {
     I.nb = std::min(b_, m);
     for (int c = 0; c < I.nb; ++c)
       for (int r = 0; r < m; ++r) ht[r + (size_t)c * m] = I.T[(size_t)r * m + c];
-    if (!ident) rot.push_back(i);
     I.M = I.T;
+    schur_ident[a] = ident;
+    schur_ok[a] = 1;
+  });
+  for (size_t a = 0; a < act.size(); ++a) {
+    if (!schur_ok[a]) return fail(TP3B_ENOCONV, "batched jdqr: projected Schur form did not converge");
+    if (!schur_ident[a]) rot.push_back(act[a]);
   }
   TP3B_TRY(sync());
   TP3B_HIP(hipMemcpyAsync(S_.d, S_.h.data(), sizeof(double) * S_.h.size(), hipMemcpyHostToDevice, s_));

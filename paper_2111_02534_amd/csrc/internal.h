@@ -3,7 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/tp3b.h"
@@ -28,6 +31,31 @@ struct DevOps {
   T* lamItem = nullptr;  // 2D: lam_x1[i1] + lam_x2[i2] per (x1, x2) plane
   T* work = nullptr;  // preconditioner intermediate, work_vecs vectors
 };
+
+// Runs f(i) for every i in [0, n) on up to kHostThreads host threads (the
+// calling one included), handing out indices one at a time.  f must write only
+// data that belongs to its own index; each f(i) does the same arithmetic
+// whichever thread runs it.  Used for the independent small dense problems of
+// the instances of a batch.
+constexpr int kHostThreads = 8;
+template <class F>
+void parallel_for(int n, F&& f) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::min({hw, kHostThreads, (n + 15) / 16});
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
+  };
+  std::vector<std::thread> th;
+  th.reserve(nt - 1);
+  for (int t = 1; t < nt; ++t) th.emplace_back(work);
+  work();
+  for (std::thread& x : th) x.join();
+}
 
 }  // namespace tp3b
 
