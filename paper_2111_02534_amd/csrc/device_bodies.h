@@ -554,6 +554,15 @@ __device__ __forceinline__ void dot_tile(int64_t N, int p, int q, const TA* __re
       }
     }
   };
+  // 16 x 16 blocks that lie wholly outside p x q are skipped (a branch that is
+  // the same for the whole wave): with the q <= 8 columns of a typical
+  // projection most of the tile is padding, and an FP64 MFMA costs as much as
+  // the vector FMAs it replaces.  The stored entries are unchanged.
+  bool ua[4], ub[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) ua[i] = p0 + i * 16 < p;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) ub[j] = q0 + j * 16 < q;
   auto mul = [&](const double (&av)[4][4], const double (&bv)[2][4]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -561,7 +570,8 @@ __device__ __forceinline__ void dot_tile(int64_t N, int p, int q, const TA* __re
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][u], bv[j][u], acc[i][j], 0, 0, 0);
+          if (ua[i] && ub[j])
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][u], bv[j][u], acc[i][j], 0, 0, 0);
   };
   // The next 64-row group is fetched while the current one is multiplied (two
   // register sets, the loop unrolled by two so that no copy waits early).
@@ -614,11 +624,18 @@ __device__ __forceinline__ double dot_reduce_elem(int gp, int gq, int nchunk, in
 }
 
 // ------------------------------------------------------------ basis update
-// Y (rows r0..r0+255, columns q0..q0+15) = beta Y + alpha A C.
-constexpr int GEMM_QB = 16, GEMM_PB = 128;
+// Y (rows rblock*64 .. +63, columns q0..q0+15) = beta Y + alpha A C.  A lane
+// owns one row; the four waves split the p range into quarters (for short
+// blocks of vectors that puts four times as many workgroups and loads in
+// flight as one row per thread over all of p would), and the four partial rows
+// are summed in LDS in wave order.
+constexpr int GEMM_QB = 16, GEMM_PB = 128, GEMM_RB = 64;
 
 struct GemmSmem {
-  double Cs[GEMM_PB][GEMM_QB];
+  union {
+    double Cs[GEMM_PB][GEMM_QB];           // a chunk of C
+    double red[4][GEMM_RB][GEMM_QB + 1];   // the waves' partial rows
+  };
 };
 
 template <typename T>
@@ -627,7 +644,8 @@ __device__ __forceinline__ void gemm_block(int64_t N, int p, int q, double alpha
                                            const double* __restrict__ C, int ldc, double beta,
                                            T* __restrict__ Y, int64_t ldy, int64_t rblock,
                                            int qblock, GemmSmem& sm) {
-  const int64_t r = rblock * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r = rblock * GEMM_RB + lane;
   const int q0 = qblock * GEMM_QB;
   const int nq = (q - q0 < GEMM_QB) ? q - q0 : GEMM_QB;
   double acc[GEMM_QB];
@@ -641,17 +659,19 @@ __device__ __forceinline__ void gemm_block(int64_t N, int p, int q, double alpha
       sm.Cs[i][j] = (i < np && j < nq) ? C[(pb + i) + (int64_t)(q0 + j) * ldc] : 0.0;
     }
     __syncthreads();
+    const int per = (np + 3) / 4;
+    const int ib = (wave * per < np) ? wave * per : np;
+    const int ie = (ib + per < np) ? ib + per : np;
     if (r < N) {
-      // eight columns of A per step, fetched before they are used, so that
-      // eight loads are in flight instead of one
-      for (int i0 = 0; i0 < np; i0 += 8) {
+      // eight columns of A per step, fetched before they are used
+      for (int i0 = ib; i0 < ie; i0 += 8) {
         double av[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          av[u] = (i0 + u < np) ? (double)A[r + (int64_t)(pb + i0 + u) * lda] : 0.0;
+          av[u] = (i0 + u < ie) ? (double)A[r + (int64_t)(pb + i0 + u) * lda] : 0.0;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          if (i0 + u < np) {
+          if (i0 + u < ie) {
 #pragma unroll
             for (int j = 0; j < GEMM_QB; ++j) acc[j] += av[u] * sm.Cs[i0 + u][j];
           }
@@ -659,17 +679,24 @@ __device__ __forceinline__ void gemm_block(int64_t N, int p, int q, double alpha
       }
     }
   }
-  if (r < N) {
+  __syncthreads();  // the last chunk of C is dead
 #pragma unroll
-    for (int j = 0; j < GEMM_QB; ++j) {
+  for (int j = 0; j < GEMM_QB; ++j) sm.red[wave][lane][j] = acc[j];
+  __syncthreads();
+  if (r < N) {
+    // wave w finishes columns 4w .. 4w+3 of the lane's row
+#pragma unroll
+    for (int jj = 0; jj < GEMM_QB / 4; ++jj) {
+      const int j = wave * (GEMM_QB / 4) + jj;
       if (j < nq) {
+        const double v = sm.red[0][lane][j] + sm.red[1][lane][j] + sm.red[2][lane][j] + sm.red[3][lane][j];
         T* y = Y + r + (int64_t)(q0 + j) * ldy;
         const double old = (beta != 0.0) ? (double)(*y) : 0.0;
-        *y = (T)(beta * old + alpha * acc[j]);
+        *y = (T)(beta * old + alpha * v);
       }
     }
   }
-  __syncthreads();  // Cs is reused by the next work item of a persistent loop
+  __syncthreads();  // `red` is reused by the next work item of a persistent loop
 }
 
 // ------------------------------------------------ per-column (diagonal) dots

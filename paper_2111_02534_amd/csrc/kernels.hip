@@ -222,7 +222,7 @@ hipError_t launch_gemm_nn(int64_t N, int p, int q, double alpha, const T* A, int
                           const double* C, int ldc, double beta, T* Y, int64_t ldy,
                           hipStream_t s) {
   if (N <= 0 || q <= 0) return hipSuccess;
-  dim3 grid((unsigned)((N + 255) / 256), (q + GEMM_QB - 1) / GEMM_QB);
+  dim3 grid((unsigned)((N + GEMM_RB - 1) / GEMM_RB), (q + GEMM_QB - 1) / GEMM_QB);
   hipLaunchKernelGGL((k_gemm_nn<T>), grid, dim3(256), 0, s, N, p, q, alpha, A, lda, C, ldc, beta,
                      Y, ldy);
   return hipGetLastError();
