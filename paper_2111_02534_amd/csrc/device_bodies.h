@@ -624,28 +624,35 @@ __device__ __forceinline__ double dot_reduce_elem(int gp, int gq, int nchunk, in
 }
 
 // ------------------------------------------------------------ basis update
-// Y (rows rblock*64 .. +63, columns q0..q0+15) = beta Y + alpha A C.  A lane
-// owns one row; the four waves split the p range into quarters (for short
-// blocks of vectors that puts four times as many workgroups and loads in
-// flight as one row per thread over all of p would), and the four partial rows
-// are summed in LDS in wave order.
-constexpr int GEMM_QB = 16, GEMM_PB = 128, GEMM_RB = 64;
+// Y (a block of rows, columns q0..q0+15) = beta Y + alpha A C, one row per lane,
+// in one of two forms:
+//  * SPLIT (64 rows per workgroup): the four waves split the p range into
+//    quarters and sum their partial rows in LDS in wave order.  For a single
+//    short block of vectors that puts four times as many workgroups and loads
+//    in flight as one row per thread over all of p would.
+//  * otherwise (256 rows per workgroup): each thread runs over all of p.  The
+//    persistent grouped launch uses this form: its items are then 4x fewer,
+//    and each item pays the job lookup and the staging of C only once.
+constexpr int GEMM_QB = 16, GEMM_PB = 128;
+template <bool SPLIT>
+constexpr int gemm_rows() { return SPLIT ? 64 : 256; }
 
+template <bool SPLIT>
 struct GemmSmem {
   union {
-    double Cs[GEMM_PB][GEMM_QB];           // a chunk of C
-    double red[4][GEMM_RB][GEMM_QB + 1];   // the waves' partial rows
+    double Cs[GEMM_PB][GEMM_QB];                 // a chunk of C
+    double red[SPLIT ? 4 : 1][64][GEMM_QB + 1];  // the waves' partial rows
   };
 };
 
-template <typename T>
+template <typename T, bool SPLIT>
 __device__ __forceinline__ void gemm_block(int64_t N, int p, int q, double alpha,
                                            const T* __restrict__ A, int64_t lda,
                                            const double* __restrict__ C, int ldc, double beta,
                                            T* __restrict__ Y, int64_t ldy, int64_t rblock,
-                                           int qblock, GemmSmem& sm) {
+                                           int qblock, GemmSmem<SPLIT>& sm) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t r = rblock * GEMM_RB + lane;
+  const int64_t r = rblock * gemm_rows<SPLIT>() + (SPLIT ? lane : (int)threadIdx.x);
   const int q0 = qblock * GEMM_QB;
   const int nq = (q - q0 < GEMM_QB) ? q - q0 : GEMM_QB;
   double acc[GEMM_QB];
@@ -659,8 +666,8 @@ __device__ __forceinline__ void gemm_block(int64_t N, int p, int q, double alpha
       sm.Cs[i][j] = (i < np && j < nq) ? C[(pb + i) + (int64_t)(q0 + j) * ldc] : 0.0;
     }
     __syncthreads();
-    const int per = (np + 3) / 4;
-    const int ib = (wave * per < np) ? wave * per : np;
+    const int per = SPLIT ? (np + 3) / 4 : np;
+    const int ib = SPLIT ? ((wave * per < np) ? wave * per : np) : 0;
     const int ie = (ib + per < np) ? ib + per : np;
     if (r < N) {
       // eight columns of A per step, fetched before they are used
@@ -679,24 +686,35 @@ __device__ __forceinline__ void gemm_block(int64_t N, int p, int q, double alpha
       }
     }
   }
-  __syncthreads();  // the last chunk of C is dead
+  if constexpr (SPLIT) {
+    __syncthreads();  // the last chunk of C is dead
 #pragma unroll
-  for (int j = 0; j < GEMM_QB; ++j) sm.red[wave][lane][j] = acc[j];
-  __syncthreads();
-  if (r < N) {
-    // wave w finishes columns 4w .. 4w+3 of the lane's row
+    for (int j = 0; j < GEMM_QB; ++j) sm.red[wave][lane][j] = acc[j];
+    __syncthreads();
+    if (r < N) {
+      // wave w finishes columns 4w .. 4w+3 of the lane's row
 #pragma unroll
-    for (int jj = 0; jj < GEMM_QB / 4; ++jj) {
-      const int j = wave * (GEMM_QB / 4) + jj;
+      for (int jj = 0; jj < GEMM_QB / 4; ++jj) {
+        const int j = wave * (GEMM_QB / 4) + jj;
+        if (j < nq) {
+          const double v = sm.red[0][lane][j] + sm.red[1][lane][j] + sm.red[2][lane][j] + sm.red[3][lane][j];
+          T* y = Y + r + (int64_t)(q0 + j) * ldy;
+          const double old = (beta != 0.0) ? (double)(*y) : 0.0;
+          *y = (T)(beta * old + alpha * v);
+        }
+      }
+    }
+  } else if (r < N) {
+#pragma unroll
+    for (int j = 0; j < GEMM_QB; ++j) {
       if (j < nq) {
-        const double v = sm.red[0][lane][j] + sm.red[1][lane][j] + sm.red[2][lane][j] + sm.red[3][lane][j];
         T* y = Y + r + (int64_t)(q0 + j) * ldy;
         const double old = (beta != 0.0) ? (double)(*y) : 0.0;
-        *y = (T)(beta * old + alpha * v);
+        *y = (T)(beta * old + alpha * acc[j]);
       }
     }
   }
-  __syncthreads();  // `red` is reused by the next work item of a persistent loop
+  __syncthreads();  // the LDS is reused by the next work item of a persistent loop
 }
 
 // ------------------------------------------------ per-column (diagonal) dots

@@ -179,15 +179,15 @@ template void dot_job_shape<float, float>(DotJob<float, float>&, int64_t*, int64
 
 // ------------------------------------------------------------ basis update
 int64_t gemm_job_items(int64_t N, int q) {
-  return (N > 0 && q > 0) ? ((N + GEMM_RB - 1) / GEMM_RB) * ((q + GEMM_QB - 1) / GEMM_QB) : 0;
+  return (N > 0 && q > 0) ? ((N + gemm_rows<false>() - 1) / gemm_rows<false>()) * ((q + GEMM_QB - 1) / GEMM_QB) : 0;
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_grouped(DevTab<GemmJob<T>> t) {
-  __shared__ GemmSmem sm;
+  __shared__ GemmSmem<false> sm;
   for_wg_items(t, 0, [&](const GemmJob<T>& j, int64_t w) {
-    const int64_t nrb = (j.N + GEMM_RB - 1) / GEMM_RB;
-    gemm_block<T>(j.N, j.p, j.q, j.alpha, j.A, j.lda, j.C, j.ldc, j.beta, j.Y, j.ldy, w % nrb,
+    const int64_t nrb = (j.N + gemm_rows<false>() - 1) / gemm_rows<false>();
+    gemm_block<T, false>(j.N, j.p, j.q, j.alpha, j.A, j.lda, j.C, j.ldc, j.beta, j.Y, j.ldy, w % nrb,
                   (int)(w / nrb), sm);
   });
 }

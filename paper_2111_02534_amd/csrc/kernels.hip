@@ -213,8 +213,8 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int64_t N, int p, int q, double
                                                  const T* __restrict__ A, int64_t lda,
                                                  const double* __restrict__ C, int ldc,
                                                  double beta, T* __restrict__ Y, int64_t ldy) {
-  __shared__ GemmSmem sm;
-  gemm_block<T>(N, p, q, alpha, A, lda, C, ldc, beta, Y, ldy, blockIdx.x, blockIdx.y, sm);
+  __shared__ GemmSmem<true> sm;
+  gemm_block<T, true>(N, p, q, alpha, A, lda, C, ldc, beta, Y, ldy, blockIdx.x, blockIdx.y, sm);
 }
 
 template <typename T>
@@ -222,7 +222,7 @@ hipError_t launch_gemm_nn(int64_t N, int p, int q, double alpha, const T* A, int
                           const double* C, int ldc, double beta, T* Y, int64_t ldy,
                           hipStream_t s) {
   if (N <= 0 || q <= 0) return hipSuccess;
-  dim3 grid((unsigned)((N + GEMM_RB - 1) / GEMM_RB), (q + GEMM_QB - 1) / GEMM_QB);
+  dim3 grid((unsigned)((N + gemm_rows<true>() - 1) / gemm_rows<true>()), (q + GEMM_QB - 1) / GEMM_QB);
   hipLaunchKernelGGL((k_gemm_nn<T>), grid, dim3(256), 0, s, N, p, q, alpha, A, lda, C, ldc, beta,
                      Y, ldy);
   return hipGetLastError();
