@@ -15,6 +15,7 @@
 // device addresses; with opts.graph it is captured once as a HIP graph and
 // replayed in every outer iteration after the tables have been rewritten.
 #include <algorithm>
+#include <utility>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -392,7 +393,7 @@ tp3b_status BatchedJdqr<TW>::setup() {
     size_t b = 0;
     b += al(8 * N * (nev_ + m_max_ + b_));          // QV
     b += al(8 * N * (m_max_ + b_ + nev_));          // AV
-    b += al(8 * N * (m_max_ + b_));                 // TMP
+    b += al(8 * N * (m_max_ + b_ + nev_));          // TMP (swaps roles with AV)
     b += al(8 * N * b_);                            // Rres
     if (use_prec_) b += 2 * al(8 * N * qt_max_);    // PQ, Yp
     b += al(8 * N * b_);                            // Tc
@@ -418,7 +419,7 @@ tp3b_status BatchedJdqr<TW>::setup() {
     };
     I.QV = (double*)take(8 * N * (nev_ + m_max_ + b_));
     I.AVb = (double*)take(8 * N * (m_max_ + b_ + nev_));
-    I.TMP = (double*)take(8 * N * (m_max_ + b_));
+    I.TMP = (double*)take(8 * N * (m_max_ + b_ + nev_));
     I.Rres = (double*)take(8 * N * b_);
     if (use_prec_) {
       I.PQ = (double*)take(8 * N * qt_max_);
@@ -965,7 +966,16 @@ tp3b_status BatchedJdqr<TW>::iterate() {
         Yb.push_back(pass ? I.AV() : I.V());
       }
       TP3B_TRY(gemm64(rot, p, q, 1.0, A, C, ldc, 0.0, Y));
-      TP3B_TRY(copy64(rot, nc, 1.0, X, Yb));
+      if (pass == 0) {
+        TP3B_TRY(copy64(rot, nc, 1.0, X, Yb));
+      } else {
+        // the rotated A V stays where it was written (no copy back)
+        for (int i : rot) {
+          Inst& I = in_[i];
+          std::swap(I.AVb, I.TMP);
+          I.av0 = 0;
+        }
+      }
     }
   }
   // 2. residuals R = (I - Q Q^T)(A U - V T[:, :nb])

@@ -18,6 +18,7 @@
 // the converged pairs meet the FP64 residual tolerance whatever the inner
 // precision.
 #include <algorithm>
+#include <utility>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -177,7 +178,8 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   DevBuf QVb, AVb, TMPb, Rresb, PQb, Ypb, Qtwb, Ypwb, Vgb, Wb, Zb, Tcb, smallb;
   TP3B_HIP(dalloc(QVb, sizeof(double) * N * qv_cols));
   TP3B_HIP(dalloc(AVb, sizeof(double) * N * av_cols));
-  TP3B_HIP(dalloc(TMPb, sizeof(double) * N * (m_max + b)));
+  // same capacity as A V: the two buffers swap roles after a rotation
+  TP3B_HIP(dalloc(TMPb, sizeof(double) * N * av_cols));
   TP3B_HIP(dalloc(Rresb, sizeof(double) * N * b));
   if (use_prec) {
     TP3B_HIP(dalloc(PQb, sizeof(double) * N * qt_max));
@@ -355,7 +357,9 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       TP3B_HIP(launch_gemm_nn<double>(N, m, m, 1.0, V(), N, dS, m, 0.0, TMP, N, s));
       TP3B_HIP(hipMemcpyAsync(V(), TMP, sizeof(double) * N * m, hipMemcpyDeviceToDevice, s));
       TP3B_HIP(launch_gemm_nn<double>(N, m, m, 1.0, AV(), N, dS, m, 0.0, TMP, N, s));
-      TP3B_HIP(hipMemcpyAsync(AV(), TMP, sizeof(double) * N * m, hipMemcpyDeviceToDevice, s));
+      // the rotated A V stays where it was written (no copy back)
+      std::swap(AVbase, TMP);
+      av0 = 0;
     }
     M = T;
     const int nb = std::min(b, m);
