@@ -353,19 +353,44 @@ template hipError_t launch_convert<float, float>(int64_t, int, double, const flo
 // factorises it there (the serial arithmetic of the grouped form, without a
 // global-memory round trip per element), and the factor is written back in
 // parallel.  nx <= TRSM_MAX.
+// Right-looking form on one wavefront: step j scales row j of R and removes
+// its outer product from the trailing upper triangle, so every entry receives
+// the same terms in the same order as the column-by-column (left-looking)
+// serial form.
 __global__ __launch_bounds__(64) void k_chol_small(int nx, const double* __restrict__ G,
                                                    const double* __restrict__ n0, double drop_tol,
                                                    double* __restrict__ R, int* __restrict__ flags) {
-  __shared__ double Gs[TRSM_MAX * TRSM_MAX], Rs[TRSM_MAX * TRSM_MAX], ns[TRSM_MAX];
-  __shared__ int fs[TRSM_MAX];
+  __shared__ double Gs[TRSM_MAX * TRSM_MAX], Rs[TRSM_MAX * TRSM_MAX];
   const int t = threadIdx.x;
-  for (int e = t; e < nx * nx; e += 64) Gs[e] = G[e];
-  for (int e = t; e < nx; e += 64) ns[e] = n0[e];
+  for (int e = t; e < nx * nx; e += 64) {
+    Gs[e] = G[e];
+    Rs[e] = 0.0;
+  }
   __syncthreads();
-  if (t == 0) chol_small_serial(nx, Gs, ns, drop_tol, Rs, fs);
-  __syncthreads();
+  for (int j = 0; j < nx; ++j) {
+    const double d = Gs[j + j * nx];
+    const double thr = drop_tol * drop_tol * n0[j];
+    if (!(d > thr) || !(d > 0.0)) {
+      // dependent column: left unscaled (replaced later), contributes nothing
+      if (t == 0) {
+        flags[j] = 1;
+        Rs[j + j * nx] = 1.0;
+      }
+      __syncthreads();
+      continue;
+    }
+    if (t == 0) flags[j] = 0;
+    const double rjj = sqrt(d);
+    for (int c = j + t; c < nx; c += 64) Rs[j + c * nx] = (c == j) ? rjj : Gs[j + c * nx] / rjj;
+    __syncthreads();
+    const int m = nx - j - 1;
+    for (int e = t; e < m * m; e += 64) {
+      const int a = j + 1 + e % m, c = j + 1 + e / m;
+      if (c >= a) Gs[a + c * nx] -= Rs[j + a * nx] * Rs[j + c * nx];
+    }
+    __syncthreads();
+  }
   for (int e = t; e < nx * nx; e += 64) R[e] = Rs[e];
-  for (int e = t; e < nx; e += 64) flags[e] = fs[e];
 }
 
 __global__ void k_gram_diag(int nx, const double* __restrict__ G, double* __restrict__ n0,
@@ -529,26 +554,34 @@ __global__ __launch_bounds__(64) void k_small_inverse(int n, const double* __res
                                                       double* __restrict__ Ainv,
                                                       int* __restrict__ singular) {
   __shared__ double M[SI_MAXN][2 * SI_MAXN + 1];
-  __shared__ int piv;
-  __shared__ int bad;
+  __shared__ double fcol[SI_MAXN];
   const int t = threadIdx.x, w = 2 * n;
-  if (t == 0) bad = 0;
   for (int e = t; e < n * w; e += 64) {
     const int r = e / w, c = e % w;
     M[r][c] = (c < n) ? A[r + (int64_t)c * n] : (c - n == r ? 1.0 : 0.0);
   }
   __syncthreads();
+  int bad = 0;
   for (int k = 0; k < n; ++k) {
-    if (t == 0) {
-      int p = k;
-      for (int r = k + 1; r < n; ++r)
-        if (fabs(M[r][k]) > fabs(M[p][k])) p = r;
-      piv = p;
-      if (M[p][k] == 0.0) bad = 1;
+    // pivot: the first row r >= k of largest |M[r][k]| (wave argmax, ties to
+    // the smaller row; NaN never wins), the same row on every lane
+    double v = (t >= k && t < n) ? fabs(M[t][k]) : -1.0;
+    if (!(v == v)) v = -1.0;
+    int idx = t;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off, 64);
+      const int oi = __shfl_xor(idx, off, 64);
+      if (ov > v || (ov == v && oi < idx)) {
+        v = ov;
+        idx = oi;
+      }
     }
-    __syncthreads();
-    if (bad) break;
-    const int p = piv;
+    int p = __shfl(idx, 0, 64);
+    if (p < k || p >= n) p = k;
+    if (M[p][k] == 0.0) {
+      bad = 1;
+      break;
+    }
     if (p != k)
       for (int c = t; c < w; c += 64) {
         const double u = M[k][c];
@@ -556,13 +589,15 @@ __global__ __launch_bounds__(64) void k_small_inverse(int n, const double* __res
         M[p][c] = u;
       }
     __syncthreads();
+    // the multipliers of the other rows, before row k is scaled
+    if (t < n) fcol[t] = M[t][k];
     const double d = M[k][k];
     __syncthreads();
     for (int c = t; c < w; c += 64) M[k][c] /= d;
     __syncthreads();
-    if (t < n && t != k) {
-      const double f = M[t][k];
-      for (int c = 0; c < w; ++c) M[t][c] -= f * M[k][c];
+    for (int e = t; e < n * w; e += 64) {
+      const int r = e / w, c = e % w;
+      if (r != k) M[r][c] -= fcol[r] * M[k][c];
     }
     __syncthreads();
   }
