@@ -11,7 +11,9 @@
  * Conventions shared by every call
  *  - Every function returns a tp3b_status: 0 on success, a negative code on
  *    failure.  No function aborts or exits; tp3b_last_error() returns a message
- *    for the calling thread's last failure.
+ *    for the calling thread's last failure.  No C++ exception leaves the
+ *    library: a failed host allocation returns TP3B_ENOMEM, any other host
+ *    exception TP3B_EDEVICE with its message.
  *  - Vectors are 2d-mode tensors stored with the x modes slowest: 1D
  *    psi[i][j] at i*n_y + j (eq. (6)); 2D psi[x1][x2][y1][y2].  N is the product
  *    of the mode sizes.

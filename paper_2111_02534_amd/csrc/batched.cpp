@@ -1464,169 +1464,185 @@ extern "C" {
 tp3b_status tp3b_apply_H_batched(const tp3b_op* ops, int32_t count, int32_t prec, int32_t nvec,
                                  const void* const* X, const int64_t* ldx, void* const* Y,
                                  const int64_t* ldy, const double* const* shifts, void* stream) {
-  tp3b_status st = check_batched_apply(ops, count, prec, nvec, X, ldx, Y, ldy, false);
-  if (st != TP3B_OK || nvec == 0) return st;
-  hipStream_t s = (hipStream_t)stream;
-  if (prec == TP3B_FP64)
-    return apply_batched<double>(ops, count, nvec, X, ldx, Y, ldy, shifts, false, false, s);
-  return apply_batched<float>(ops, count, nvec, X, ldx, Y, ldy, shifts, false, prec == TP3B_BF16X3, s);
+  try {
+    tp3b_status st = check_batched_apply(ops, count, prec, nvec, X, ldx, Y, ldy, false);
+    if (st != TP3B_OK || nvec == 0) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == TP3B_FP64)
+      return apply_batched<double>(ops, count, nvec, X, ldx, Y, ldy, shifts, false, false, s);
+    return apply_batched<float>(ops, count, nvec, X, ldx, Y, ldy, shifts, false, prec == TP3B_BF16X3, s);
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 tp3b_status tp3b_apply_prec_batched(const tp3b_op* ops, int32_t count, int32_t prec, int32_t nvec,
                                     const void* const* X, const int64_t* ldx, void* const* Y,
                                     const int64_t* ldy, void* stream) {
-  tp3b_status st = check_batched_apply(ops, count, prec, nvec, X, ldx, Y, ldy, true);
-  if (st != TP3B_OK || nvec == 0) return st;
-  hipStream_t s = (hipStream_t)stream;
-  if (prec == TP3B_FP64)
-    return apply_batched<double>(ops, count, nvec, X, ldx, Y, ldy, nullptr, true, false, s);
-  return apply_batched<float>(ops, count, nvec, X, ldx, Y, ldy, nullptr, true, prec == TP3B_BF16X3, s);
+  try {
+    tp3b_status st = check_batched_apply(ops, count, prec, nvec, X, ldx, Y, ldy, true);
+    if (st != TP3B_OK || nvec == 0) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == TP3B_FP64)
+      return apply_batched<double>(ops, count, nvec, X, ldx, Y, ldy, nullptr, true, false, s);
+    return apply_batched<float>(ops, count, nvec, X, ldx, Y, ldy, nullptr, true, prec == TP3B_BF16X3, s);
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 tp3b_status tp3b_autotune_batched(const tp3b_op* ops, int32_t count, int32_t prec, int32_t nvec,
                                   int32_t reps) {
-  tp3b_status st = check_batch(ops, count, false);
-  if (st != TP3B_OK) return st;
-  if (prec != TP3B_FP64 && prec != TP3B_FP32 && prec != TP3B_BF16X3)
-    return fail(TP3B_EINVAL, "unknown precision");
-  if (nvec < 1 || reps < 1) return fail(TP3B_EINVAL, "nvec and reps must be >= 1");
-  for (int i = 0; i < count; ++i)
-    if (nvec > ops[i]->work_vecs) return fail(TP3B_EINVAL, "autotune_batched: nvec too large");
-  const bool f64 = prec == TP3B_FP64, bf3 = prec == TP3B_BF16X3;
-  const size_t es = f64 ? 8 : 4;
-  // groups of equal grid size
-  std::vector<std::vector<int>> groups;
-  std::vector<std::pair<int, int>> keys;
-  for (int i = 0; i < count; ++i) {
-    const std::pair<int, int> key(ops[i]->n[0], ops[i]->n[1]);
-    size_t g = 0;
-    while (g < keys.size() && keys[g] != key) ++g;
-    if (g == keys.size()) {
-      keys.push_back(key);
-      groups.emplace_back();
-    }
-    groups[g].push_back(i);
-  }
-  // scratch blocks (zero: timing does not depend on the values)
-  size_t maxb = 0;
-  for (int i = 0; i < count; ++i) maxb += es * ops[i]->N * nvec;
-  void *X = nullptr, *Y = nullptr;
-  TP3B_HIP(hipMalloc(&X, maxb));
-  if (hipMalloc(&Y, maxb) != hipSuccess) {
-    (void)hipFree(X);
-    return fail(TP3B_ENOMEM, "autotune_batched: scratch allocation failed");
-  }
-  (void)hipMemset(X, 0, maxb);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
-  st = TP3B_OK;
-  const int pi = f64 ? TP3B_FP64 : (bf3 ? TP3B_BF16X3 : TP3B_FP32);
-  for (size_t g = 0; g < groups.size() && st == TP3B_OK; ++g) {
-    const std::vector<int>& gi = groups[g];
-    std::vector<tp3b_op> gops;
-    std::vector<const void*> xs;
-    std::vector<void*> ys;
-    std::vector<int64_t> ld;
-    size_t o = 0;
-    for (int i : gi) {
-      gops.push_back(ops[i]);
-      xs.push_back((char*)X + o);
-      ys.push_back((char*)Y + o);
-      ld.push_back(ops[i]->N);
-      o += es * ops[i]->N * nvec;
-    }
-    const int nx = keys[g].first, ny = keys[g].second;
-    for (int kind = 0; kind < 2 && st == TP3B_OK; ++kind) {
-      const bool kprec = kind == 1;
-      if (kprec) {
-        bool all = true;
-        for (int i : gi) all &= ops[i]->have_prec;
-        if (!all) break;
+  try {
+    tp3b_status st = check_batch(ops, count, false);
+    if (st != TP3B_OK) return st;
+    if (prec != TP3B_FP64 && prec != TP3B_FP32 && prec != TP3B_BF16X3)
+      return fail(TP3B_EINVAL, "unknown precision");
+    if (nvec < 1 || reps < 1) return fail(TP3B_EINVAL, "nvec and reps must be >= 1");
+    for (int i = 0; i < count; ++i)
+      if (nvec > ops[i]->work_vecs) return fail(TP3B_EINVAL, "autotune_batched: nvec too large");
+    const bool f64 = prec == TP3B_FP64, bf3 = prec == TP3B_BF16X3;
+    const size_t es = f64 ? 8 : 4;
+    // groups of equal grid size
+    std::vector<std::vector<int>> groups;
+    std::vector<std::pair<int, int>> keys;
+    for (int i = 0; i < count; ++i) {
+      const std::pair<int, int> key(ops[i]->n[0], ops[i]->n[1]);
+      size_t g = 0;
+      while (g < keys.size() && keys[g] != key) ++g;
+      if (g == keys.size()) {
+        keys.push_back(key);
+        groups.emplace_back();
       }
-      double best = 1e300;
-      int best_tile = -1;
-      std::vector<int> saved;
-      for (int i : gi) saved.push_back(ops[i]->tile_override);
-      for (int tile = 0; tile < NUM_TILE_CFGS && st == TP3B_OK; ++tile) {
-        const int tm = tile_rows(tile), tn = tile_cols(tile);
-        if (tm > 32 && (tm > nx || tn > ny)) continue;
-        if (bf3 && tm == 32) continue;
-        for (int i : gi) ops[i]->tile_override = tile;
-        auto run = [&]() -> tp3b_status {
-          if (f64)
-            return apply_batched<double>(gops.data(), (int)gops.size(), nvec, xs.data(), ld.data(),
-                                         ys.data(), ld.data(), nullptr, kprec, false, nullptr);
-          return apply_batched<float>(gops.data(), (int)gops.size(), nvec, xs.data(), ld.data(),
-                                      ys.data(), ld.data(), nullptr, kprec, bf3, nullptr);
-        };
-        st = run();
-        if (st != TP3B_OK) break;
-        // apply_batched synchronises before staging its tables, so each
-        // repetition is timed separately and the times summed
-        double ms_total = 0.0;
-        for (int r = 0; r < reps && st == TP3B_OK; ++r) {
-          (void)hipDeviceSynchronize();
-          (void)hipEventRecord(e0, nullptr);
+      groups[g].push_back(i);
+    }
+    // scratch blocks (zero: timing does not depend on the values)
+    size_t maxb = 0;
+    for (int i = 0; i < count; ++i) maxb += es * ops[i]->N * nvec;
+    void *X = nullptr, *Y = nullptr;
+    TP3B_HIP(hipMalloc(&X, maxb));
+    if (hipMalloc(&Y, maxb) != hipSuccess) {
+      (void)hipFree(X);
+      return fail(TP3B_ENOMEM, "autotune_batched: scratch allocation failed");
+    }
+    (void)hipMemset(X, 0, maxb);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    st = TP3B_OK;
+    const int pi = f64 ? TP3B_FP64 : (bf3 ? TP3B_BF16X3 : TP3B_FP32);
+    for (size_t g = 0; g < groups.size() && st == TP3B_OK; ++g) {
+      const std::vector<int>& gi = groups[g];
+      std::vector<tp3b_op> gops;
+      std::vector<const void*> xs;
+      std::vector<void*> ys;
+      std::vector<int64_t> ld;
+      size_t o = 0;
+      for (int i : gi) {
+        gops.push_back(ops[i]);
+        xs.push_back((char*)X + o);
+        ys.push_back((char*)Y + o);
+        ld.push_back(ops[i]->N);
+        o += es * ops[i]->N * nvec;
+      }
+      const int nx = keys[g].first, ny = keys[g].second;
+      for (int kind = 0; kind < 2 && st == TP3B_OK; ++kind) {
+        const bool kprec = kind == 1;
+        if (kprec) {
+          bool all = true;
+          for (int i : gi) all &= ops[i]->have_prec;
+          if (!all) break;
+        }
+        double best = 1e300;
+        int best_tile = -1;
+        std::vector<int> saved;
+        for (int i : gi) saved.push_back(ops[i]->tile_override);
+        for (int tile = 0; tile < NUM_TILE_CFGS && st == TP3B_OK; ++tile) {
+          const int tm = tile_rows(tile), tn = tile_cols(tile);
+          if (tm > 32 && (tm > nx || tn > ny)) continue;
+          if (bf3 && tm == 32) continue;
+          for (int i : gi) ops[i]->tile_override = tile;
+          auto run = [&]() -> tp3b_status {
+            if (f64)
+              return apply_batched<double>(gops.data(), (int)gops.size(), nvec, xs.data(), ld.data(),
+                                           ys.data(), ld.data(), nullptr, kprec, false, nullptr);
+            return apply_batched<float>(gops.data(), (int)gops.size(), nvec, xs.data(), ld.data(),
+                                        ys.data(), ld.data(), nullptr, kprec, bf3, nullptr);
+          };
           st = run();
-          (void)hipEventRecord(e1, nullptr);
-          (void)hipEventSynchronize(e1);
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          ms_total += ms;
+          if (st != TP3B_OK) break;
+          // apply_batched synchronises before staging its tables, so each
+          // repetition is timed separately and the times summed
+          double ms_total = 0.0;
+          for (int r = 0; r < reps && st == TP3B_OK; ++r) {
+            (void)hipDeviceSynchronize();
+            (void)hipEventRecord(e0, nullptr);
+            st = run();
+            (void)hipEventRecord(e1, nullptr);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms_total += ms;
+          }
+          if (ms_total / reps < best) {
+            best = ms_total / reps;
+            best_tile = tile;
+          }
         }
-        if (ms_total / reps < best) {
-          best = ms_total / reps;
-          best_tile = tile;
-        }
+        for (size_t a = 0; a < gi.size(); ++a) ops[gi[a]]->tile_override = saved[a];
+        if (st == TP3B_OK)
+          for (int i : gi) ops[i]->tuned[pi][kind] = best_tile;
       }
-      for (size_t a = 0; a < gi.size(); ++a) ops[gi[a]]->tile_override = saved[a];
-      if (st == TP3B_OK)
-        for (int i : gi) ops[i]->tuned[pi][kind] = best_tile;
     }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(X);
+    (void)hipFree(Y);
+    return st;
+  } catch (...) {
+    return exception_status();
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipFree(X);
-  (void)hipFree(Y);
-  return st;
 }
 
 tp3b_status tp3b_jdqr_solve_batched(const tp3b_op* ops, int32_t count, const tp3b_jdqr_opts* opts,
                                     double* evals, double* resnorm, int32_t* n_conv,
                                     int32_t* n_outer, double* const* Q, tp3b_jdqr_stats* stats) {
-  if (!opts) return fail(TP3B_EINVAL, "null options");
-  tp3b_jdqr_opts o = *opts;
-  if (o.nev < 1 || o.block < 1) return fail(TP3B_EINVAL, "nev and block must be >= 1");
-  if (o.block > 32) return fail(TP3B_EINVAL, "block must be <= 32");
-  if (o.gmres_steps <= 0) o.gmres_steps = 10;
-  if (o.gmres_steps > 38) return fail(TP3B_EINVAL, "gmres_steps must be <= 38");
-  if (o.max_outer <= 0) o.max_outer = 1000;
-  if (!(o.tol > 0)) o.tol = 1e-12;
-  if (!(o.switch_tol > 0)) o.switch_tol = 1e-2;
-  int mmax = std::max(4 * o.block, 2 * (o.nev + o.block));
-  mmax = ((mmax + o.block - 1) / o.block) * o.block;
-  if (o.m_max <= 0) o.m_max = mmax;
-  if (o.m_min <= 0) o.m_min = o.m_max / 2;
-  if (o.m_min < o.block || o.m_max < o.m_min + o.block)
-    return fail(TP3B_EINVAL, "need block <= m_min and m_min + block <= m_max");
-  if (o.nev + o.m_max + o.block > 64) return fail(TP3B_EINVAL, "batched: nev + m_max + block must be <= 64");
-  tp3b_status st = check_batch(ops, count, o.precond != 0);
-  if (st != TP3B_OK) return st;
-  for (int i = 0; i < count; ++i) {
-    if (ops[i]->N < (int64_t)(o.nev + o.m_max + o.block))
-      return fail(TP3B_EINVAL, "batched: an instance is too small for nev + m_max + block vectors");
-    if (o.precond && (o.block > ops[i]->work_vecs || o.nev > ops[i]->work_vecs))
-      return fail(TP3B_EINVAL, "batched: block larger than the preconditioner's work buffer");
-  }
-  if (o.inner_prec != TP3B_FP64 && o.inner_prec != TP3B_FP32 && o.inner_prec != TP3B_BF16X3)
-    return fail(TP3B_EINVAL, "unknown inner precision");
-  if (o.inner_prec == TP3B_FP64) {
-    BatchedJdqr<double> solver(ops, count, o, false);
+  try {
+    if (!opts) return fail(TP3B_EINVAL, "null options");
+    tp3b_jdqr_opts o = *opts;
+    if (o.nev < 1 || o.block < 1) return fail(TP3B_EINVAL, "nev and block must be >= 1");
+    if (o.block > 32) return fail(TP3B_EINVAL, "block must be <= 32");
+    if (o.gmres_steps <= 0) o.gmres_steps = 10;
+    if (o.gmres_steps > 38) return fail(TP3B_EINVAL, "gmres_steps must be <= 38");
+    if (o.max_outer <= 0) o.max_outer = 1000;
+    if (!(o.tol > 0)) o.tol = 1e-12;
+    if (!(o.switch_tol > 0)) o.switch_tol = 1e-2;
+    int mmax = std::max(4 * o.block, 2 * (o.nev + o.block));
+    mmax = ((mmax + o.block - 1) / o.block) * o.block;
+    if (o.m_max <= 0) o.m_max = mmax;
+    if (o.m_min <= 0) o.m_min = o.m_max / 2;
+    if (o.m_min < o.block || o.m_max < o.m_min + o.block)
+      return fail(TP3B_EINVAL, "need block <= m_min and m_min + block <= m_max");
+    if (o.nev + o.m_max + o.block > 64) return fail(TP3B_EINVAL, "batched: nev + m_max + block must be <= 64");
+    tp3b_status st = check_batch(ops, count, o.precond != 0);
+    if (st != TP3B_OK) return st;
+    for (int i = 0; i < count; ++i) {
+      if (ops[i]->N < (int64_t)(o.nev + o.m_max + o.block))
+        return fail(TP3B_EINVAL, "batched: an instance is too small for nev + m_max + block vectors");
+      if (o.precond && (o.block > ops[i]->work_vecs || o.nev > ops[i]->work_vecs))
+        return fail(TP3B_EINVAL, "batched: block larger than the preconditioner's work buffer");
+    }
+    if (o.inner_prec != TP3B_FP64 && o.inner_prec != TP3B_FP32 && o.inner_prec != TP3B_BF16X3)
+      return fail(TP3B_EINVAL, "unknown inner precision");
+    if (o.inner_prec == TP3B_FP64) {
+      BatchedJdqr<double> solver(ops, count, o, false);
+      return solver.run(evals, resnorm, n_conv, n_outer, Q, stats);
+    }
+    BatchedJdqr<float> solver(ops, count, o, o.inner_prec == TP3B_BF16X3);
     return solver.run(evals, resnorm, n_conv, n_outer, Q, stats);
+  } catch (...) {
+    return exception_status();
   }
-  BatchedJdqr<float> solver(ops, count, o, o.inner_prec == TP3B_BF16X3);
-  return solver.run(evals, resnorm, n_conv, n_outer, Q, stats);
 }
 
 }  // extern "C"

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <exception>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -47,14 +49,27 @@ void parallel_for(int n, F&& f) {
     return;
   }
   std::atomic<int> next{0};
+  std::exception_ptr err = nullptr;
+  std::mutex err_m;
   auto work = [&]() {
-    for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
+    try {
+      for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
+    } catch (...) {
+      std::lock_guard<std::mutex> g(err_m);
+      if (!err) err = std::current_exception();
+      next.store(n);  // the other threads stop at their next index
+    }
   };
   std::vector<std::thread> th;
-  th.reserve(nt - 1);
-  for (int t = 1; t < nt; ++t) th.emplace_back(work);
+  try {
+    th.reserve(nt - 1);
+    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+  } catch (...) {
+    // fewer threads than asked for: the calling thread takes what is left
+  }
   work();
   for (std::thread& x : th) x.join();
+  if (err) std::rethrow_exception(err);
 }
 
 }  // namespace tp3b
@@ -90,6 +105,10 @@ namespace tp3b {
 void set_error(const std::string& msg);
 tp3b_status fail(tp3b_status code, const std::string& msg);
 tp3b_status hip_fail(hipError_t e, const char* where);
+// Inside a catch block: the status for the exception in flight (ENOMEM for a
+// failed host allocation, EDEVICE otherwise), with its message recorded.  The
+// C-ABI entry points catch every exception and return this.
+tp3b_status exception_status();
 
 #define TP3B_HIP(...)                                              \
   do {                                                             \

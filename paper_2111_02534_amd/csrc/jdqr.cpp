@@ -701,53 +701,61 @@ using namespace tp3b;
 extern "C" {
 
 tp3b_status tp3b_jdqr_default_opts(tp3b_jdqr_opts* o) {
-  if (!o) return fail(TP3B_EINVAL, "null options");
-  std::memset(o, 0, sizeof(*o));
-  o->nev = 1;
-  o->block = 1;
-  o->gmres_steps = 10;
-  o->max_outer = 1000;
-  o->precond = 1;
-  o->inner_prec = TP3B_FP64;
-  o->tol = 1e-12;
-  o->switch_tol = 1e-2;
-  o->stall_tol = 1e-8;
-  o->low_start = 3;
-  o->target = NAN;
-  o->seed = 0;
-  return TP3B_OK;
+  try {
+    if (!o) return fail(TP3B_EINVAL, "null options");
+    std::memset(o, 0, sizeof(*o));
+    o->nev = 1;
+    o->block = 1;
+    o->gmres_steps = 10;
+    o->max_outer = 1000;
+    o->precond = 1;
+    o->inner_prec = TP3B_FP64;
+    o->tol = 1e-12;
+    o->switch_tol = 1e-2;
+    o->stall_tol = 1e-8;
+    o->low_start = 3;
+    o->target = NAN;
+    o->seed = 0;
+    return TP3B_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 tp3b_status tp3b_jdqr_solve(tp3b_op op, const tp3b_jdqr_opts* opts, const double* X0, int32_t b0,
                             double* evals, double* Q, double* R, double* resnorm,
                             tp3b_jdqr_stats* stats) {
-  if (!op || !opts) return fail(TP3B_EINVAL, "null operator or options");
-  tp3b_jdqr_opts o = *opts;
-  if (o.nev < 1 || o.block < 1) return fail(TP3B_EINVAL, "nev and block must be >= 1");
-  if (o.block > 32) return fail(TP3B_EINVAL, "block must be <= 32");
-  if (o.gmres_steps <= 0) o.gmres_steps = 10;
-  if (o.gmres_steps > 38) return fail(TP3B_EINVAL, "gmres_steps must be <= 38");
-  if (o.max_outer <= 0) o.max_outer = 1000;
-  if (!(o.tol > 0)) o.tol = 1e-12;
-  if (!(o.switch_tol > 0)) o.switch_tol = 1e-2;
-  int mmax = std::max(4 * o.block, 2 * (o.nev + o.block));
-  mmax = ((mmax + o.block - 1) / o.block) * o.block;
-  if (o.m_max <= 0) o.m_max = mmax;
-  if (o.m_min <= 0) o.m_min = o.m_max / 2;
-  if (o.m_min < o.block || o.m_max < o.m_min + o.block)
-    return fail(TP3B_EINVAL, "need block <= m_min and m_min + block <= m_max");
-  if (op->N < (int64_t)(o.nev + o.m_max + o.block))
-    return fail(TP3B_EINVAL, "problem too small for nev + m_max + block basis vectors");
-  if (o.precond && !op->have_prec)
-    return fail(TP3B_ENOTSUP, "the kinetic preconditioner is unavailable for this operator");
-  if (X0 && b0 < 0) return fail(TP3B_EINVAL, "b0 must be >= 0");
-  TP3B_HIP(hipSetDevice(op->device));
-  if (o.inner_prec != TP3B_FP64 && o.inner_prec != TP3B_FP32 && o.inner_prec != TP3B_BF16X3)
-    return fail(TP3B_EINVAL, "unknown inner precision");
-  if (o.inner_prec != TP3B_FP64)
-    return jdqr_run<float>(op, o, X0, b0, evals, Q, R, resnorm, stats,
-                           o.inner_prec == TP3B_BF16X3);
-  return jdqr_run<double>(op, o, X0, b0, evals, Q, R, resnorm, stats, false);
+  try {
+    if (!op || !opts) return fail(TP3B_EINVAL, "null operator or options");
+    tp3b_jdqr_opts o = *opts;
+    if (o.nev < 1 || o.block < 1) return fail(TP3B_EINVAL, "nev and block must be >= 1");
+    if (o.block > 32) return fail(TP3B_EINVAL, "block must be <= 32");
+    if (o.gmres_steps <= 0) o.gmres_steps = 10;
+    if (o.gmres_steps > 38) return fail(TP3B_EINVAL, "gmres_steps must be <= 38");
+    if (o.max_outer <= 0) o.max_outer = 1000;
+    if (!(o.tol > 0)) o.tol = 1e-12;
+    if (!(o.switch_tol > 0)) o.switch_tol = 1e-2;
+    int mmax = std::max(4 * o.block, 2 * (o.nev + o.block));
+    mmax = ((mmax + o.block - 1) / o.block) * o.block;
+    if (o.m_max <= 0) o.m_max = mmax;
+    if (o.m_min <= 0) o.m_min = o.m_max / 2;
+    if (o.m_min < o.block || o.m_max < o.m_min + o.block)
+      return fail(TP3B_EINVAL, "need block <= m_min and m_min + block <= m_max");
+    if (op->N < (int64_t)(o.nev + o.m_max + o.block))
+      return fail(TP3B_EINVAL, "problem too small for nev + m_max + block basis vectors");
+    if (o.precond && !op->have_prec)
+      return fail(TP3B_ENOTSUP, "the kinetic preconditioner is unavailable for this operator");
+    if (X0 && b0 < 0) return fail(TP3B_EINVAL, "b0 must be >= 0");
+    TP3B_HIP(hipSetDevice(op->device));
+    if (o.inner_prec != TP3B_FP64 && o.inner_prec != TP3B_FP32 && o.inner_prec != TP3B_BF16X3)
+      return fail(TP3B_EINVAL, "unknown inner precision");
+    if (o.inner_prec != TP3B_FP64)
+      return jdqr_run<float>(op, o, X0, b0, evals, Q, R, resnorm, stats,
+                             o.inner_prec == TP3B_BF16X3);
+    return jdqr_run<double>(op, o, X0, b0, evals, Q, R, resnorm, stats, false);
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 }  // extern "C"

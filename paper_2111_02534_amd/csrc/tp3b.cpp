@@ -5,6 +5,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -24,6 +26,17 @@ tp3b_status fail(tp3b_status code, const std::string& msg) {
 tp3b_status hip_fail(hipError_t e, const char* where) {
   g_err = std::string("HIP error '") + hipGetErrorString(e) + "' in " + where;
   return e == hipErrorOutOfMemory ? TP3B_ENOMEM : TP3B_EDEVICE;
+}
+tp3b_status exception_status() {
+  try {
+    throw;
+  } catch (const std::bad_alloc&) {
+    return fail(TP3B_ENOMEM, "host memory allocation failed");
+  } catch (const std::exception& e) {
+    return fail(TP3B_EDEVICE, std::string("host exception: ") + e.what());
+  } catch (...) {
+    return fail(TP3B_EDEVICE, "unknown host exception");
+  }
 }
 
 // ---------------------------------------------------------------- grids
@@ -694,202 +707,222 @@ extern "C" {
 const char* tp3b_last_error(void) { return g_err.c_str(); }
 
 tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* out) {
-  (void)stream;
-  if (!desc || !out) return fail(TP3B_EINVAL, "tp3b_create: null descriptor or output");
-  *out = nullptr;
-  if (desc->ndim != 1 && desc->ndim != 2) return fail(TP3B_EINVAL, "ndim must be 1 or 2");
-  const int nm = 2 * desc->ndim;
-  int64_t N = 1;
-  for (int k = 0; k < nm; ++k) {
-    if (desc->n[k] < 2 || desc->n[k] > 8192) return fail(TP3B_EINVAL, "mode sizes must be in [2, 8192]");
-    if (!(desc->L[k] > 0)) return fail(TP3B_EINVAL, "half-widths L must be positive");
-    N *= desc->n[k];
-  }
-  if (!(desc->c_x > 0) || !(desc->c_y > 0)) return fail(TP3B_EINVAL, "c_x and c_y must be positive");
-  if (desc->pot < TP3B_POT_GAUSS || desc->pot > TP3B_POT_TABLE) return fail(TP3B_EINVAL, "unknown potential");
-  if (desc->pot == TP3B_POT_TABLE && !desc->V_table) return fail(TP3B_EINVAL, "TP3B_POT_TABLE needs V_table");
-  if (desc->pot == TP3B_POT_GAUSS && !(desc->width > 0)) return fail(TP3B_EINVAL, "width must be positive");
-  if (desc->ndim == 2 && (desc->n[0] != desc->n[1] || desc->n[2] != desc->n[3]))
-    return fail(TP3B_ENOTSUP, "2D operators need n[0] == n[1] and n[2] == n[3]");
-  if (desc->grid != TP3B_GRID_CGL && desc->grid != TP3B_GRID_MAPPED)
-    return fail(TP3B_EINVAL, "unknown grid");
-  for (int k = 0; k < nm; ++k) {
-    if (desc->parity[k] < -1 || desc->parity[k] > 1) return fail(TP3B_EINVAL, "parity must be -1, 0 or +1");
-    if (desc->parity[k] != 0 && desc->grid != TP3B_GRID_MAPPED)
-      return fail(TP3B_EINVAL, "parity half grids need TP3B_GRID_MAPPED");
-  }
-
-  tp3b_op op = new tp3b_op_s();
-  op->ndim = desc->ndim;
-  op->nmodes = nm;
-  op->N = N;
-  op->cx = desc->c_x;
-  op->cy = desc->c_y;
-  op->pot = desc->pot;
-  op->v0 = desc->v0;
-  op->width = desc->width;
-  op->mu_hl = desc->mu_hl > 0 ? desc->mu_hl : 1.0;
-  (void)hipGetDevice(&op->device);
-  std::vector<double> x[4];
-  for (int k = 0; k < nm; ++k) {
-    op->n[k] = desc->n[k];
-    op->L[k] = desc->L[k];
-    mode_grid(desc, k, op->D2h[k], x[k]);
-  }
-  // Potential V = u(|y - x/2|) + u(|y + x/2|) on the tensor grid (eq. (3)).
-  op->Vh.resize(N);
-  if (desc->pot == TP3B_POT_TABLE) {
-    std::memcpy(op->Vh.data(), desc->V_table, sizeof(double) * N);
-  } else if (desc->ndim == 1) {
-    for (int i = 0; i < op->n[0]; ++i)
-      for (int j = 0; j < op->n[1]; ++j) {
-        const double xi = x[0][i], yj = x[1][j];
-        op->Vh[(size_t)i * op->n[1] + j] = pair_pot(op->pot, std::fabs(yj - 0.5 * xi), op->v0, op->width) +
-                                           pair_pot(op->pot, std::fabs(yj + 0.5 * xi), op->v0, op->width);
-      }
-  } else {
-    const int a = op->n[0], b = op->n[1], c = op->n[2], e = op->n[3];
-    for (int i1 = 0; i1 < a; ++i1)
-      for (int i2 = 0; i2 < b; ++i2)
-        for (int j1 = 0; j1 < c; ++j1)
-          for (int j2 = 0; j2 < e; ++j2) {
-            const double x1 = x[0][i1], x2 = x[1][i2], y1 = x[2][j1], y2 = x[3][j2];
-            const double rm = std::hypot(y1 - 0.5 * x1, y2 - 0.5 * x2);
-            const double rp = std::hypot(y1 + 0.5 * x1, y2 + 0.5 * x2);
-            op->Vh[(((size_t)i1 * b + i2) * c + j1) * e + j2] =
-                pair_pot(op->pot, rm, op->v0, op->width) + pair_pot(op->pot, rp, op->v0, op->width);
-          }
-  }
-  // Scaled kinetic factors K_k = -c D2_k.
-  std::vector<double> Kh[4];
-  for (int k = 0; k < nm; ++k) {
-    const double c = (k < nm / 2) ? op->cx : op->cy;
-    Kh[k].resize(op->D2h[k].size());
-    for (size_t e = 0; e < Kh[k].size(); ++e) Kh[k][e] = -c * op->D2h[k][e];
-  }
-  // Preconditioner shift: two-body ground energy on the y grid (Sec. 4.2).
-  if (std::isnan(desc->sigma)) {
-    const int ky = nm / 2, n = op->n[ky];
-    std::vector<double> A((size_t)n * n), wr(n), wi(n);
-    const double ck = 1.0 / (2.0 * op->mu_hl);
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = -ck * op->D2h[ky][(size_t)i * n + j];
-    if (desc->pot == TP3B_POT_TABLE) {
-      op->sigma = 0.0;
-    } else {
-      for (int i = 0; i < n; ++i) A[(size_t)i * n + i] += pair_pot(op->pot, std::fabs(x[ky][i]), op->v0, op->width);
-      if (!real_schur(n, A.data(), nullptr, wr.data(), wi.data())) {
-        delete op;
-        return fail(TP3B_EDEVICE, "two-body eigenvalue iteration did not converge");
-      }
-      double m = wr[0];
-      for (int i = 1; i < n; ++i) m = std::min(m, wr[i]);
-      op->sigma = m;
-    }
-  } else {
-    op->sigma = desc->sigma;
-  }
-  // Fast-diagonalisation factors of the kinetic operator, one per mode: the
-  // shifted Kronecker sum is then inverted exactly by mode products and a
-  // pointwise divide (1D: the Sylvester equation of eq. (14); 2D: the same
-  // construction over four modes).
-  PrecFactors pf;
-  {
-    bool ok = true;
-    for (int k = 0; k < nm && ok; ++k) {
-      const int n = op->n[k];
-      pf.S[k].resize((size_t)n * n);
-      pf.Si[k].resize((size_t)n * n);
-      pf.lam[k].resize(n);
-      ok = eigen_decompose_real(n, Kh[k].data(), pf.S[k].data(), pf.Si[k].data(), pf.lam[k].data());
-    }
-    if (ok) {
-      // smallest |denominator|: sums over the x modes against sums over the y modes
-      std::vector<double> xs, ys;
-      if (op->ndim == 1) {
-        xs = pf.lam[0];
-        ys = pf.lam[1];
-      } else {
-        for (double a : pf.lam[0])
-          for (double b : pf.lam[1]) xs.push_back(a + b);
-        for (double a : pf.lam[2])
-          for (double b : pf.lam[3]) ys.push_back(a + b);
-        pf.lamItem = xs;  // index i1 * n1 + i2
-      }
-      std::vector<double> ysort = ys;
-      std::sort(ysort.begin(), ysort.end());
-      double mn = 1e300;
-      for (double a : xs) {
-        const double want = op->sigma - a;
-        auto it = std::lower_bound(ysort.begin(), ysort.end(), want);
-        if (it != ysort.end()) mn = std::min(mn, std::fabs(a + *it - op->sigma));
-        if (it != ysort.begin()) mn = std::min(mn, std::fabs(a + *(it - 1) - op->sigma));
-      }
-      op->lam_min = mn;
-      op->have_prec = mn > 0;
-    }
-    // lower bound of the spectrum (Weyl, continuous problem): the eigensolver's
-    // starting target
-    double lo = op->Vh.empty() ? 0.0 : *std::min_element(op->Vh.begin(), op->Vh.end());
+  try {
+    (void)stream;
+    if (!desc || !out) return fail(TP3B_EINVAL, "tp3b_create: null descriptor or output");
+    *out = nullptr;
+    if (desc->ndim != 1 && desc->ndim != 2) return fail(TP3B_EINVAL, "ndim must be 1 or 2");
+    const int nm = 2 * desc->ndim;
+    int64_t N = 1;
     for (int k = 0; k < nm; ++k) {
-      if (pf.lam[k].empty() || !ok) {
-        // no real eigen-factors: Gershgorin bound of the mode operator
-        double g = 1e300;
-        const int n = op->n[k];
-        for (int i = 0; i < n; ++i) {
-          double off = 0.0;
-          for (int j = 0; j < n; ++j)
-            if (j != i) off += std::fabs(Kh[k][(size_t)i * n + j]);
-          g = std::min(g, Kh[k][(size_t)i * n + i] - off);
-        }
-        lo += g;
-      } else {
-        lo += *std::min_element(pf.lam[k].begin(), pf.lam[k].end());
-      }
+      if (desc->n[k] < 2 || desc->n[k] > 8192) return fail(TP3B_EINVAL, "mode sizes must be in [2, 8192]");
+      if (!(desc->L[k] > 0)) return fail(TP3B_EINVAL, "half-widths L must be positive");
+      N *= desc->n[k];
     }
-    op->spec_lo = lo;
-    // preconditioner work buffer: up to 64 vectors, at most 4 GiB (FP64)
-    const int64_t cap = (int64_t)(1ll << 32) / (N * 8);
-    op->work_vecs = (int)std::max<int64_t>(1, std::min<int64_t>(64, cap));
+    if (!(desc->c_x > 0) || !(desc->c_y > 0)) return fail(TP3B_EINVAL, "c_x and c_y must be positive");
+    if (desc->pot < TP3B_POT_GAUSS || desc->pot > TP3B_POT_TABLE) return fail(TP3B_EINVAL, "unknown potential");
+    if (desc->pot == TP3B_POT_TABLE && !desc->V_table) return fail(TP3B_EINVAL, "TP3B_POT_TABLE needs V_table");
+    if (desc->pot == TP3B_POT_GAUSS && !(desc->width > 0)) return fail(TP3B_EINVAL, "width must be positive");
+    if (desc->ndim == 2 && (desc->n[0] != desc->n[1] || desc->n[2] != desc->n[3]))
+      return fail(TP3B_ENOTSUP, "2D operators need n[0] == n[1] and n[2] == n[3]");
+    if (desc->grid != TP3B_GRID_CGL && desc->grid != TP3B_GRID_MAPPED)
+      return fail(TP3B_EINVAL, "unknown grid");
+    for (int k = 0; k < nm; ++k) {
+      if (desc->parity[k] < -1 || desc->parity[k] > 1) return fail(TP3B_EINVAL, "parity must be -1, 0 or +1");
+      if (desc->parity[k] != 0 && desc->grid != TP3B_GRID_MAPPED)
+        return fail(TP3B_EINVAL, "parity half grids need TP3B_GRID_MAPPED");
+    }
+  
+    tp3b_op op = new tp3b_op_s();
+    op->ndim = desc->ndim;
+    op->nmodes = nm;
+    op->N = N;
+    op->cx = desc->c_x;
+    op->cy = desc->c_y;
+    op->pot = desc->pot;
+    op->v0 = desc->v0;
+    op->width = desc->width;
+    op->mu_hl = desc->mu_hl > 0 ? desc->mu_hl : 1.0;
+    (void)hipGetDevice(&op->device);
+    std::vector<double> x[4];
+    for (int k = 0; k < nm; ++k) {
+      op->n[k] = desc->n[k];
+      op->L[k] = desc->L[k];
+      mode_grid(desc, k, op->D2h[k], x[k]);
+    }
+    // Potential V = u(|y - x/2|) + u(|y + x/2|) on the tensor grid (eq. (3)).
+    op->Vh.resize(N);
+    if (desc->pot == TP3B_POT_TABLE) {
+      std::memcpy(op->Vh.data(), desc->V_table, sizeof(double) * N);
+    } else if (desc->ndim == 1) {
+      for (int i = 0; i < op->n[0]; ++i)
+        for (int j = 0; j < op->n[1]; ++j) {
+          const double xi = x[0][i], yj = x[1][j];
+          op->Vh[(size_t)i * op->n[1] + j] = pair_pot(op->pot, std::fabs(yj - 0.5 * xi), op->v0, op->width) +
+                                             pair_pot(op->pot, std::fabs(yj + 0.5 * xi), op->v0, op->width);
+        }
+    } else {
+      const int a = op->n[0], b = op->n[1], c = op->n[2], e = op->n[3];
+      for (int i1 = 0; i1 < a; ++i1)
+        for (int i2 = 0; i2 < b; ++i2)
+          for (int j1 = 0; j1 < c; ++j1)
+            for (int j2 = 0; j2 < e; ++j2) {
+              const double x1 = x[0][i1], x2 = x[1][i2], y1 = x[2][j1], y2 = x[3][j2];
+              const double rm = std::hypot(y1 - 0.5 * x1, y2 - 0.5 * x2);
+              const double rp = std::hypot(y1 + 0.5 * x1, y2 + 0.5 * x2);
+              op->Vh[(((size_t)i1 * b + i2) * c + j1) * e + j2] =
+                  pair_pot(op->pot, rm, op->v0, op->width) + pair_pot(op->pot, rp, op->v0, op->width);
+            }
+    }
+    // Scaled kinetic factors K_k = -c D2_k.
+    std::vector<double> Kh[4];
+    for (int k = 0; k < nm; ++k) {
+      const double c = (k < nm / 2) ? op->cx : op->cy;
+      Kh[k].resize(op->D2h[k].size());
+      for (size_t e = 0; e < Kh[k].size(); ++e) Kh[k][e] = -c * op->D2h[k][e];
+    }
+    // Preconditioner shift: two-body ground energy on the y grid (Sec. 4.2).
+    if (std::isnan(desc->sigma)) {
+      const int ky = nm / 2, n = op->n[ky];
+      std::vector<double> A((size_t)n * n), wr(n), wi(n);
+      const double ck = 1.0 / (2.0 * op->mu_hl);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = -ck * op->D2h[ky][(size_t)i * n + j];
+      if (desc->pot == TP3B_POT_TABLE) {
+        op->sigma = 0.0;
+      } else {
+        for (int i = 0; i < n; ++i) A[(size_t)i * n + i] += pair_pot(op->pot, std::fabs(x[ky][i]), op->v0, op->width);
+        if (!real_schur(n, A.data(), nullptr, wr.data(), wi.data())) {
+          delete op;
+          return fail(TP3B_EDEVICE, "two-body eigenvalue iteration did not converge");
+        }
+        double m = wr[0];
+        for (int i = 1; i < n; ++i) m = std::min(m, wr[i]);
+        op->sigma = m;
+      }
+    } else {
+      op->sigma = desc->sigma;
+    }
+    // Fast-diagonalisation factors of the kinetic operator, one per mode: the
+    // shifted Kronecker sum is then inverted exactly by mode products and a
+    // pointwise divide (1D: the Sylvester equation of eq. (14); 2D: the same
+    // construction over four modes).
+    PrecFactors pf;
+    {
+      bool ok = true;
+      for (int k = 0; k < nm && ok; ++k) {
+        const int n = op->n[k];
+        pf.S[k].resize((size_t)n * n);
+        pf.Si[k].resize((size_t)n * n);
+        pf.lam[k].resize(n);
+        ok = eigen_decompose_real(n, Kh[k].data(), pf.S[k].data(), pf.Si[k].data(), pf.lam[k].data());
+      }
+      if (ok) {
+        // smallest |denominator|: sums over the x modes against sums over the y modes
+        std::vector<double> xs, ys;
+        if (op->ndim == 1) {
+          xs = pf.lam[0];
+          ys = pf.lam[1];
+        } else {
+          for (double a : pf.lam[0])
+            for (double b : pf.lam[1]) xs.push_back(a + b);
+          for (double a : pf.lam[2])
+            for (double b : pf.lam[3]) ys.push_back(a + b);
+          pf.lamItem = xs;  // index i1 * n1 + i2
+        }
+        std::vector<double> ysort = ys;
+        std::sort(ysort.begin(), ysort.end());
+        double mn = 1e300;
+        for (double a : xs) {
+          const double want = op->sigma - a;
+          auto it = std::lower_bound(ysort.begin(), ysort.end(), want);
+          if (it != ysort.end()) mn = std::min(mn, std::fabs(a + *it - op->sigma));
+          if (it != ysort.begin()) mn = std::min(mn, std::fabs(a + *(it - 1) - op->sigma));
+        }
+        op->lam_min = mn;
+        op->have_prec = mn > 0;
+      }
+      // lower bound of the spectrum (Weyl, continuous problem): the eigensolver's
+      // starting target
+      double lo = op->Vh.empty() ? 0.0 : *std::min_element(op->Vh.begin(), op->Vh.end());
+      for (int k = 0; k < nm; ++k) {
+        if (pf.lam[k].empty() || !ok) {
+          // no real eigen-factors: Gershgorin bound of the mode operator
+          double g = 1e300;
+          const int n = op->n[k];
+          for (int i = 0; i < n; ++i) {
+            double off = 0.0;
+            for (int j = 0; j < n; ++j)
+              if (j != i) off += std::fabs(Kh[k][(size_t)i * n + j]);
+            g = std::min(g, Kh[k][(size_t)i * n + i] - off);
+          }
+          lo += g;
+        } else {
+          lo += *std::min_element(pf.lam[k].begin(), pf.lam[k].end());
+        }
+      }
+      op->spec_lo = lo;
+      // preconditioner work buffer: up to 64 vectors, at most 4 GiB (FP64)
+      const int64_t cap = (int64_t)(1ll << 32) / (N * 8);
+      op->work_vecs = (int)std::max<int64_t>(1, std::min<int64_t>(64, cap));
+    }
+    tp3b_status st = upload_ops<double>(op, op->d64, Kh, pf);
+    if (st == TP3B_OK) st = upload_ops<float>(op, op->d32, Kh, pf);
+    if (st != TP3B_OK) {
+      std::string msg = g_err;
+      tp3b_destroy(op);
+      return fail(st, msg);
+    }
+    *out = op;
+    return TP3B_OK;
+  } catch (...) {
+    return exception_status();
   }
-  tp3b_status st = upload_ops<double>(op, op->d64, Kh, pf);
-  if (st == TP3B_OK) st = upload_ops<float>(op, op->d32, Kh, pf);
-  if (st != TP3B_OK) {
-    std::string msg = g_err;
-    tp3b_destroy(op);
-    return fail(st, msg);
-  }
-  *out = op;
-  return TP3B_OK;
 }
 
 tp3b_status tp3b_destroy(tp3b_op op) {
-  if (!op) return TP3B_OK;
-  free_ops(op->d64);
-  free_ops(op->d32);
-  delete op;
-  return TP3B_OK;
+  try {
+    if (!op) return TP3B_OK;
+    free_ops(op->d64);
+    free_ops(op->d32);
+    delete op;
+    return TP3B_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 tp3b_status tp3b_op_info(tp3b_op op, int64_t* N, double* sigma, double* lam_min) {
-  if (!op) return fail(TP3B_EINVAL, "null operator");
-  if (N) *N = op->N;
-  if (sigma) *sigma = op->sigma;
-  if (lam_min) *lam_min = op->lam_min;
-  return TP3B_OK;
+  try {
+    if (!op) return fail(TP3B_EINVAL, "null operator");
+    if (N) *N = op->N;
+    if (sigma) *sigma = op->sigma;
+    if (lam_min) *lam_min = op->lam_min;
+    return TP3B_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 tp3b_status tp3b_get_D2(tp3b_op op, int32_t mode, double* out) {
-  if (!op || !out) return fail(TP3B_EINVAL, "null argument");
-  if (mode < 0 || mode >= op->nmodes) return fail(TP3B_EINVAL, "mode out of range");
-  std::memcpy(out, op->D2h[mode].data(), sizeof(double) * op->D2h[mode].size());
-  return TP3B_OK;
+  try {
+    if (!op || !out) return fail(TP3B_EINVAL, "null argument");
+    if (mode < 0 || mode >= op->nmodes) return fail(TP3B_EINVAL, "mode out of range");
+    std::memcpy(out, op->D2h[mode].data(), sizeof(double) * op->D2h[mode].size());
+    return TP3B_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 tp3b_status tp3b_get_V(tp3b_op op, double* out) {
-  if (!op || !out) return fail(TP3B_EINVAL, "null argument");
-  std::memcpy(out, op->Vh.data(), sizeof(double) * op->N);
-  return TP3B_OK;
+  try {
+    if (!op || !out) return fail(TP3B_EINVAL, "null argument");
+    std::memcpy(out, op->Vh.data(), sizeof(double) * op->N);
+    return TP3B_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 static tp3b_status check_apply(tp3b_op op, int32_t prec, int32_t nvec, const void* X, int64_t ldx,
@@ -913,71 +946,99 @@ static tp3b_status check_apply(tp3b_op op, int32_t prec, int32_t nvec, const voi
 tp3b_status tp3b_apply_H_shifted(tp3b_op op, int32_t prec, int32_t nvec, const void* X,
                                  int64_t ldx, void* Y, int64_t ldy, const double* shifts,
                                  void* stream) {
-  tp3b_status st = check_apply(op, prec, nvec, X, ldx, Y, ldy);
-  if (st != TP3B_OK || nvec == 0) return st;
-  TP3B_HIP(hipSetDevice(op->device));
-  hipStream_t s = (hipStream_t)stream;
-  if (prec == TP3B_FP64)
-    return apply_H_impl<double>(op, nvec, (const double*)X, ldx, (double*)Y, ldy, shifts, s);
-  return apply_H_impl<float>(op, nvec, (const float*)X, ldx, (float*)Y, ldy, shifts, s,
-                             prec == TP3B_BF16X3);
+  try {
+    tp3b_status st = check_apply(op, prec, nvec, X, ldx, Y, ldy);
+    if (st != TP3B_OK || nvec == 0) return st;
+    TP3B_HIP(hipSetDevice(op->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == TP3B_FP64)
+      return apply_H_impl<double>(op, nvec, (const double*)X, ldx, (double*)Y, ldy, shifts, s);
+    return apply_H_impl<float>(op, nvec, (const float*)X, ldx, (float*)Y, ldy, shifts, s,
+                               prec == TP3B_BF16X3);
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 tp3b_status tp3b_apply_H(tp3b_op op, int32_t prec, int32_t nvec, const void* X, int64_t ldx,
                          void* Y, int64_t ldy, void* stream) {
-  return tp3b_apply_H_shifted(op, prec, nvec, X, ldx, Y, ldy, nullptr, stream);
+  try {
+    return tp3b_apply_H_shifted(op, prec, nvec, X, ldx, Y, ldy, nullptr, stream);
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 tp3b_status tp3b_apply_prec(tp3b_op op, int32_t prec, int32_t nvec, const void* X, int64_t ldx,
                             void* Y, int64_t ldy, void* stream) {
-  tp3b_status st = check_apply(op, prec, nvec, X, ldx, Y, ldy);
-  if (st != TP3B_OK || nvec == 0) return st;
-  if (!op->have_prec) return fail(TP3B_ENOTSUP, "kinetic factors have complex spectrum or K - sigma is singular");
-  TP3B_HIP(hipSetDevice(op->device));
-  hipStream_t s = (hipStream_t)stream;
-  if (prec == TP3B_FP64)
-    return apply_prec_impl<double>(op, nvec, (const double*)X, ldx, (double*)Y, ldy, s);
-  return apply_prec_impl<float>(op, nvec, (const float*)X, ldx, (float*)Y, ldy, s,
-                                prec == TP3B_BF16X3);
+  try {
+    tp3b_status st = check_apply(op, prec, nvec, X, ldx, Y, ldy);
+    if (st != TP3B_OK || nvec == 0) return st;
+    if (!op->have_prec) return fail(TP3B_ENOTSUP, "kinetic factors have complex spectrum or K - sigma is singular");
+    TP3B_HIP(hipSetDevice(op->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == TP3B_FP64)
+      return apply_prec_impl<double>(op, nvec, (const double*)X, ldx, (double*)Y, ldy, s);
+    return apply_prec_impl<float>(op, nvec, (const float*)X, ldx, (float*)Y, ldy, s,
+                                  prec == TP3B_BF16X3);
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 tp3b_status tp3b_block_orth(int64_t N, int32_t nq, const double* Q, int64_t ldq, int32_t nx,
                             double* X, int64_t ldx, double* C_qx, double* R_xx, int32_t* rank,
                             uint64_t seed, void* stream) {
-  if (N < 0 || nq < 0 || nx < 0) return fail(TP3B_EINVAL, "negative size");
-  if (nx > 32) return fail(TP3B_EINVAL, "nx must be <= 32");
-  if (nx == 0) {
-    if (rank) *rank = 0;
-    return TP3B_OK;
+  try {
+    if (N < 0 || nq < 0 || nx < 0) return fail(TP3B_EINVAL, "negative size");
+    if (nx > 32) return fail(TP3B_EINVAL, "nx must be <= 32");
+    if (nx == 0) {
+      if (rank) *rank = 0;
+      return TP3B_OK;
+    }
+    if (!X || (nq > 0 && !Q)) return fail(TP3B_EINVAL, "null X or Q");
+    if (ldx < N || (nq > 0 && ldq < N)) return fail(TP3B_EINVAL, "leading dimension smaller than N");
+    if (N < nq + nx) return fail(TP3B_EINVAL, "N must be >= nq + nx");
+    return block_orth_impl(N, nq, Q, ldq, nx, X, ldx, C_qx, R_xx, rank, seed, (hipStream_t)stream);
+  } catch (...) {
+    return exception_status();
   }
-  if (!X || (nq > 0 && !Q)) return fail(TP3B_EINVAL, "null X or Q");
-  if (ldx < N || (nq > 0 && ldq < N)) return fail(TP3B_EINVAL, "leading dimension smaller than N");
-  if (N < nq + nx) return fail(TP3B_EINVAL, "N must be >= nq + nx");
-  return block_orth_impl(N, nq, Q, ldq, nx, X, ldx, C_qx, R_xx, rank, seed, (hipStream_t)stream);
 }
 
 tp3b_status tp3b_set_tile(tp3b_op op, int32_t tile) {
-  if (!op) return fail(TP3B_EINVAL, "null operator");
-  if (tile < -1 || tile >= NUM_TILE_CFGS) return fail(TP3B_EINVAL, "unknown tile shape");
-  op->tile_override = tile;
-  return TP3B_OK;
+  try {
+    if (!op) return fail(TP3B_EINVAL, "null operator");
+    if (tile < -1 || tile >= NUM_TILE_CFGS) return fail(TP3B_EINVAL, "unknown tile shape");
+    op->tile_override = tile;
+    return TP3B_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 tp3b_status tp3b_autotune(tp3b_op op, int32_t prec, int32_t nvec, int32_t reps, double* best_ms) {
-  if (!op) return fail(TP3B_EINVAL, "null operator");
-  if (nvec < 1 || reps < 1) return fail(TP3B_EINVAL, "nvec and reps must be >= 1");
-  if (prec != TP3B_FP64 && prec != TP3B_FP32 && prec != TP3B_BF16X3)
-    return fail(TP3B_EINVAL, "unknown precision");
-  TP3B_HIP(hipSetDevice(op->device));
-  if (best_ms) best_ms[0] = best_ms[1] = NAN;
-  return prec == TP3B_FP64 ? autotune_impl<double>(op, nvec, reps, best_ms, false)
-                           : autotune_impl<float>(op, nvec, reps, best_ms, prec == TP3B_BF16X3);
+  try {
+    if (!op) return fail(TP3B_EINVAL, "null operator");
+    if (nvec < 1 || reps < 1) return fail(TP3B_EINVAL, "nvec and reps must be >= 1");
+    if (prec != TP3B_FP64 && prec != TP3B_FP32 && prec != TP3B_BF16X3)
+      return fail(TP3B_EINVAL, "unknown precision");
+    TP3B_HIP(hipSetDevice(op->device));
+    if (best_ms) best_ms[0] = best_ms[1] = NAN;
+    return prec == TP3B_FP64 ? autotune_impl<double>(op, nvec, reps, best_ms, false)
+                             : autotune_impl<float>(op, nvec, reps, best_ms, prec == TP3B_BF16X3);
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 tp3b_status tp3b_host_schur(int32_t n, double* A, double* Z, double* wr, double* wi) {
-  if (n < 1 || !A || !wr || !wi) return fail(TP3B_EINVAL, "bad arguments");
-  if (!real_schur(n, A, Z, wr, wi)) return fail(TP3B_ENOCONV, "QR iteration did not converge");
-  return TP3B_OK;
+  try {
+    if (n < 1 || !A || !wr || !wi) return fail(TP3B_EINVAL, "bad arguments");
+    if (!real_schur(n, A, Z, wr, wi)) return fail(TP3B_ENOCONV, "QR iteration did not converge");
+    return TP3B_OK;
+  } catch (...) {
+    return exception_status();
+  }
 }
 
 }  // extern "C"

@@ -167,106 +167,114 @@ using namespace tp3b;
 extern "C" {
 
 tp3b_status tp3b_two_body_depth(const tp3b_problem_desc* desc, double E0, double* v0) {
-  if (!desc || !v0) return fail(TP3B_EINVAL, "tp3b_two_body_depth: null descriptor or output");
-  if (desc->ndim != 1 && desc->ndim != 2) return fail(TP3B_EINVAL, "ndim must be 1 or 2");
-  if (!(E0 > 0) || !std::isfinite(E0)) return fail(TP3B_EINVAL, "E0 must be positive and finite");
-  if (desc->pot != TP3B_POT_GAUSS && desc->pot != TP3B_POT_GAUSS_PAPER && desc->pot != TP3B_POT_LORENTZ3)
-    return fail(TP3B_ENOTSUP, "a depth is defined for the Gaussian and Lorentzian-cube shapes only");
-  if (desc->pot == TP3B_POT_GAUSS && !(desc->width > 0)) return fail(TP3B_EINVAL, "width must be positive");
-  if (desc->grid != TP3B_GRID_CGL && desc->grid != TP3B_GRID_MAPPED) return fail(TP3B_EINVAL, "unknown grid");
-  const int nm = 2 * desc->ndim;
-  const int k0 = nm / 2;  // light-particle modes k0 .. nm-1
-  for (int k = k0; k < nm; ++k) {
-    if (desc->n[k] < 2 || desc->n[k] > 1024)
-      return fail(TP3B_EINVAL, "light-particle mode sizes must be in [2, 1024]");
-    if (!(desc->L[k] > 0)) return fail(TP3B_EINVAL, "half-widths L must be positive");
-    if (desc->parity[k] < -1 || desc->parity[k] > 1) return fail(TP3B_EINVAL, "parity must be -1, 0 or +1");
-    if (desc->parity[k] != 0 && desc->grid != TP3B_GRID_MAPPED)
-      return fail(TP3B_EINVAL, "parity half grids need TP3B_GRID_MAPPED");
+  try {
+    if (!desc || !v0) return fail(TP3B_EINVAL, "tp3b_two_body_depth: null descriptor or output");
+    if (desc->ndim != 1 && desc->ndim != 2) return fail(TP3B_EINVAL, "ndim must be 1 or 2");
+    if (!(E0 > 0) || !std::isfinite(E0)) return fail(TP3B_EINVAL, "E0 must be positive and finite");
+    if (desc->pot != TP3B_POT_GAUSS && desc->pot != TP3B_POT_GAUSS_PAPER && desc->pot != TP3B_POT_LORENTZ3)
+      return fail(TP3B_ENOTSUP, "a depth is defined for the Gaussian and Lorentzian-cube shapes only");
+    if (desc->pot == TP3B_POT_GAUSS && !(desc->width > 0)) return fail(TP3B_EINVAL, "width must be positive");
+    if (desc->grid != TP3B_GRID_CGL && desc->grid != TP3B_GRID_MAPPED) return fail(TP3B_EINVAL, "unknown grid");
+    const int nm = 2 * desc->ndim;
+    const int k0 = nm / 2;  // light-particle modes k0 .. nm-1
+    for (int k = k0; k < nm; ++k) {
+      if (desc->n[k] < 2 || desc->n[k] > 1024)
+        return fail(TP3B_EINVAL, "light-particle mode sizes must be in [2, 1024]");
+      if (!(desc->L[k] > 0)) return fail(TP3B_EINVAL, "half-widths L must be positive");
+      if (desc->parity[k] < -1 || desc->parity[k] > 1) return fail(TP3B_EINVAL, "parity must be -1, 0 or +1");
+      if (desc->parity[k] != 0 && desc->grid != TP3B_GRID_MAPPED)
+        return fail(TP3B_EINVAL, "parity half grids need TP3B_GRID_MAPPED");
+    }
+    const double mu = desc->mu_hl > 0 ? desc->mu_hl : 1.0;
+    TwoBody tb;
+    tb.dims = desc->ndim;
+    tb.E0 = E0;
+    std::vector<double> x[2];
+    for (int d = 0; d < tb.dims; ++d) {
+      const int k = k0 + d, n = desc->n[k];
+      tb.n[d] = n;
+      std::vector<double> D2;
+      mode_grid(desc, k, D2, x[d]);
+      std::vector<double> A((size_t)n * n);
+      for (size_t e = 0; e < A.size(); ++e) A[e] = -(0.5 / mu) * D2[e];
+      tb.S[d].resize((size_t)n * n);
+      tb.Si[d].resize((size_t)n * n);
+      tb.lam[d].resize(n);
+      if (!eigen_decompose_real(n, A.data(), tb.S[d].data(), tb.Si[d].data(), tb.lam[d].data()))
+        return fail(TP3B_ENOTSUP, "the light-particle kinetic operator has a complex spectrum");
+    }
+    tb.F.resize(tb.size());
+    if (tb.dims == 1) {
+      for (int i = 0; i < tb.n[0]; ++i)
+        tb.F[i] = -pair_potential(desc->pot, std::fabs(x[0][i]), 1.0, desc->width);
+    } else {
+      for (int i = 0; i < tb.n[0]; ++i)
+        for (int j = 0; j < tb.n[1]; ++j)
+          tb.F[(size_t)i * tb.n[1] + j] =
+              -pair_potential(desc->pot, std::hypot(x[0][i], x[1][j]), 1.0, desc->width);
+    }
+    double mu_max = 0.0;
+    if (!largest_eigenvalue(tb, &mu_max)) return fail(TP3B_ENOCONV, "two-body depth iteration did not converge");
+    if (!(mu_max > 0)) return fail(TP3B_ENOCONV, "no bound state for this binding energy on this grid");
+    *v0 = 1.0 / mu_max;
+    return TP3B_OK;
+  } catch (...) {
+    return exception_status();
   }
-  const double mu = desc->mu_hl > 0 ? desc->mu_hl : 1.0;
-  TwoBody tb;
-  tb.dims = desc->ndim;
-  tb.E0 = E0;
-  std::vector<double> x[2];
-  for (int d = 0; d < tb.dims; ++d) {
-    const int k = k0 + d, n = desc->n[k];
-    tb.n[d] = n;
-    std::vector<double> D2;
-    mode_grid(desc, k, D2, x[d]);
-    std::vector<double> A((size_t)n * n);
-    for (size_t e = 0; e < A.size(); ++e) A[e] = -(0.5 / mu) * D2[e];
-    tb.S[d].resize((size_t)n * n);
-    tb.Si[d].resize((size_t)n * n);
-    tb.lam[d].resize(n);
-    if (!eigen_decompose_real(n, A.data(), tb.S[d].data(), tb.Si[d].data(), tb.lam[d].data()))
-      return fail(TP3B_ENOTSUP, "the light-particle kinetic operator has a complex spectrum");
-  }
-  tb.F.resize(tb.size());
-  if (tb.dims == 1) {
-    for (int i = 0; i < tb.n[0]; ++i)
-      tb.F[i] = -pair_potential(desc->pot, std::fabs(x[0][i]), 1.0, desc->width);
-  } else {
-    for (int i = 0; i < tb.n[0]; ++i)
-      for (int j = 0; j < tb.n[1]; ++j)
-        tb.F[(size_t)i * tb.n[1] + j] =
-            -pair_potential(desc->pot, std::hypot(x[0][i], x[1][j]), 1.0, desc->width);
-  }
-  double mu_max = 0.0;
-  if (!largest_eigenvalue(tb, &mu_max)) return fail(TP3B_ENOCONV, "two-body depth iteration did not converge");
-  if (!(mu_max > 0)) return fail(TP3B_ENOCONV, "no bound state for this binding energy on this grid");
-  *v0 = 1.0 / mu_max;
-  return TP3B_OK;
 }
 
 tp3b_status tp3b_homotopy_solve(const tp3b_problem_desc* desc, const tp3b_problem_desc* two_body,
                                 const tp3b_jdqr_opts* opts, int32_t count, const double* E0,
                                 double* v0, double* evals, double* resnorm, int32_t* n_outer) {
-  if (!desc || !opts || !E0) return fail(TP3B_EINVAL, "tp3b_homotopy_solve: null descriptor, options or E0");
-  if (count < 1) return fail(TP3B_EINVAL, "count must be >= 1");
-  if (desc->pot == TP3B_POT_TABLE) return fail(TP3B_ENOTSUP, "the depth of a tabulated potential is not defined");
-  const int nev = opts->nev;
-  if (nev < 1) return fail(TP3B_EINVAL, "nev must be >= 1");
-  struct Buf {
-    double* p = nullptr;
-    ~Buf() {
-      if (p) (void)hipFree(p);
-    }
-  } Q;
-  int64_t N = 0;
-  for (int i = 0; i < count; ++i) {
-    double vi = 0.0;
-    tp3b_status st = tp3b_two_body_depth(two_body ? two_body : desc, E0[i], &vi);
-    if (st != TP3B_OK) return st;
-    tp3b_problem_desc d = *desc;
-    d.v0 = vi;
-    if (std::isnan(desc->sigma)) d.sigma = -E0[i];  // the two-body threshold
-    tp3b_op op = nullptr;
-    st = tp3b_create(&d, nullptr, &op);
-    if (st != TP3B_OK) return st;
-    if (!Q.p) {
-      double sig = 0, lm = 0;
-      (void)tp3b_op_info(op, &N, &sig, &lm);
-      hipError_t e = hipMalloc((void**)&Q.p, sizeof(double) * (size_t)N * nev);
-      if (e != hipSuccess) {
-        (void)tp3b_destroy(op);
-        return hip_fail(e, "tp3b_homotopy_solve: Schur vector buffer");
+  try {
+    if (!desc || !opts || !E0) return fail(TP3B_EINVAL, "tp3b_homotopy_solve: null descriptor, options or E0");
+    if (count < 1) return fail(TP3B_EINVAL, "count must be >= 1");
+    if (desc->pot == TP3B_POT_TABLE) return fail(TP3B_ENOTSUP, "the depth of a tabulated potential is not defined");
+    const int nev = opts->nev;
+    if (nev < 1) return fail(TP3B_EINVAL, "nev must be >= 1");
+    struct Buf {
+      double* p = nullptr;
+      ~Buf() {
+        if (p) (void)hipFree(p);
       }
+    } Q;
+    int64_t N = 0;
+    for (int i = 0; i < count; ++i) {
+      double vi = 0.0;
+      tp3b_status st = tp3b_two_body_depth(two_body ? two_body : desc, E0[i], &vi);
+      if (st != TP3B_OK) return st;
+      tp3b_problem_desc d = *desc;
+      d.v0 = vi;
+      if (std::isnan(desc->sigma)) d.sigma = -E0[i];  // the two-body threshold
+      tp3b_op op = nullptr;
+      st = tp3b_create(&d, nullptr, &op);
+      if (st != TP3B_OK) return st;
+      if (!Q.p) {
+        double sig = 0, lm = 0;
+        (void)tp3b_op_info(op, &N, &sig, &lm);
+        hipError_t e = hipMalloc((void**)&Q.p, sizeof(double) * (size_t)N * nev);
+        if (e != hipSuccess) {
+          (void)tp3b_destroy(op);
+          return hip_fail(e, "tp3b_homotopy_solve: Schur vector buffer");
+        }
+      }
+      std::vector<double> ev(nev), rn(nev);
+      tp3b_jdqr_stats js{};
+      // the previous Schur vectors start the next solve; the solver copies its
+      // start block before it writes its own Schur vectors to the same buffer
+      st = tp3b_jdqr_solve(op, opts, i > 0 ? Q.p : nullptr, i > 0 ? nev : 0, ev.data(), Q.p, nullptr,
+                           rn.data(), &js);
+      (void)tp3b_destroy(op);
+      if (v0) v0[i] = vi;
+      if (evals) std::memcpy(evals + (size_t)i * nev, ev.data(), sizeof(double) * nev);
+      if (resnorm) std::memcpy(resnorm + (size_t)i * nev, rn.data(), sizeof(double) * nev);
+      if (n_outer) n_outer[i] = js.n_outer;
+      if (st != TP3B_OK) return st;
     }
-    std::vector<double> ev(nev), rn(nev);
-    tp3b_jdqr_stats js{};
-    // the previous Schur vectors start the next solve; the solver copies its
-    // start block before it writes its own Schur vectors to the same buffer
-    st = tp3b_jdqr_solve(op, opts, i > 0 ? Q.p : nullptr, i > 0 ? nev : 0, ev.data(), Q.p, nullptr,
-                         rn.data(), &js);
-    (void)tp3b_destroy(op);
-    if (v0) v0[i] = vi;
-    if (evals) std::memcpy(evals + (size_t)i * nev, ev.data(), sizeof(double) * nev);
-    if (resnorm) std::memcpy(resnorm + (size_t)i * nev, rn.data(), sizeof(double) * nev);
-    if (n_outer) n_outer[i] = js.n_outer;
-    if (st != TP3B_OK) return st;
+    return TP3B_OK;
+  } catch (...) {
+    return exception_status();
   }
-  return TP3B_OK;
 }
 
 }  // extern "C"
