@@ -813,18 +813,24 @@ __device__ __forceinline__ void bupdate_row(int64_t N, int nb, double alpha,
   *w = (T)((double)(*w) + alpha * s);
 }
 
-// Vout[r, j] = W[r, j] / sqrt(nrm2[j]); row 0 also stores the norm in hout.
+// Vout[r, j] = W[r, j] / sqrt(n2) (n2 = the squared norm of column j); row 0
+// also stores the norm in hout.
 template <typename T>
-__device__ __forceinline__ void normalize_row(int64_t N, const double* __restrict__ nrm2,
-                                              const T* __restrict__ W, T* __restrict__ Vout,
-                                              double* __restrict__ hout, int hld, int64_t r,
-                                              int j) {
-  const double n2 = nrm2[j];
+__device__ __forceinline__ void normalize_row_n2(int64_t N, double n2, const T* __restrict__ W,
+                                                 T* __restrict__ Vout, double* __restrict__ hout,
+                                                 int hld, int64_t r, int j) {
   const double h = n2 > 0.0 ? sqrt(n2) : 0.0;
   if (r == 0 && hout) hout[(int64_t)j * hld] = h;
   if (r >= N) return;
   const double inv = h > 0.0 ? 1.0 / h : 0.0;
   Vout[(int64_t)j * N + r] = (T)((double)W[(int64_t)j * N + r] * inv);
+}
+template <typename T>
+__device__ __forceinline__ void normalize_row(int64_t N, const double* __restrict__ nrm2,
+                                              const T* __restrict__ W, T* __restrict__ Vout,
+                                              double* __restrict__ hout, int hld, int64_t r,
+                                              int j) {
+  normalize_row_n2<T>(N, nrm2[j], W, Vout, hout, hld, r, j);
 }
 
 // -------------------------------------------------------- Cholesky-QR pieces

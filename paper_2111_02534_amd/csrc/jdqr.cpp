@@ -541,8 +541,8 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
         TP3B_HIP((launch_convert<double, TW>(N, nb, -1.0, Rres, N, rhs, N, s)));
       }
       { tp3b_status ps = project(rhs); if (ps != TP3B_OK) return ps; }
-      TP3B_HIP(launch_bdot_diag<TW>(N, nb, 1, rhs, 0, rhs, dNrm, 1, part, s));
-      TP3B_HIP(launch_normalize_cols<TW>(N, nb, dNrm, rhs, Vg, dBeta, 1, s));
+      TP3B_HIP(launch_bdot_partials<TW>(N, nb, 1, rhs, 0, rhs, part, s));
+      TP3B_HIP(launch_normalize_cols_red<TW>(N, nb, part, rhs, Vg, dBeta, 1, s));
       for (int kk = 0; kk < steps; ++kk) {
         TW* vk = Vg + (int64_t)kk * bs;
         TW* w = W;
@@ -558,13 +558,15 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
         { tp3b_status ps = project(w); if (ps != TP3B_OK) return ps; }
         double* h1 = dH1 + (size_t)kk * b * hld;
         double* h2 = dH2 + (size_t)kk * b * hld;
-        TP3B_HIP(launch_bdot_diag<TW>(N, nb, kk + 1, Vg, bs, w, h1, hld, part, s));
-        TP3B_HIP(launch_bupdate_diag<TW>(N, nb, kk + 1, -1.0, Vg, bs, h1, hld, w, s));
-        TP3B_HIP(launch_bdot_diag<TW>(N, nb, kk + 1, Vg, bs, w, h2, hld, part, s));
-        TP3B_HIP(launch_bupdate_diag<TW>(N, nb, kk + 1, -1.0, Vg, bs, h2, hld, w, s));
-        TP3B_HIP(launch_bdot_diag<TW>(N, nb, 1, w, 0, w, dNrm, 1, part, s));
-        TP3B_HIP(launch_normalize_cols<TW>(N, nb, dNrm, w, Vg + (int64_t)(kk + 1) * bs,
-                                           dHs + (size_t)kk * b, 1, s));
+        // CGS2 against the basis, then the norm; each update sums its dot's
+        // partials itself (no separate reduction launch)
+        TP3B_HIP(launch_bdot_partials<TW>(N, nb, kk + 1, Vg, bs, w, part, s));
+        TP3B_HIP(launch_bupdate_diag_red<TW>(N, nb, kk + 1, -1.0, Vg, bs, part, h1, hld, w, s));
+        TP3B_HIP(launch_bdot_partials<TW>(N, nb, kk + 1, Vg, bs, w, part, s));
+        TP3B_HIP(launch_bupdate_diag_red<TW>(N, nb, kk + 1, -1.0, Vg, bs, part, h2, hld, w, s));
+        TP3B_HIP(launch_bdot_partials<TW>(N, nb, 1, w, 0, w, part, s));
+        TP3B_HIP(launch_normalize_cols_red<TW>(N, nb, part, w, Vg + (int64_t)(kk + 1) * bs,
+                                               dHs + (size_t)kk * b, 1, s));
       }
       // least squares on the device, then t_j = V_j y_j (FP64 copy in Tc)
       TP3B_HIP(launch_gmres_lstsq(nb, b, steps, hld, dH1, dH2, dHs, dBeta, dY, s));

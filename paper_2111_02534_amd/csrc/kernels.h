@@ -112,6 +112,23 @@ template <typename T>
 hipError_t launch_normalize_cols(int64_t N, int b, const double* nrm2, const T* W, T* Vout,
                                  double* hout, int hld, hipStream_t s);
 
+// The Arnoldi steps with the dots' second stage folded into their consumer:
+// launch_bdot_partials runs only the first stage of launch_bdot_diag into
+// `partial`; launch_bupdate_diag_red then sums those partials per column (the
+// same order as launch_bdot_diag), stores them to H[j*hld + i] and applies
+// W[r, j] += alpha * sum_i Vb[i][r, j] H[j*hld + i]; launch_normalize_cols_red
+// sums the partials of a norm (nb = 1) and normalizes as launch_normalize_cols.
+// Results equal those of the unfused sequence bit for bit.
+template <typename T>
+hipError_t launch_bdot_partials(int64_t N, int b, int nb, const T* V, int64_t bs, const T* W,
+                                double* partial, hipStream_t s);
+template <typename T>
+hipError_t launch_bupdate_diag_red(int64_t N, int b, int nb, double alpha, const T* V, int64_t bs,
+                                   const double* partial, double* H, int hld, T* W, hipStream_t s);
+template <typename T>
+hipError_t launch_normalize_cols_red(int64_t N, int b, const double* partial, const T* W, T* Vout,
+                                     double* hout, int hld, hipStream_t s);
+
 // Y[:, j] = alpha * X[:, j] (type conversion included); X == nullptr: Y = 0.
 template <typename TI, typename TO>
 hipError_t launch_convert(int64_t N, int ncol, double alpha, const TI* X, int64_t ldx, TO* Y,

@@ -321,6 +321,97 @@ template hipError_t launch_normalize_cols<double>(int64_t, int, const double*, c
 template hipError_t launch_normalize_cols<float>(int64_t, int, const double*, const float*, float*,
                                                  double*, int, hipStream_t);
 
+// ------------------------------------- Arnoldi steps with the reduction fused
+// The per-column dots' first stage alone: partials for launch_bupdate_diag_red
+// and launch_normalize_cols_red, which sum them themselves (each workgroup in
+// the same order as k_bdot_reduce, so the results are those of
+// launch_bdot_diag followed by the plain update) and save one launch each.
+template <typename T>
+hipError_t launch_bdot_partials(int64_t N, int b, int nb, const T* V, int64_t bs, const T* W,
+                                double* partial, hipStream_t s) {
+  if (nb <= 0 || b <= 0) return hipSuccess;
+  if (nb > BD_MAXNB) return hipErrorInvalidValue;
+  const int rows = bdot_rows(N);
+  const int nchunk = (int)((N + rows - 1) / rows);
+  hipLaunchKernelGGL((k_bdot_diag<T>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W, rows,
+                     partial);
+  return hipGetLastError();
+}
+template hipError_t launch_bdot_partials<double>(int64_t, int, int, const double*, int64_t,
+                                                 const double*, double*, hipStream_t);
+template hipError_t launch_bdot_partials<float>(int64_t, int, int, const float*, int64_t,
+                                                const float*, double*, hipStream_t);
+
+// The workgroup's column j: hs[i] = sum of the partials of entry i (one wave
+// per entry, the order of k_bdot_reduce); workgroup 0 of the column also
+// stores them to H.
+__device__ __forceinline__ void bdot_sum_column(int b, int nb, int nchunk, int j,
+                                                const double* __restrict__ part,
+                                                double* __restrict__ H, int hld, double* hs) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < nb; i += 4) {
+    const double v = bdot_reduce_elem(b, j, i, nchunk, part, lane);
+    if (lane == 0) hs[i] = v;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && H && (int)threadIdx.x < nb) H[(int64_t)j * hld + threadIdx.x] = hs[threadIdx.x];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bupdate_diag_red(int64_t N, int b, int nb, int nchunk,
+                                                          double alpha, const T* __restrict__ V,
+                                                          int64_t bs, const double* __restrict__ part,
+                                                          double* __restrict__ H, int hld,
+                                                          T* __restrict__ W) {
+  __shared__ double hs[BD_MAXNB];
+  bdot_sum_column(b, nb, nchunk, blockIdx.y, part, H, hld, hs);
+  bupdate_row<T>(N, nb, alpha, V, bs, hs, 0, W, (int64_t)blockIdx.x * 256 + threadIdx.x, blockIdx.y);
+}
+
+template <typename T>
+hipError_t launch_bupdate_diag_red(int64_t N, int b, int nb, double alpha, const T* V, int64_t bs,
+                                   const double* partial, double* H, int hld, T* W, hipStream_t s) {
+  if (N <= 0 || b <= 0) return hipSuccess;
+  if (nb > BD_MAXNB) return hipErrorInvalidValue;
+  const int rows = bdot_rows(N);
+  const int nchunk = (int)((N + rows - 1) / rows);
+  hipLaunchKernelGGL((k_bupdate_diag_red<T>), dim3((unsigned)((N + 255) / 256), b), dim3(256), 0, s,
+                     N, b, nb, nchunk, alpha, V, bs, partial, H, hld, W);
+  return hipGetLastError();
+}
+template hipError_t launch_bupdate_diag_red<double>(int64_t, int, int, double, const double*,
+                                                    int64_t, const double*, double*, int, double*,
+                                                    hipStream_t);
+template hipError_t launch_bupdate_diag_red<float>(int64_t, int, int, double, const float*, int64_t,
+                                                   const double*, double*, int, float*, hipStream_t);
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_normalize_cols_red(int64_t N, int b, int nchunk,
+                                                            const double* __restrict__ part,
+                                                            const T* __restrict__ W,
+                                                            T* __restrict__ Vout,
+                                                            double* __restrict__ hout, int hld) {
+  __shared__ double hs[1];
+  bdot_sum_column(b, 1, nchunk, blockIdx.y, part, nullptr, 0, hs);
+  normalize_row_n2<T>(N, hs[0], W, Vout, hout, hld, (int64_t)blockIdx.x * 256 + threadIdx.x,
+                      blockIdx.y);
+}
+
+template <typename T>
+hipError_t launch_normalize_cols_red(int64_t N, int b, const double* partial, const T* W, T* Vout,
+                                     double* hout, int hld, hipStream_t s) {
+  if (b <= 0) return hipSuccess;
+  const int rows = bdot_rows(N);
+  const int nchunk = (int)((N + rows - 1) / rows);
+  hipLaunchKernelGGL((k_normalize_cols_red<T>), dim3((unsigned)((N + 255) / 256 + (N == 0)), b),
+                     dim3(256), 0, s, N, b, nchunk, partial, W, Vout, hout, hld);
+  return hipGetLastError();
+}
+template hipError_t launch_normalize_cols_red<double>(int64_t, int, const double*, const double*,
+                                                      double*, double*, int, hipStream_t);
+template hipError_t launch_normalize_cols_red<float>(int64_t, int, const double*, const float*,
+                                                     float*, double*, int, hipStream_t);
+
 // -------------------------------------------------------------- conversions
 template <typename TI, typename TO>
 __global__ void k_convert(int64_t N, double alpha, const TI* __restrict__ X, int64_t ldx,

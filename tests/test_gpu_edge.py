@@ -40,6 +40,18 @@ def test_empty_blocks_are_noops():
     assert rank == 0
 
 
+def test_tile_shape_range():
+    """Tile shapes -1 (automatic) to 4 are accepted, anything else is EINVAL."""
+    t3 = need_gpu()
+    op = t3.Operator.from_config(config("c1"))
+    for tile in (-1, 0, 1, 2, 3, 4, -1):
+        op.set_tile(tile)
+    for tile in (-2, 5, 100):
+        with pytest.raises(t3.Tp3bError) as e:
+            op.set_tile(tile)
+        assert e.value.code == -1
+
+
 def test_smallest_grid_apply_prec_and_solve():
     import torch
     t3 = need_gpu()
