@@ -222,6 +222,29 @@ def test_prec_fp32():
     assert err <= 1e-4
 
 
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_prec_c3_full_size(prec, bar):
+    """n = 1024 per coordinate, the 16-vector block of the c3 solves; the first
+    vector against the oracle's Bartels-Stewart solve (R7: 1e-10 in FP64; FP32
+    as at c2)."""
+    import torch
+    cfg = config("c3")
+    t3, P, op = _pair(cfg)
+    b = cfg["block"]
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Xn = normal_block(P.N, b, cfg["seed_apply"] + 7)
+    X = to_dev(Xn, dt)
+    Y = torch.empty_like(X)
+    say("c3 prec full size", prec)
+    op.apply_prec(X, Y)
+    torch.cuda.synchronize()
+    x0 = X[0].double().cpu().numpy()
+    Zr = P.preconditioner(sigma=op.sigma).apply(x0)
+    err = np.linalg.norm(Y[0].double().cpu().numpy() - Zr) / np.linalg.norm(Zr)
+    say("  rel err", err)
+    assert err <= bar
+
+
 def test_apply_2d_small():
     import torch
     t3 = need_gpu()
