@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from gpu_util import need_gpu, say, to_dev
-from oracle import dense, orth, problem
+from oracle import dense, operator, orth, problem
 from workloads import config, normal_block
 
 pytestmark = pytest.mark.gpu
@@ -132,6 +132,45 @@ def test_jdqr_c2_matches_oracle(inner, steps):
     err = np.max(np.abs(r.evals - ref) / np.abs(ref))
     say("  err", err, r.stats)
     assert err <= 1e-10
+
+
+def test_jdqr_c3_full_size():
+    """c3 at full size (n = 1024, N = 1,048,576, 16 eigenpairs, block 16), with
+    FP64 and with FP32 inner solves; properties that hold at any size: the two
+    solves' eigenvalues agree to 1e-10 (|dE| / max(|E|, 1), R21); the Schur
+    vectors are orthonormal to 1e-12; and the oracle's own apply of H to them
+    gives partial-Schur residuals ||H q_j - Q R[:, j]|| within the loosest
+    locking bar, 1e-8 max(|R_jj|, 1) (R18), plus the FP64 floor of forming
+    H q_j on either side: 4 (n_x + n_y + 1) eps || |H| |q_j| || (R21; at
+    n = 1024, ||H|| is about 6e9, so that floor is of the order of 1e-8)."""
+    import torch
+    t3 = need_gpu()
+    cfg = config("c3")
+    P = problem.make_problem(**cfg)
+    op = t3.Operator.from_config(cfg)
+    say("jdqr c3 fp64")
+    r64 = op.jdqr(cfg["nev"], cfg["block"], inner_prec=t3.FP64, seed=cfg["seed_start"])
+    say("  outer", r64.stats["n_outer"])
+    say("jdqr c3 fp32 inner")
+    r32 = op.jdqr(cfg["nev"], cfg["block"], inner_prec=t3.FP32, seed=cfg["seed_start"],
+                  want_Q=False)
+    say("  outer", r32.stats["n_outer"])
+    dE = np.max(np.abs(r64.evals - r32.evals) / np.maximum(np.abs(r64.evals), 1.0))
+    Q = r64.Q.cpu().numpy()                      # (nev, N)
+    R = np.asarray(r64.R)
+    orth = np.max(np.abs(Q @ Q.T - np.eye(Q.shape[0])))
+    HQ = P.apply(Q.T)                            # (N, nev), the oracle's operator
+    res = np.linalg.norm(HQ - Q.T @ R, axis=0)
+    # |H| |q|: the operator with every coefficient and entry by its magnitude
+    absHQ = operator.apply_1d(-np.abs(P.D2[0]), -np.abs(P.D2[1]), P.cx, P.cy, np.abs(P.V),
+                              np.abs(Q.T))
+    floor = 4 * (sum(P.n) + 1) * 2.2e-16 * np.linalg.norm(absHQ, axis=0)
+    bar = 1e-8 * np.maximum(np.abs(np.diag(R)), 1.0) + floor
+    say("  fp64 vs fp32-inner", dE, "orthonormality", orth, "residual", res.max(),
+        "worst residual / bar", np.max(res / bar))
+    assert dE <= 1e-10
+    assert orth <= 1e-12
+    assert np.all(res <= bar)
 
 
 @pytest.mark.parametrize("seed", [0, 5, 26, 34])
