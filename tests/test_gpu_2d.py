@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from gpu_util import need_gpu, say, to_dev
-from oracle import dense, physics, problem
+from oracle import dense, operator, physics, problem
 from workloads import config, normal_block
 
 pytestmark = pytest.mark.gpu
@@ -148,3 +148,39 @@ def test_jdqr_2d_preconditioned_vs_dense(inner):
         r0.stats["n_outer"])
     assert err <= 1e-10
     assert r.stats["n_outer"] < r0.stats["n_outer"]
+
+
+def test_jdqr_2d_c5_full_size():
+    """c5 at full size (2D, n = 64 per mode, N = 16.8 M; 6 eigenpairs, block 8)
+    with the 2D preconditioner, FP64 and FP32 inner solves: the eigenvalues of
+    the two agree to 1e-10 (|dE| / max(|E|, 1)); the Schur vectors are
+    orthonormal to 1e-12; for the first and the last Schur vector the oracle's
+    own apply gives ||H q_j - Q R[:, j]|| within the loosest locking bar
+    1e-8 max(|R_jj|, 1) plus the FP64 floor of forming H q_j,
+    4 (sum of the mode sizes + 1) eps || |H| |q_j| ||."""
+    t3 = need_gpu()
+    cfg = config("c5")
+    P = problem.make_problem(**cfg)
+    op = t3.Operator.from_config(cfg)
+    say("jdqr c5 fp64")
+    r64 = op.jdqr(cfg["nev"], cfg["block"], inner_prec=t3.FP64, seed=cfg["seed_start"])
+    say("  outer", r64.stats["n_outer"])
+    say("jdqr c5 fp32 inner")
+    r32 = op.jdqr(cfg["nev"], cfg["block"], inner_prec=t3.FP32, seed=cfg["seed_start"],
+                  want_Q=False)
+    say("  outer", r32.stats["n_outer"])
+    dE = np.max(np.abs(r64.evals - r32.evals) / np.maximum(np.abs(r64.evals), 1.0))
+    Q = r64.Q.cpu().numpy()
+    R = np.asarray(r64.R)
+    orth = np.max(np.abs(Q @ Q.T - np.eye(Q.shape[0])))
+    say("  fp64 vs fp32-inner", dE, "orthonormality", orth)
+    assert dE <= 1e-10
+    assert orth <= 1e-12
+    nev = Q.shape[0]
+    for j in (0, nev - 1):
+        hq = P.apply(Q[j])
+        res = np.linalg.norm(hq - Q.T @ R[:, j])
+        absHq = operator.apply_2d([-np.abs(d) for d in P.D2], P.cx, P.cy, np.abs(P.V), np.abs(Q[j]))
+        bar = 1e-8 * max(abs(R[j, j]), 1.0) + 4 * (sum(P.n) + 1) * 2.2e-16 * np.linalg.norm(absHq)
+        say("  column", j, "residual", res, "bar", bar)
+        assert res <= bar
