@@ -106,18 +106,15 @@ hipError_t launch_small_inverse(int n, const double* A, double* Ainv, int* singu
 template <typename T>
 hipError_t launch_bupdate_diag(int64_t N, int b, int nb, double alpha, const T* V, int64_t bs,
                                const double* H, int hld, T* W, hipStream_t s);
-// Vout[:, j] = W[:, j] / sqrt(nrm2[j]) (0 if the norm is not positive);
-// also stores hout[j*hld] = sqrt(nrm2[j]).
-template <typename T>
-hipError_t launch_normalize_cols(int64_t N, int b, const double* nrm2, const T* W, T* Vout,
-                                 double* hout, int hld, hipStream_t s);
 
 // The Arnoldi steps with the dots' second stage folded into their consumer:
 // launch_bdot_partials runs only the first stage of launch_bdot_diag into
 // `partial`; launch_bupdate_diag_red then sums those partials per column (the
 // same order as launch_bdot_diag), stores them to H[j*hld + i] and applies
 // W[r, j] += alpha * sum_i Vb[i][r, j] H[j*hld + i]; launch_normalize_cols_red
-// sums the partials of a norm (nb = 1) and normalizes as launch_normalize_cols.
+// sums the partials of a squared norm (nb = 1) and writes
+// Vout[:, j] = W[:, j] / sqrt(nrm2_j) (0 if the norm is not positive) and
+// hout[j*hld] = sqrt(nrm2_j).
 // Results equal those of the unfused sequence bit for bit.
 template <typename T>
 hipError_t launch_bdot_partials(int64_t N, int b, int nb, const T* V, int64_t bs, const T* W,

@@ -300,27 +300,6 @@ template hipError_t launch_bupdate_diag<double>(int64_t, int, int, double, const
 template hipError_t launch_bupdate_diag<float>(int64_t, int, int, double, const float*, int64_t,
                                                const double*, int, float*, hipStream_t);
 
-template <typename T>
-__global__ void k_normalize_cols(int64_t N, int b, const double* __restrict__ nrm2,
-                                 const T* __restrict__ W, T* __restrict__ Vout,
-                                 double* __restrict__ hout, int hld) {
-  normalize_row<T>(N, nrm2, W, Vout, hout, hld, (int64_t)blockIdx.x * 256 + threadIdx.x,
-                   blockIdx.y);
-}
-
-template <typename T>
-hipError_t launch_normalize_cols(int64_t N, int b, const double* nrm2, const T* W, T* Vout,
-                                 double* hout, int hld, hipStream_t s) {
-  if (b <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_normalize_cols<T>), dim3((unsigned)((N + 255) / 256 + (N == 0)), b),
-                     dim3(256), 0, s, N, b, nrm2, W, Vout, hout, hld);
-  return hipGetLastError();
-}
-template hipError_t launch_normalize_cols<double>(int64_t, int, const double*, const double*,
-                                                  double*, double*, int, hipStream_t);
-template hipError_t launch_normalize_cols<float>(int64_t, int, const double*, const float*, float*,
-                                                 double*, int, hipStream_t);
-
 // ------------------------------------- Arnoldi steps with the reduction fused
 // The per-column dots' first stage alone: partials for launch_bupdate_diag_red
 // and launch_normalize_cols_red, which sum them themselves (each workgroup in
