@@ -295,8 +295,11 @@ tp3b_status tp3b_autotune_batched(const tp3b_op* ops, int32_t count, int32_t pre
  * count x nev or NULL; n_conv, n_outer: host arrays of count or NULL; Q: NULL
  * or a host array of count device pointers (each NULL or N_i x nev) receiving
  * the Schur vectors; stats: totals over the batch (n_outer = the largest).
- * Synchronous.  ENOCONV if any instance stopped short of nev pairs (its
- * converged prefix is returned, the rest of its row is NaN). */
+ * Synchronous.  The instances' small dense problems (the ordered Schur forms
+ * of their projected matrices) are solved on up to 8 host threads that the
+ * call starts and joins; their results do not depend on the thread count.
+ * ENOCONV if any instance stopped short of nev pairs (its converged prefix is
+ * returned, the rest of its row is NaN). */
 tp3b_status tp3b_jdqr_solve_batched(const tp3b_op* ops, int32_t count, const tp3b_jdqr_opts* opts,
                                     double* evals, double* resnorm, int32_t* n_conv,
                                     int32_t* n_outer, double* const* Q, tp3b_jdqr_stats* stats);
