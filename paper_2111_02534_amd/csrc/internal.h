@@ -140,5 +140,12 @@ double* dot_scratch(int64_t doubles);
 tp3b_status block_orth_impl(int64_t N, int nq, const double* Q, int64_t ldq, int nx, double* X,
                             int64_t ldx, double* C_qx, double* R_xx, int* rank, uint64_t seed,
                             hipStream_t s);
+// The factor-free block orthogonalisation queued with no host round trip (CGS
+// twice against Q, Cholesky-QR twice).  dflags (device, nx + 1 ints) receive
+// the first factorisation's dependence flags and, at [nx], the non-finite test
+// of the input.  With no flag set X holds the orthonormal block; otherwise the
+// caller replaces the flagged columns and runs block_orth_impl on X.
+tp3b_status block_orth_queue(int64_t N, int nq, const double* Q, int64_t ldq, int nx, double* X,
+                             int64_t ldx, int* dflags, hipStream_t s);
 
 }  // namespace tp3b

@@ -215,7 +215,7 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
                r_upHinv = region((size_t)qt_max * qt_max), r_dnM = region(big * big),
                r_dnC1 = region((size_t)nev * b), r_dnC2 = region((size_t)nev * b),
                r_dnRn = region(b), r_dnTop = region(mb * b), r_dnLeft = region(mb * b),
-               r_dnFlag = region(1);
+               r_dnFlag = region(1), r_dnOFlags = region(b + 1);
   TP3B_HIP(hipHostMalloc((void**)&pin.p, sizeof(double) * pin_used, hipHostMallocDefault));
   auto P = [&](size_t r) { return pin.p + r; };
   // Declared after the buffers, so destroyed before them: on every return the
@@ -228,7 +228,7 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   const int hld = steps + 2;
   const size_t n_small = (size_t)(m_max + b) * (m_max + b) * 2 + (size_t)qt_max * qt_max +
                          (size_t)qt_max * b * 2 + (size_t)steps * b * hld * 2 + (size_t)steps * b +
-                         (size_t)b * 4 + (size_t)hld * b + 64;
+                         (size_t)b * 4 + (size_t)hld * b + (size_t)b + 64;
   TP3B_HIP(dalloc(smallb, sizeof(double) * n_small));
   double* QV = QVb.as<double>();
   double* AVbase = AVb.as<double>();
@@ -253,6 +253,7 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   double* dBeta = dNrm + b;                                          // b
   double* dY = dBeta + 2 * b;                                        // b*hld
   int* dFlag = (int*)(dY + (size_t)b * hld);  // singular projected preconditioner
+  int* dOFlags = dFlag + 2;                    // expansion block: b dependence flags, non-finite
   TP3B_HIP(hipMemsetAsync(dFlag, 0, sizeof(int), s));
   const int64_t dscr = dot_scratch_doubles(N, qt_max + m_max + b, qt_max + m_max + b) +
                        bdot_scratch_doubles(N, b, steps + 2) + 8 * (int64_t)(qv_cols + 1) * b +
@@ -622,20 +623,21 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     double to = now();
     double* Vn = QV + (int64_t)(k + m) * N;
     TP3B_HIP(hipMemcpyAsync(Vn, Tc, sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
-    int rank = 0;
-    tp3b_status os = block_orth_impl(N, k + m, QV, N, nb, Vn, N, nullptr, nullptr, &rank,
-                                     o.seed + 7919ull * (uint64_t)outer, s);
+    const uint64_t orth_seed = o.seed + 7919ull * (uint64_t)outer;
+    // queued without a round trip: the dependence flags come back with the
+    // projected matrix below
+    tp3b_status os = block_orth_queue(N, k + m, QV, N, nb, Vn, N, dOFlags, s);
     if (os != TP3B_OK) return os;
     part = dot_scratch(dscr);
     if (!part) return fail(TP3B_ENOMEM, "jdqr: scratch allocation failed");
     stats.t_orth += now() - to;
     double ta = now();
-    tp3b_status as = applyA64(nb, Vn, AV() + (int64_t)m * N);
-    if (as != TP3B_OK) return as;
     // the new columns (V^T A Vn) and rows (Vn^T A V) of the projected matrix,
-    // read back together
+    // read back together (with the block's dependence flags)
     std::vector<double> top((size_t)(m + nb) * nb), left((size_t)nb * m);
-    {
+    for (int pass = 0;; ++pass) {
+      tp3b_status as = applyA64(nb, Vn, AV() + (int64_t)m * N);
+      if (as != TP3B_OK) return as;
       std::vector<double> ct((size_t)(m + nb) * nb), cl((size_t)nb * m);
       TP3B_HIP(launch_dot_tn<double, double>(N, m + nb, nb, V(), N, AV() + (int64_t)m * N, N, dM2,
                                              m + nb, part, s));
@@ -643,14 +645,37 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       TP3B_HIP(launch_dot_tn<double, double>(N, nb, m, Vn, N, AV(), N, dS, nb, part, s));
       TP3B_HIP(hipMemcpyAsync(P(r_dnLeft), dS, sizeof(double) * cl.size(), hipMemcpyDeviceToHost, s));
       TP3B_HIP(hipMemcpyAsync(P(r_dnFlag), dFlag, sizeof(int), hipMemcpyDeviceToHost, s));
+      TP3B_HIP(hipMemcpyAsync(P(r_dnOFlags), dOFlags, sizeof(int) * (nb + 1), hipMemcpyDeviceToHost, s));
       TP3B_HIP(hipStreamSynchronize(s));
       if (*(const int*)P(r_dnFlag)) return fail(TP3B_ENOCONV, "jdqr: singular projected preconditioner");
+      const int* of = (const int*)P(r_dnOFlags);
+      if (pass == 0) {
+        if (of[nb]) return fail(TP3B_ENONFINITE, "block_orth: non-finite input");
+        bool dep = false;
+        for (int j = 0; j < nb; ++j) dep = dep || of[j];
+        if (dep) {
+          // a dependent column (rare): replaced by a random vector as the
+          // synchronous routine does, the block orthogonalised again with it,
+          // and A Vn and the projected entries recomputed
+          if (o.verbose) fprintf(stderr, "[tp3b jdqr] outer %d: dependent expansion column replaced\n", outer);
+          for (int j = 0; j < nb; ++j)
+            if (of[j]) TP3B_HIP(launch_hash_fill(N, Vn + (int64_t)j * N, orth_seed, (uint64_t)(1000 + j), s));
+          int rank = 0;
+          os = block_orth_impl(N, k + m, QV, N, nb, Vn, N, nullptr, nullptr, &rank, orth_seed, s);
+          if (os != TP3B_OK) return os;
+          part = dot_scratch(dscr);
+          if (!part) return fail(TP3B_ENOMEM, "jdqr: scratch allocation failed");
+          stats.n_apply_H_fp64 -= nb;  // the first A Vn is redone, not counted twice
+          continue;
+        }
+      }
       std::memcpy(ct.data(), P(r_dnTop), sizeof(double) * ct.size());
       std::memcpy(cl.data(), P(r_dnLeft), sizeof(double) * cl.size());
       for (int i = 0; i < m + nb; ++i)
         for (int j = 0; j < nb; ++j) top[(size_t)i * nb + j] = ct[i + (size_t)j * (m + nb)];
       for (int i = 0; i < nb; ++i)
         for (int j = 0; j < m; ++j) left[(size_t)i * m + j] = cl[i + (size_t)j * nb];
+      break;
     }
     std::vector<double> Mn((size_t)(m + nb) * (m + nb), 0.0);
     for (int i = 0; i < m; ++i)

@@ -499,13 +499,53 @@ template tp3b_status apply_prec_impl<float>(tp3b_op, int, const float*, int64_t,
 // as dependent.  Cholesky-QR forms the Gram matrix, whose pivots carry absolute
 // errors of order eps |x|^2, so dependence is only detectable above ~sqrt(eps).
 constexpr double kDropTol = 1e-7;
+// The scratch layout shared by block_orth_queue and block_orth_impl: dot
+// partials, C1, C2 ((nq+1) x nx each), G, R1, R2 (nx x nx), n0 (nx + 1), then
+// 2 nx + 1 ints of flags.
+static int64_t orth_scratch_doubles(int64_t N, int nq, int nx) {
+  const int pmax = nq > nx ? nq : nx;
+  return dot_scratch_doubles(N, pmax, nx) + 4 * (int64_t)(nq + 1) * nx + 6 * (int64_t)nx * nx +
+         2 * nx + 64;
+}
+
+tp3b_status block_orth_queue(int64_t N, int nq, const double* Q, int64_t ldq, int nx, double* X,
+                             int64_t ldx, int* dflags, hipStream_t s) {
+  const int pmax = nq > nx ? nq : nx;
+  double* scr = dot_scratch(orth_scratch_doubles(N, nq, nx));
+  if (!scr) return fail(TP3B_ENOMEM, "block_orth: scratch allocation failed");
+  double* part = scr;
+  double* C1 = part + dot_scratch_doubles(N, pmax, nx);
+  double* C2 = C1 + (int64_t)(nq + 1) * nx;
+  double* G = C2 + (int64_t)(nq + 1) * nx;
+  double* R1 = G + (int64_t)nx * nx;
+  double* R2 = R1 + (int64_t)nx * nx;
+  double* n0 = R2 + (int64_t)nx * nx;
+  int* fl2 = (int*)(n0 + nx + 1) + nx + 1;  // second Cholesky (no test)
+  int* fl1 = dflags;                        // first Cholesky: dependence flags
+  int* nonfin = dflags + nx;                // non-finite input
+  // the dependence test reads the input norms on the device
+  TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
+  TP3B_HIP(launch_gram_diag(nx, G, n0, nonfin, s));
+  if (nq > 0) {
+    TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, X, ldx, C1, nq, part, s));
+    TP3B_HIP(launch_gemm_nn<double>(N, nq, nx, -1.0, Q, ldq, C1, nq, 1.0, X, ldx, s));
+    TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, X, ldx, C2, nq, part, s));
+    TP3B_HIP(launch_gemm_nn<double>(N, nq, nx, -1.0, Q, ldq, C2, nq, 1.0, X, ldx, s));
+  }
+  TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
+  TP3B_HIP(launch_chol_small(nx, G, n0, kDropTol, R1, fl1, s));
+  TP3B_HIP(launch_trsm_right(N, nx, R1, X, ldx, s));
+  TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
+  TP3B_HIP(launch_chol_small(nx, G, n0, 0.0, R2, fl2, s));
+  TP3B_HIP(launch_trsm_right(N, nx, R2, X, ldx, s));
+  return TP3B_OK;
+}
+
 tp3b_status block_orth_impl(int64_t N, int nq, const double* Q, int64_t ldq, int nx, double* X,
                             int64_t ldx, double* C_qx, double* R_xx, int* rank, uint64_t seed,
                             hipStream_t s) {
   const int pmax = nq > nx ? nq : nx;
-  const int64_t sc = dot_scratch_doubles(N, pmax, nx) + 4 * (int64_t)(nq + 1) * nx +
-                     6 * (int64_t)nx * nx + 2 * nx + 64;
-  double* scr = dot_scratch(sc);
+  double* scr = dot_scratch(orth_scratch_doubles(N, nq, nx));
   if (!scr) return fail(TP3B_ENOMEM, "block_orth: scratch allocation failed");
   double* part = scr;
   double* C1 = part + dot_scratch_doubles(N, pmax, nx);
@@ -522,28 +562,12 @@ tp3b_status block_orth_impl(int64_t N, int nq, const double* Q, int64_t ldq, int
 
   if (!C_qx && !R_xx) {
     // Without factors to return, the whole sequence is queued with one host
-    // round trip at the end: the dependence test reads the input norms on the
-    // device, and the first factorisation's flags are read back last.  A
-    // dependent column (rare) is replaced by a random vector and the general
-    // path below runs on the result; span(X) is unchanged by the triangular
-    // transforms (a dependent column only carries directions of earlier ones).
-    int* fl1 = flags;           // first Cholesky: dependence flags
-    int* nonfin = flags + nx;   // non-finite input
-    int* fl2 = flags + nx + 1;  // second Cholesky (no test)
-    TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
-    TP3B_HIP(launch_gram_diag(nx, G, n0, nonfin, s));
-    if (nq > 0) {
-      TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, X, ldx, C1, nq, part, s));
-      TP3B_HIP(launch_gemm_nn<double>(N, nq, nx, -1.0, Q, ldq, C1, nq, 1.0, X, ldx, s));
-      TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, X, ldx, C2, nq, part, s));
-      TP3B_HIP(launch_gemm_nn<double>(N, nq, nx, -1.0, Q, ldq, C2, nq, 1.0, X, ldx, s));
-    }
-    TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
-    TP3B_HIP(launch_chol_small(nx, G, n0, kDropTol, R1, fl1, s));
-    TP3B_HIP(launch_trsm_right(N, nx, R1, X, ldx, s));
-    TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
-    TP3B_HIP(launch_chol_small(nx, G, n0, 0.0, R2, fl2, s));
-    TP3B_HIP(launch_trsm_right(N, nx, R2, X, ldx, s));
+    // round trip at the end (block_orth_queue).  A dependent column (rare) is
+    // replaced by a random vector and the general path below runs on the
+    // result; span(X) is unchanged by the triangular transforms (a dependent
+    // column only carries directions of earlier ones).
+    tp3b_status qs = block_orth_queue(N, nq, Q, ldq, nx, X, ldx, flags, s);
+    if (qs != TP3B_OK) return qs;
     TP3B_HIP(hipMemcpyAsync(hflags.data(), flags, sizeof(int) * (nx + 1), hipMemcpyDeviceToHost, s));
     TP3B_HIP(hipStreamSynchronize(s));
     if (hflags[nx]) return fail(TP3B_ENONFINITE, "block_orth: non-finite input");
