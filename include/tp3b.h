@@ -45,7 +45,7 @@ typedef enum {
   TP3B_ENOMEM = -2,     /* device or host allocation failed, or above the workspace cap */
   TP3B_EDEVICE = -3,    /* a HIP call failed; the message carries the HIP error string */
   TP3B_ENOCONV = -4,    /* eigensolver stopped before nev pairs converged */
-  TP3B_ENOTSUP = -5,    /* valid request this build does not support */
+  TP3B_ENOTSUP = -5,    /* valid request that the library does not support */
   TP3B_ENONFINITE = -6  /* NaN or Inf found in an input (when checking is enabled) */
 } tp3b_status;
 
