@@ -28,15 +28,23 @@ tp3b_status hip_fail(hipError_t e, const char* where) {
   return e == hipErrorOutOfMemory ? TP3B_ENOMEM : TP3B_EDEVICE;
 }
 tp3b_status exception_status() {
+  tp3b_status code = TP3B_EDEVICE;
+  char what[256] = "unknown host exception";
   try {
     throw;
   } catch (const std::bad_alloc&) {
-    return fail(TP3B_ENOMEM, "host memory allocation failed");
+    code = TP3B_ENOMEM;
+    std::snprintf(what, sizeof(what), "%s", "host memory allocation failed");
   } catch (const std::exception& e) {
-    return fail(TP3B_EDEVICE, std::string("host exception: ") + e.what());
+    std::snprintf(what, sizeof(what), "%s", e.what());
   } catch (...) {
-    return fail(TP3B_EDEVICE, "unknown host exception");
   }
+  try {
+    g_err = std::string("host exception: ") + what;
+  } catch (...) {
+    // no memory even for the message: the status alone reports it
+  }
+  return code;
 }
 
 // ---------------------------------------------------------------- grids
