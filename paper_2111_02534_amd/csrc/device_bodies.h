@@ -624,8 +624,8 @@ __device__ __forceinline__ double dot_reduce_elem(int gp, int gq, int nchunk, in
 }
 
 // ------------------------------------------------------------ basis update
-// Y (a block of rows, columns q0..q0+15) = beta Y + alpha A C, one row per lane,
-// in one of two forms:
+// Y (a block of rows, columns q0..q0+15) = beta Y + alpha A C (or, with X0,
+// beta X0 + alpha A C, X0 not aliasing Y), one row per lane, in one of two forms:
 //  * SPLIT (64 rows per workgroup): the four waves split the p range into
 //    quarters and sum their partial rows in LDS in wave order.  For a single
 //    short block of vectors that puts four times as many workgroups and loads
@@ -650,7 +650,8 @@ __device__ __forceinline__ void gemm_block(int64_t N, int p, int q, double alpha
                                            const T* __restrict__ A, int64_t lda,
                                            const double* __restrict__ C, int ldc, double beta,
                                            T* __restrict__ Y, int64_t ldy, int64_t rblock,
-                                           int qblock, GemmSmem<SPLIT>& sm) {
+                                           int qblock, GemmSmem<SPLIT>& sm,
+                                           const T* __restrict__ X0 = nullptr, int64_t ldx0 = 0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r = rblock * gemm_rows<SPLIT>() + (SPLIT ? lane : (int)threadIdx.x);
   const int q0 = qblock * GEMM_QB;
@@ -699,7 +700,7 @@ __device__ __forceinline__ void gemm_block(int64_t N, int p, int q, double alpha
         if (j < nq) {
           const double v = sm.red[0][lane][j] + sm.red[1][lane][j] + sm.red[2][lane][j] + sm.red[3][lane][j];
           T* y = Y + r + (int64_t)(q0 + j) * ldy;
-          const double old = (beta != 0.0) ? (double)(*y) : 0.0;
+          const double old = (beta != 0.0) ? (double)(X0 ? X0[r + (int64_t)(q0 + j) * ldx0] : *y) : 0.0;
           *y = (T)(beta * old + alpha * v);
         }
       }
@@ -709,7 +710,7 @@ __device__ __forceinline__ void gemm_block(int64_t N, int p, int q, double alpha
     for (int j = 0; j < GEMM_QB; ++j) {
       if (j < nq) {
         T* y = Y + r + (int64_t)(q0 + j) * ldy;
-        const double old = (beta != 0.0) ? (double)(*y) : 0.0;
+        const double old = (beta != 0.0) ? (double)(X0 ? X0[r + (int64_t)(q0 + j) * ldx0] : *y) : 0.0;
         *y = (T)(beta * old + alpha * acc[j]);
       }
     }

@@ -365,12 +365,12 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     M = T;
     const int nb = std::min(b, m);
     // ---- 2. residuals R = (I - Q Q^T)(A U - V T[:, :nb])
-    TP3B_HIP(hipMemcpyAsync(Rres, AV(), sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
     {
       std::vector<double> Tc_ = colmajor(T, m, 0, 0, m, nb);
       std::memcpy(P(r_upT), Tc_.data(), sizeof(double) * m * nb);
       TP3B_HIP(hipMemcpyAsync(dS, P(r_upT), sizeof(double) * m * nb, hipMemcpyHostToDevice, s));
-      TP3B_HIP(launch_gemm_nn<double>(N, m, nb, -1.0, V(), N, dS, m, 1.0, Rres, N, s));
+      // Rres = A U - V T[:, :nb], A U being the first nb columns of A V
+      TP3B_HIP(launch_gemm_nn_x0<double>(N, m, nb, -1.0, V(), N, dS, m, 1.0, AV(), N, Rres, N, s));
     }
     std::vector<double> Cq((size_t)std::max(k, 1) * nb, 0.0);  // Q^T A U, column-major k x nb
     std::vector<double> c1((size_t)std::max(k, 1) * nb), c2((size_t)std::max(k, 1) * nb);

@@ -83,6 +83,13 @@ hipError_t launch_gemm_nn(int64_t N, int p, int q, double alpha, const T* A, int
                           const double* C, int ldc, double beta, T* Y, int64_t ldy,
                           hipStream_t s);
 
+// Y (N x q, ldy) = beta X0 + alpha A C with X0 (N x q, ldx0) a separate input
+// that Y does not alias (X0 == nullptr: as launch_gemm_nn).
+template <typename T>
+hipError_t launch_gemm_nn_x0(int64_t N, int p, int q, double alpha, const T* A, int64_t lda,
+                             const double* C, int ldc, double beta, const T* X0, int64_t ldx0, T* Y,
+                             int64_t ldy, hipStream_t s);
+
 // Batched per-column dots for b independent Krylov bases stored as blocks
 // Vb[i] = V + i*bs (each N x b, ld N):  H[j*hld + i] = sum_r Vb[i][r, j] W[r, j]
 // for i < nb.  `partial` as for the dot.

@@ -212,20 +212,32 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_nn(int64_t N, int p, int q, double alpha,
                                                  const T* __restrict__ A, int64_t lda,
                                                  const double* __restrict__ C, int ldc,
-                                                 double beta, T* __restrict__ Y, int64_t ldy) {
+                                                 double beta, const T* __restrict__ X0, int64_t ldx0,
+                                                 T* __restrict__ Y, int64_t ldy) {
   __shared__ GemmSmem<true> sm;
-  gemm_block<T, true>(N, p, q, alpha, A, lda, C, ldc, beta, Y, ldy, blockIdx.x, blockIdx.y, sm);
+  gemm_block<T, true>(N, p, q, alpha, A, lda, C, ldc, beta, Y, ldy, blockIdx.x, blockIdx.y, sm, X0,
+                      ldx0);
 }
+
+template <typename T>
+hipError_t launch_gemm_nn_x0(int64_t N, int p, int q, double alpha, const T* A, int64_t lda,
+                             const double* C, int ldc, double beta, const T* X0, int64_t ldx0, T* Y,
+                             int64_t ldy, hipStream_t s) {
+  if (N <= 0 || q <= 0) return hipSuccess;
+  dim3 grid((unsigned)((N + gemm_rows<true>() - 1) / gemm_rows<true>()), (q + GEMM_QB - 1) / GEMM_QB);
+  hipLaunchKernelGGL((k_gemm_nn<T>), grid, dim3(256), 0, s, N, p, q, alpha, A, lda, C, ldc, beta, X0,
+                     ldx0, Y, ldy);
+  return hipGetLastError();
+}
+template hipError_t launch_gemm_nn_x0<double>(int64_t, int, int, double, const double*, int64_t,
+                                              const double*, int, double, const double*, int64_t,
+                                              double*, int64_t, hipStream_t);
 
 template <typename T>
 hipError_t launch_gemm_nn(int64_t N, int p, int q, double alpha, const T* A, int64_t lda,
                           const double* C, int ldc, double beta, T* Y, int64_t ldy,
                           hipStream_t s) {
-  if (N <= 0 || q <= 0) return hipSuccess;
-  dim3 grid((unsigned)((N + gemm_rows<true>() - 1) / gemm_rows<true>()), (q + GEMM_QB - 1) / GEMM_QB);
-  hipLaunchKernelGGL((k_gemm_nn<T>), grid, dim3(256), 0, s, N, p, q, alpha, A, lda, C, ldc, beta,
-                     Y, ldy);
-  return hipGetLastError();
+  return launch_gemm_nn_x0<T>(N, p, q, alpha, A, lda, C, ldc, beta, (const T*)nullptr, 0, Y, ldy, s);
 }
 template hipError_t launch_gemm_nn<double>(int64_t, int, int, double, const double*, int64_t,
                                            const double*, int, double, double*, int64_t,
