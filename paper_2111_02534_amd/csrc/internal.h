@@ -144,8 +144,10 @@ tp3b_status block_orth_impl(int64_t N, int nq, const double* Q, int64_t ldq, int
 // twice against Q, Cholesky-QR twice).  dflags (device, nx + 1 ints) receive
 // the first factorisation's dependence flags and, at [nx], the non-finite test
 // of the input.  With no flag set X holds the orthonormal block; otherwise the
-// caller replaces the flagged columns and runs block_orth_impl on X.
+// caller replaces the flagged columns and runs block_orth_impl on X.  Xin
+// (optional, same leading dimension, not aliasing X) is the input block when it
+// lives elsewhere: the first projection writes its result into X.
 tp3b_status block_orth_queue(int64_t N, int nq, const double* Q, int64_t ldq, int nx, double* X,
-                             int64_t ldx, int* dflags, hipStream_t s);
+                             int64_t ldx, int* dflags, hipStream_t s, const double* Xin = nullptr);
 
 }  // namespace tp3b

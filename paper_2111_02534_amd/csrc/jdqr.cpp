@@ -622,11 +622,10 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     // ---- 5. expand the basis
     double to = now();
     double* Vn = QV + (int64_t)(k + m) * N;
-    TP3B_HIP(hipMemcpyAsync(Vn, Tc, sizeof(double) * N * nb, hipMemcpyDeviceToDevice, s));
     const uint64_t orth_seed = o.seed + 7919ull * (uint64_t)outer;
-    // queued without a round trip: the dependence flags come back with the
-    // projected matrix below
-    tp3b_status os = block_orth_queue(N, k + m, QV, N, nb, Vn, N, dOFlags, s);
+    // queued without a round trip (the dependence flags come back with the
+    // projected matrix below); reads the correction from Tc and writes Vn
+    tp3b_status os = block_orth_queue(N, k + m, QV, N, nb, Vn, N, dOFlags, s, Tc);
     if (os != TP3B_OK) return os;
     part = dot_scratch(dscr);
     if (!part) return fail(TP3B_ENOMEM, "jdqr: scratch allocation failed");

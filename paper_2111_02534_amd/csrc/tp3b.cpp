@@ -517,7 +517,12 @@ static int64_t orth_scratch_doubles(int64_t N, int nq, int nx) {
 }
 
 tp3b_status block_orth_queue(int64_t N, int nq, const double* Q, int64_t ldq, int nx, double* X,
-                             int64_t ldx, int* dflags, hipStream_t s) {
+                             int64_t ldx, int* dflags, hipStream_t s, const double* Xin) {
+  if (!Xin) Xin = X;
+  if (Xin != X && nq <= 0)
+    TP3B_HIP(hipMemcpy2DAsync(X, sizeof(double) * ldx, Xin, sizeof(double) * ldx, sizeof(double) * N,
+                              nx, hipMemcpyDeviceToDevice, s));
+  if (nq <= 0) Xin = X;
   const int pmax = nq > nx ? nq : nx;
   double* scr = dot_scratch(orth_scratch_doubles(N, nq, nx));
   if (!scr) return fail(TP3B_ENOMEM, "block_orth: scratch allocation failed");
@@ -532,11 +537,12 @@ tp3b_status block_orth_queue(int64_t N, int nq, const double* Q, int64_t ldq, in
   int* fl1 = dflags;                        // first Cholesky: dependence flags
   int* nonfin = dflags + nx;                // non-finite input
   // the dependence test reads the input norms on the device
-  TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
+  TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, Xin, ldx, Xin, ldx, G, nx, part, s));
   TP3B_HIP(launch_gram_diag(nx, G, n0, nonfin, s));
   if (nq > 0) {
-    TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, X, ldx, C1, nq, part, s));
-    TP3B_HIP(launch_gemm_nn<double>(N, nq, nx, -1.0, Q, ldq, C1, nq, 1.0, X, ldx, s));
+    // the first pass reads the input and writes X = Xin - Q C1
+    TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, Xin, ldx, C1, nq, part, s));
+    TP3B_HIP(launch_gemm_nn_x0<double>(N, nq, nx, -1.0, Q, ldq, C1, nq, 1.0, Xin, ldx, X, ldx, s));
     TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, X, ldx, C2, nq, part, s));
     TP3B_HIP(launch_gemm_nn<double>(N, nq, nx, -1.0, Q, ldq, C2, nq, 1.0, X, ldx, s));
   }
