@@ -145,7 +145,7 @@ class JDQRResult:
 def jdqr(apply_A, N, nev, block, *, tol=1e-12, m_min=None, m_max=None,
          gmres_steps=10, precond=None, apply_inner=None, X0=None, seed=0,
          max_outer=1000, target=None, switch_tol=1e-2, stall_tol=1e-8, target_low=None,
-         low_iters=3):
+         low_iters=3, progress=None):
     """Partial Schur form for the nev eigenvalues of smallest real part.
 
     apply_A(X) -> A X for X of shape (N, k), in FP64.  apply_inner, if given,
@@ -162,7 +162,9 @@ def jdqr(apply_A, N, nev, block, *, tol=1e-12, m_min=None, m_max=None,
     its residual is <= stall_tol max(|theta|, 1) and has stayed within 10 % of
     its previous value in three consecutive outer iterations -- the residual has
     reached the FP64 rounding floor of the stored images A V, which grows with
-    ||A|| (<= 0 disables)."""
+    ||A|| (<= 0 disables).
+    progress: optional callable(outer, n_locked, rn, theta) called once per
+    outer iteration (reporting only)."""
     b = block
     dmin, dmax = default_sizes(nev, b)
     m_min = dmin if m_min is None else m_min
@@ -271,6 +273,8 @@ def jdqr(apply_A, N, nev, block, *, tol=1e-12, m_min=None, m_max=None,
         AV = np.hstack([AV, apply_A(Vn)])
         res.n_apply += Vn.shape[1]
         res.history.append(("iter", outer, float(rn[0]), float(theta[0])))
+        if progress is not None:
+            progress(outer, Q.shape[1], rn, theta)
     ev = np.linalg.eigvals(Rl) if Rl.size else np.zeros(0)
     order = np.argsort(ev.real, kind="stable")
     res.evals = ev[order]

@@ -48,19 +48,23 @@ class KineticSylvester:
         single = B.ndim == 2
         if single:
             B = B[None]
+        nb = B.shape[0]
         F = self.Ux.T @ B @ self.Uy
-        # Work with G^T (columns of G as contiguous rows) for the sweep.
-        Ft = np.ascontiguousarray(np.swapaxes(F, 1, 2))      # (b, n_y, n_x)
+        # Columns of G are found from the last one backwards (T_y^T is lower
+        # triangular, so column j of G T_y^T involves the columns l >= j).  The
+        # columns are stored as contiguous slabs Gt[j] of shape (n_x, b) so that
+        # the sum over l > j is one matrix-vector product.
+        Ft = np.ascontiguousarray(np.transpose(F, (2, 1, 0)))   # (n_y, n_x, b)
         Gt = np.zeros_like(Ft)
         Ty = self.Ty
-        # T_y^T is lower triangular: column j of G T_y^T involves G[:, l] for
-        # l >= j, so the columns are found from the last one backwards.
+        M = np.array(self.Tx, order="F")
+        diag = np.diag_indices(self.nx)
         for j in range(self.ny - 1, -1, -1):
-            rhs = Ft[:, j, :] - (Ty[j, j + 1:] @ Gt[:, j + 1:, :])
-            M = self.Tx + Ty[j, j] * np.eye(self.nx)
-            Gt[:, j, :] = scipy.linalg.solve_triangular(M, rhs.T, lower=False,
-                                                        check_finite=False).T
-        G = np.swapaxes(Gt, 1, 2)
+            rest = self.ny - j - 1
+            rhs = Ft[j] - (Ty[j, j + 1:] @ Gt[j + 1:].reshape(rest, self.nx * nb)).reshape(self.nx, nb)
+            M[diag] = self.Tx[diag] + Ty[j, j]
+            Gt[j] = scipy.linalg.solve_triangular(M, rhs, lower=False, check_finite=False)
+        G = np.ascontiguousarray(np.transpose(Gt, (2, 1, 0)))   # (b, n_x, n_y)
         Z = self.Ux @ G @ self.Uy.T
         return Z[0] if single else Z
 

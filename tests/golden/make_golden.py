@@ -27,8 +27,15 @@ def run(name):
     pc = P.preconditioner()
     sig = P.two_body_shift()
     t = time.time()
+    t0 = time.time()
+
+    def progress(outer, nlock, rn, theta):
+        print(f"  {name} outer {outer} locked {nlock} theta0 {theta[0]:.12g} "
+              f"res0 {rn[0]:.3e} ({time.time() - t0:.0f} s)", flush=True)
+
     r = jdqr.jdqr(P.apply, P.N, c["nev"], c["block"], precond=pc.apply, seed=c["seed_start"],
-                  target=sig, target_low=P.spectrum_lower_bound(), max_outer=400)
+                  target=sig, target_low=P.spectrum_lower_bound(), max_outer=400,
+                  progress=progress)
     dt = time.time() - t
     assert r.converged, name
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_evals.txt")
