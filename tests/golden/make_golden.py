@@ -3,11 +3,17 @@ CPU oracle only (block JDQR with the Bartels-Stewart preconditioner, FP64).
 
     python tests/golden/make_golden.py c2 [c3 ...]
     python tests/golden/make_golden.py c4 [--procs 8]
+    python tests/golden/make_golden.py c4dense [--procs 8]
+    python tests/golden/make_golden.py c5r
 
 Each output file holds the nev converged eigenvalues of the named workload
 (ascending) and the oracle's final residual norms.  For the batched workload c4
 the file holds one line per instance: index, n, M/m, V0, w and the 4 lowest
-eigenvalues (instances solved independently in a process pool)."""
+eigenvalues (instances solved independently in a process pool).  c4dense: for every instance
+of the batched workload with n = 64 (N = 4096) the 4 eigenvalues of smallest real
+part of the explicit Kronecker matrix (dense eigensolver, the plain definition).
+c5r: the 2D workload c5 at n = 20 per mode (N = 160,000), the reduced size at
+which the oracle's four-mode preconditioned JDQR finishes in minutes."""
 import os
 import sys
 import time
@@ -93,6 +99,37 @@ def run_c4(procs):
     print("c4", len(res), f"{time.time() - t:.1f}s", flush=True)
 
 
+def _c4_dense_one(args):
+    from oracle import dense
+    i, c = args
+    P = problem.make_problem(**c)
+    return i, dense.lowest_eigenvalues(P.kron(), c["nev"]).real.copy()
+
+
+def run_c4_dense(procs):
+    from multiprocessing import Pool
+
+    from workloads import c4_instances
+    inst = c4_instances()
+    todo = [(i, c) for i, c in enumerate(inst) if c["n"] == 64]
+    t = time.time()
+    res = []
+    with Pool(procs) as pool:
+        for k, out in enumerate(pool.imap_unordered(_c4_dense_one, todo)):
+            res.append(out)
+            print(f"  {k + 1}/{len(todo)} instance {out[0]}", flush=True)
+    res.sort(key=lambda r: r[0])
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c4_dense_n64.txt")
+    with open(out, "w") as f:
+        f.write(f"# Lowest 4 eigenvalues (smallest real part) of the explicit Kronecker matrix of\n")
+        f.write(f"# each of the {len(todo)} instances of workload c4 with n = 64 (N = 4096),\n")
+        f.write(f"# dense eigensolver of the CPU oracle; {time.time() - t:.0f} s in total.\n")
+        f.write("# index e0 e1 e2 e3\n")
+        for i, ev in res:
+            f.write(f"{i} " + " ".join(f"{e:.17g}" for e in ev) + "\n")
+    print("c4dense", len(res), f"{time.time() - t:.1f}s", flush=True)
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
     procs = 8
@@ -103,5 +140,7 @@ if __name__ == "__main__":
     for name in args:
         if name == "c4":
             run_c4(procs)
+        elif name == "c4dense":
+            run_c4_dense(procs)
         else:
             run(name)

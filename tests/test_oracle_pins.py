@@ -168,6 +168,131 @@ def test_separable_harmonic_closed_form():
     assert np.max(np.abs(r.evals.real - exact) / exact) < 1e-10
 
 
+# ------------------------------------------------ 2D operator (eqs. (8), (11))
+# Distinct grid sizes and half-widths per mode: a mode operator applied to the
+# wrong index, or the x and y coefficients given to the wrong modes, changes the
+# spectrum.
+N2D_SMALL = (5, 4, 6, 3)
+L2D_SMALL = (3.0, 4.0, 2.5, 5.0)
+
+
+def _lowest_sums(parts, k):
+    """The k smallest values of a_1 + a_2 + a_3 + a_4 over one value a_m from
+    each of the four 1D spectra in `parts` (the spectrum of a Kronecker sum)."""
+    tot = np.zeros(1)
+    for p in parts:
+        tot = (tot[:, None] + np.sort(np.asarray(p))[None, :]).ravel()
+    return np.sort(tot)[:k]
+
+
+def test_free_2d_is_kronecker_sum_of_modes():
+    """P3 in 2D, exact discrete form: with V0 = 0 the 2D Hamiltonian is the
+    Kronecker sum over the four modes of -c D2_k with (c_x, c_x, c_y, c_y) for
+    (x1, x2, y1, y2), so its eigenvalues are all sums of one eigenvalue of each
+    mode operator."""
+    P = problem.make_problem(ndim=2, n=N2D_SMALL, L=L2D_SMALL, alpha=3.0, v0=0.0)
+    ev = np.sort(np.linalg.eigvals(P.kron()).real)[:8]
+    coef = (P.cx, P.cx, P.cy, P.cy)
+    parts = [np.linalg.eigvals(-c * d).real for c, d in zip(coef, P.D2)]
+    want = _lowest_sums(parts, 8)
+    assert np.max(np.abs(ev - want) / np.abs(want)) < 1e-12
+    # the tensor-form apply drives the eigensolver to the same values
+    r = jdqr.jdqr(P.apply, P.N, 4, 4, seed=21, max_outer=400)
+    assert r.converged
+    assert np.max(np.abs(np.sort(r.evals.real) - want[:4]) / want[:4]) < 1e-10
+
+
+def test_free_2d_closed_form():
+    """P3 in 2D at resolution: with V0 = 0 the lowest eigenvalues are
+    sum_k c_k (j_k pi / 2 L_k)^2 over the four modes (particle in a box per
+    mode), found by the tensor-form apply inside the preconditioned eigensolver
+    (the kinetic preconditioner is the exact inverse here)."""
+    n = (14, 15, 11, 12)
+    L = (3.0, 3.5, 2.0, 2.5)
+    P = problem.make_problem(ndim=2, n=n, L=L, alpha=3.0, v0=0.0)
+    coef = (P.cx, P.cx, P.cy, P.cy)
+    j = np.arange(1, 4)
+    parts = [c * (j * np.pi / (2.0 * l)) ** 2 for c, l in zip(coef, L)]
+    exact = _lowest_sums(parts, 4)
+    pc = P.preconditioner(sigma=0.0)
+    r = jdqr.jdqr(P.apply, P.N, 4, 4, precond=pc.apply, target=0.0, seed=22, max_outer=100)
+    assert r.converged
+    assert np.max(np.abs(np.sort(r.evals.real) - exact) / exact) < 1e-10
+
+
+def test_harmonic_2d_separates_over_modes():
+    """P4 in 2D: u(r) = k r^2 / 2 for both light-heavy pairs gives
+    V = k |y|^2 + k |x|^2 / 4 (the cross terms x.y cancel), a sum of one
+    potential per mode, so H is the Kronecker sum of the 1D operators
+    -c_x D2 + k x_m^2 / 4 (x modes) and -c_y D2 + k y_m^2 (y modes); exact on
+    any grid.  With the 1D closed form of each piece (2 sqrt(c q)(j + 1/2) for
+    -c d^2 + q s^2, checked on resolved 1D grids) this gives the 2D closed form
+    E = sum over x modes 2 sqrt(c_x k/4)(j + 1/2) + sum over y modes
+    2 sqrt(c_y k)(l + 1/2)."""
+    kk = 1.3
+    P = problem.make_problem(ndim=2, n=N2D_SMALL, L=L2D_SMALL, alpha=3.0, v0=kk,
+                             shape="harmonic")
+    ev = np.sort(np.linalg.eigvals(P.kron()).real)[:8]
+    coef = (P.cx, P.cx, P.cy, P.cy)
+    q = (kk / 4.0, kk / 4.0, kk, kk)
+    parts = [np.linalg.eigvals(-c * d + np.diag(qq * g * g)).real
+             for c, d, qq, g in zip(coef, P.D2, q, P.grids)]
+    want = _lowest_sums(parts, 8)
+    assert np.max(np.abs(ev - want) / np.abs(want)) < 1e-11
+    r = jdqr.jdqr(P.apply, P.N, 4, 4, seed=23, max_outer=400)
+    assert r.converged
+    assert np.max(np.abs(np.sort(r.evals.real) - want[:4]) / want[:4]) < 1e-10
+    # the pieces on resolved grids reproduce the oscillator levels, so the sums
+    # reproduce the 2D closed form
+    res = []
+    for c, qq in ((P.cx, kk / 4.0), (P.cy, kk)):
+        x = cheb.nodes(56, 8.0)
+        d = cheb.second_derivative_dirichlet(56, 8.0)
+        e = np.sort(np.linalg.eigvals(-c * d + np.diag(qq * x * x)).real)[:3]
+        w = 2.0 * np.sqrt(c * qq)
+        assert np.max(np.abs(e - w * (np.arange(3) + 0.5)) / e) < 1e-10
+        res.append(e)
+    exact = _lowest_sums([w * (np.arange(3) + 0.5) for w in
+                          (2 * np.sqrt(P.cx * kk / 4), 2 * np.sqrt(P.cx * kk / 4),
+                           2 * np.sqrt(P.cy * kk), 2 * np.sqrt(P.cy * kk))], 4)
+    assert np.max(np.abs(_lowest_sums([res[0], res[0], res[1], res[1]], 4) - exact) / exact) < 1e-10
+
+
+def test_potential_2d_on_coordinate_lines():
+    """The 2D potential on configurations that lie on a line: along either
+    axis (x2 = y2 = 0, or x1 = y1 = 0) and along the diagonal (x1 = x2,
+    y1 = y2, i.e. x = s (1, 1), y = t (1, 1), |x| = sqrt(2) |s|) it equals the 1D
+    potential at the corresponding signed distances.  Pairing x1 with y2 (or
+    any other cross pairing of the components) fails the axis cases."""
+    x = np.linspace(-3.0, 3.0, 7)
+    y = np.linspace(-2.0, 2.5, 6)
+    V1 = physics.potential_1d(x, y, "gauss", 2.0, 0.8)
+    z1, z2 = np.array([0.0]), np.array([0.0])
+    assert np.allclose(physics.potential_2d(x, z1, y, z2, "gauss", 2.0, 0.8)[:, 0, :, 0], V1,
+                       rtol=0, atol=1e-15)
+    assert np.allclose(physics.potential_2d(z1, x, z2, y, "gauss", 2.0, 0.8)[0, :, 0, :], V1,
+                       rtol=0, atol=1e-15)
+    V2 = physics.potential_2d(x, x, y, y, "gauss", 2.0, 0.8)
+    Vd = physics.potential_1d(np.sqrt(2.0) * x, np.sqrt(2.0) * y, "gauss", 2.0, 0.8)
+    diag = np.array([[V2[i, i, j, j] for j in range(y.size)] for i in range(x.size)])
+    assert np.allclose(diag, Vd, rtol=0, atol=1e-14)
+
+
+def test_hamiltonian_2d_rotation_symmetry():
+    """Rotating both Jacobi vectors by 90 degrees, (x1, x2, y1, y2) ->
+    (-x2, x1, -y2, y1), leaves the three-body Hamiltonian unchanged: on a grid
+    with equal x modes and equal y modes (symmetric nodes) the permutation
+    commutes with H, and the spectrum contains degenerate pairs."""
+    n, L = (5, 5, 4, 4), (3.0, 3.0, 2.0, 2.0)
+    P = problem.make_problem(ndim=2, n=n, L=L, alpha=3.0, v0=2.0, width=0.9)
+    idx = np.arange(P.N).reshape(n)
+    # new[i1, i2, j1, j2] = old[rotated point]: x1' = -x2 -> index n-1-i2, x2' = x1 -> i1
+    perm = idx[:, ::-1, :, ::-1].transpose(1, 0, 3, 2)
+    perm = np.ascontiguousarray(perm).ravel()
+    H = P.kron()
+    assert np.max(np.abs(H[np.ix_(perm, perm)] - H)) <= 1e-12 * np.max(np.abs(H))
+
+
 # ------------------------------------------------------ two-body (eq. (1), Table 1)
 def test_two_body_depth_matches_table1():
     """P8: depth v0 giving binding energy E0 = 0.1 for f_G, paper units."""
@@ -469,7 +594,11 @@ def _table3():
 
 
 def _shape(code):
-    return (lambda r: np.exp(-r * r)) if code == 0 else (lambda r: 1.0 / (1.0 + r * r) ** 3)
+    """The oracle's pair-potential shapes of eq. (4) (code 0, f_G) and eq. (5)
+    (code 1, f_L) at unit depth: f(r) = -u(r) with u the oracle's pair
+    potential of depth 1, so the Table 3 depths below pin both shapes."""
+    name = "gauss_paper" if code == 0 else "lorentz3"
+    return lambda r: -physics.PAIR[name](r, 1.0)
 
 
 def test_radial_2d_depths_match_table3():

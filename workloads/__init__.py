@@ -20,6 +20,8 @@ measured on:
   [0.5, 2]; lowest 4, block 4.
 * ``c5`` 2D (four tensor modes), n = 64 per mode (N = 16,777,216), M/m = 20,
   depth 3, lowest 6, block 8.
+* ``c5r`` the same 2D problem at n = 20 per mode (N = 160,000): the reduced size
+  at which the CPU oracle's eigensolver finishes in minutes.
 
 All use Chebyshev-Gauss-Lobatto grids on [-15, 15] with Dirichlet conditions and
 the Gaussian pair potential -V0 exp(-r^2 / (2 w^2)).
@@ -41,6 +43,8 @@ CONFIGS = {
                nev=16, block=16, seed_apply=3, seed_start=3),
     "c5": dict(ndim=2, n=64, L=L_DEFAULT, alpha=20.0, v0=3.0, width=1.0,
                nev=6, block=8, seed_apply=5, seed_start=5),
+    "c5r": dict(ndim=2, n=20, L=L_DEFAULT, alpha=20.0, v0=3.0, width=1.0,
+                nev=6, block=8, seed_apply=5, seed_start=5),
 }
 
 C4_SIZES = (64, 96, 128, 192, 256)
