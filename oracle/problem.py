@@ -73,8 +73,8 @@ def make_problem(ndim, n, L, alpha=None, v0=1.0, width=1.0, shape="gauss",
                  **_ignored):
     """grid: "cgl" (n interior Gauss-Lobatto points of [-L, L], Dirichlet) or
     "mapped" (Chebyshev roots mapped to the real line with parameter L).
-    parity (mapped grid only): per mode 0 (full grid of n points), +1 or -1
-    (even / odd functions; n unknowns at the positive nodes of a 2n-point grid)."""
+    parity: per mode 0 (full grid of n points), +1 or -1 (even / odd functions;
+    n unknowns at the positive nodes of a 2n-point grid of the same kind)."""
     nn = (n,) * (2 * ndim) if np.isscalar(n) else tuple(n)
     LL = (L,) * (2 * ndim) if np.isscalar(L) else tuple(L)
     if cx is None:
@@ -83,8 +83,18 @@ def make_problem(ndim, n, L, alpha=None, v0=1.0, width=1.0, shape="gauss",
         else:
             cx, cy, mu_hl = physics.coeffs_paper_units(alpha)
     if grid == "cgl":
-        D2 = tuple(cheb.second_derivative_dirichlet(k, l) for k, l in zip(nn, LL))
-        grids = tuple(cheb.nodes(k, l) for k, l in zip(nn, LL))
+        par = (0,) * len(nn) if parity is None else tuple(parity)
+        D2, grids = [], []
+        for k, l, p in zip(nn, LL, par):
+            if p == 0:
+                D2.append(cheb.second_derivative_dirichlet(k, l))
+                grids.append(cheb.nodes(k, l))
+            else:
+                xh, Dh = cheb.parity_half(cheb.nodes(2 * k, l),
+                                          cheb.second_derivative_dirichlet(2 * k, l), p)
+                D2.append(Dh)
+                grids.append(xh)
+        D2, grids = tuple(D2), tuple(grids)
     elif grid == "mapped":
         par = (0,) * len(nn) if parity is None else tuple(parity)
         D2, grids = [], []

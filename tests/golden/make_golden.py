@@ -1,7 +1,8 @@
 """Writes the stored eigenvalue references under tests/golden/ by running the
 CPU oracle only (block JDQR with the Bartels-Stewart preconditioner, FP64).
 
-    python tests/golden/make_golden.py c2 [c3 ...]
+    python tests/golden/make_golden.py c2
+    python tests/golden/make_golden.py c3
     python tests/golden/make_golden.py c4 [--procs 8]
     python tests/golden/make_golden.py c4dense [--procs 8]
     python tests/golden/make_golden.py c5r
@@ -12,6 +13,9 @@ the file holds one line per instance: index, n, M/m, V0, w and the 4 lowest
 eigenvalues (instances solved independently in a process pool).  c4dense: for every instance
 of the batched workload with n = 64 (N = 4096) the 4 eigenvalues of smallest real
 part of the explicit Kronecker matrix (dense eigensolver, the plain definition).
+c3 (n = 1024 per mode) is computed from its four parity sectors
+(oracle.parity: each sector has n/2 unknowns per mode and is solved by the same
+block JDQR; the spectrum of H is the union of the sectors' spectra).
 c5r: the 2D workload c5 at n = 20 per mode (N = 160,000), the reduced size at
 which the oracle's four-mode preconditioned JDQR finishes in minutes."""
 import os
@@ -54,6 +58,42 @@ def run(name):
         for e, rn in zip(r.evals.real, r.resnorm):
             f.write(f"{e:.17g} {rn:.3e}\n")
     print(name, r.evals.real, r.n_outer, f"{dt:.1f}s", flush=True)
+
+
+def run_parity(name, per_sector, block):
+    from oracle import parity
+    c = config(name)
+    P = problem.make_problem(**c)
+    sig = P.two_body_shift()
+    lo = P.spectrum_lower_bound()
+    t0 = time.time()
+
+    def progress(s, outer, nlock, rn, theta):
+        print(f"  {name} sector {s} outer {outer} locked {nlock} theta0 {theta[0]:.12g} "
+              f"res0 {rn[0]:.3e} ({time.time() - t0:.0f} s)", flush=True)
+
+    ev, info = parity.lowest_by_parity(c, c["nev"], block, per_sector, sig, lo,
+                                       seed=c["seed_start"], max_outer=400, progress=progress)
+    dt = time.time() - t0
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_evals.txt")
+    with open(out, "w") as f:
+        f.write(f"# Lowest {c['nev']} eigenvalues of workload {name} "
+                f"(n={c['n']}, L={c['L']}, M/m={c['alpha']}, V0={c['v0']}, w={c['width']}),\n")
+        f.write("# computed by the CPU FP64 oracle from the four parity sectors (x, y even/odd,\n")
+        f.write(f"# n/2 unknowns per mode; block JDQR, block {block}, Bartels-Stewart preconditioner,\n")
+        f.write(f"# residual tolerance 1e-12 max(|theta|, 1)); {dt:.1f} s.\n")
+        f.write(f"# two-body shift sigma = {sig:.17g}\n")
+        for sec, evs, rns, no in info:
+            f.write(f"# sector {sec}: {len(evs)} eigenvalues, {no} outer iterations, "
+                    f"largest {evs[-1]:.17g}\n")
+        f.write("# eigenvalue sector_px sector_py resnorm\n")
+        for e in ev:
+            for sec, evs, rns, no in info:
+                hit = np.nonzero(evs == e)[0]
+                if hit.size:
+                    f.write(f"{e:.17g} {sec[0]} {sec[1]} {rns[hit[0]]:.3e}\n")
+                    break
+    print(name, ev, f"{dt:.1f}s", flush=True)
 
 
 def _c4_one(args):
@@ -142,5 +182,7 @@ if __name__ == "__main__":
             run_c4(procs)
         elif name == "c4dense":
             run_c4_dense(procs)
+        elif name == "c3":
+            run_parity("c3", {(1, 1): 10, (-1, 1): 10, (1, -1): 4, (-1, -1): 4}, 8)
         else:
             run(name)
