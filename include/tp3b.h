@@ -193,6 +193,11 @@ typedef struct {
                            smallest eigenvalue of each kinetic mode operator)
                            instead of `target`, so that a ground state far below
                            the target is not passed over (default 3; 0 = off) */
+  int32_t test_dup_column; /* testing hook (single-instance solver): at this outer
+                           iteration the second correction column is made a copy
+                           of the first before the basis is extended, which
+                           exercises the replacement of dependent columns
+                           (0 = off, the default) */
 } tp3b_jdqr_opts;
 
 typedef struct {
@@ -207,6 +212,10 @@ typedef struct {
   double t_kernel[4];
   int64_t n_kernel[4];
   int64_t v_kernel[4];
+  int32_t n_stall_lock;    /* pairs locked by the stagnation rule (opts.stall_tol)
+                              rather than by the residual tolerance */
+  int32_t n_dep_replaced;  /* dependent expansion columns replaced by random
+                              vectors */
 } tp3b_jdqr_stats;
 
 tp3b_status tp3b_jdqr_default_opts(tp3b_jdqr_opts* opts);

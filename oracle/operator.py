@@ -75,3 +75,36 @@ def kron_2d(D2, cx, cy, V):
 
     H = -cx * (embed(0, D2[0]) + embed(1, D2[1])) - cy * (embed(2, D2[2]) + embed(3, D2[3]))
     return H + np.diag(V.ravel())
+
+
+def apply_1d_at(D2x, D2y, cx, cy, V, W, idx):
+    """(H w) and (|H| |w|) at the flat indices idx of one vector W (n_x, n_y),
+    entry by entry from eq. (10): row i of D2x against column j of W, row i of W
+    against row j of D2y, and the potential term."""
+    ny = D2y.shape[0]
+    i, j = np.divmod(np.asarray(idx), ny)
+    a = cx * np.einsum("sk,sk->s", D2x[i, :], W[:, j].T)
+    b = cy * np.einsum("sk,sk->s", W[i, :], D2y[j, :])
+    vw = V[i, j] * W[i, j]
+    ref = -a - b + vw
+    scale = (cx * np.einsum("sk,sk->s", np.abs(D2x[i, :]), np.abs(W[:, j].T))
+             + cy * np.einsum("sk,sk->s", np.abs(W[i, :]), np.abs(D2y[j, :])) + np.abs(vw))
+    return ref, scale
+
+
+def apply_2d_at(D2, cx, cy, V, W, idx):
+    """(H w) and (|H| |w|) at the flat indices idx of one vector W (n1, n2, n3,
+    n4), entry by entry from eq. (8): each mode's row against the fibre of W
+    through the entry along that mode, plus the potential term."""
+    n = W.shape
+    i1, r = np.divmod(np.asarray(idx), n[1] * n[2] * n[3])
+    i2, r = np.divmod(r, n[2] * n[3])
+    j1, j2 = np.divmod(r, n[3])
+    coef = (cx, cx, cy, cy)
+    rows = (D2[0][i1, :], D2[1][i2, :], D2[2][j1, :], D2[3][j2, :])
+    fibres = (W[:, i2, j1, j2].T, W[i1, :, j1, j2], W[i1, i2, :, j2], W[i1, i2, j1, :])
+    vw = V[i1, i2, j1, j2] * W[i1, i2, j1, j2]
+    ref = vw - sum(c * np.einsum("sk,sk->s", a, f) for c, a, f in zip(coef, rows, fibres))
+    scale = np.abs(vw) + sum(c * np.einsum("sk,sk->s", np.abs(a), np.abs(f))
+                             for c, a, f in zip(coef, rows, fibres))
+    return ref, scale

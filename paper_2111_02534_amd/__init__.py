@@ -51,7 +51,7 @@ class JdqrOpts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("check_finite", ctypes.c_int32),
                 ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("stall_tol", ctypes.c_double),
-                ("low_start", ctypes.c_int32)]
+                ("low_start", ctypes.c_int32), ("test_dup_column", ctypes.c_int32)]
 
 
 class JdqrStats(ctypes.Structure):
@@ -62,7 +62,8 @@ class JdqrStats(ctypes.Structure):
                 ("t_prec", ctypes.c_double), ("t_orth", ctypes.c_double), ("t_rr", ctypes.c_double),
                 ("t_gmres", ctypes.c_double), ("t_total", ctypes.c_double),
                 ("t_kernel", ctypes.c_double * 4), ("n_kernel", ctypes.c_int64 * 4),
-                ("v_kernel", ctypes.c_int64 * 4)]
+                ("v_kernel", ctypes.c_int64 * 4), ("n_stall_lock", ctypes.c_int32),
+                ("n_dep_replaced", ctypes.c_int32)]
 
     def as_dict(self):
         out = {}
@@ -362,7 +363,7 @@ class Operator:
     def jdqr(self, nev, block, *, X0=None, inner_prec=FP64, precond=True, tol=1e-12,
              gmres_steps=10, m_min=0, m_max=0, max_outer=1000, seed=0, switch_tol=1e-2,
              target=None, verbose=False, want_Q=True, profile=False, stall_tol=1e-8,
-             low_start=3, graph=True):
+             low_start=3, graph=True, test_dup_column=0):
         import numpy as np
         import torch
         o = JdqrOpts()
@@ -373,6 +374,7 @@ class Operator:
         o.target = float("nan") if target is None else float(target)
         o.seed, o.verbose, o.profile = seed, int(verbose), int(profile)
         o.stall_tol, o.low_start, o.graph = float(stall_tol), int(low_start), int(bool(graph))
+        o.test_dup_column = int(test_dup_column)
         evals = np.empty(nev)
         R = np.empty((nev, nev), order="F")
         res = np.empty(nev)

@@ -1078,7 +1078,10 @@ tp3b_status BatchedJdqr<TW>::iterate() {
         I.stall = 0;
       I.prev_rn0 = r0;
       const int blk = I.pair[0] ? 2 : 1;
-      if (I.stall >= 3 && blk <= nb) p = blk;
+      if (I.stall >= 3 && blk <= nb) {
+        p = blk;
+        stats_.n_stall_lock += blk;
+      }
     }
     if (p > 0) {
       I.prev_rn0 = INFINITY;

@@ -32,6 +32,13 @@ struct DevOps {
   T* lam[4] = {nullptr, nullptr, nullptr, nullptr};
   T* lamItem = nullptr;  // 2D: lam_x1[i1] + lam_x2[i2] per (x1, x2) plane
   T* work = nullptr;  // preconditioner intermediate, work_vecs vectors
+  // 2D operators with every mode size <= P2_MAXN: MFMA fragments (plane2d.hip)
+  // of K_k, S_k and S_k^{-1} per mode, and the separable factors of a Gaussian
+  // potential (4 x 64 x 64, NULL for other potentials).
+  T* frK[4] = {nullptr, nullptr, nullptr, nullptr};
+  T* frS[4] = {nullptr, nullptr, nullptr, nullptr};
+  T* frSi[4] = {nullptr, nullptr, nullptr, nullptr};
+  T* G = nullptr;
 };
 
 // Runs f(i) for every i in [0, n) on up to kHostThreads host threads (the
@@ -94,6 +101,9 @@ struct tp3b_op_s {
   tp3b::DevOps<double> d64;
   tp3b::DevOps<float> d32;
   int work_vecs = 0;
+  bool plane2d = false;         // 2D with every mode size <= P2_MAXN: two-pass applies
+  std::vector<double> Gh;       // separable Gaussian factors of V (plane2d, Gaussian shapes)
+  double gscale = 0;            // -v0 for those factors
   // tile choice: explicit override, else autotuned [tp3b_prec][0 = H, 1 = prec],
   // else heuristic
   int tile_override = -1;

@@ -425,7 +425,10 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
         stall = 0;
       prev_rn0 = r0;
       const int blk = pair[0] ? 2 : 1;
-      if (stall >= 3 && blk <= nb) p = blk;
+      if (stall >= 3 && blk <= nb) {
+        p = blk;
+        stats.n_stall_lock += blk;
+      }
     }
     if (p > 0) {
       prev_rn0 = INFINITY;
@@ -623,6 +626,10 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     double to = now();
     double* Vn = QV + (int64_t)(k + m) * N;
     const uint64_t orth_seed = o.seed + 7919ull * (uint64_t)outer;
+    if (o.test_dup_column > 0 && outer == o.test_dup_column && nb > 1)
+      // testing hook: the second correction column becomes a copy of the first,
+      // so the expansion block is rank deficient
+      TP3B_HIP(hipMemcpyAsync(Tc + N, Tc, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     // queued without a round trip (the dependence flags come back with the
     // projected matrix below); reads the correction from Tc and writes Vn
     tp3b_status os = block_orth_queue(N, k + m, QV, N, nb, Vn, N, dOFlags, s, Tc);
@@ -658,7 +665,10 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
           // and A Vn and the projected entries recomputed
           if (o.verbose) fprintf(stderr, "[tp3b jdqr] outer %d: dependent expansion column replaced\n", outer);
           for (int j = 0; j < nb; ++j)
-            if (of[j]) TP3B_HIP(launch_hash_fill(N, Vn + (int64_t)j * N, orth_seed, (uint64_t)(1000 + j), s));
+            if (of[j]) {
+              TP3B_HIP(launch_hash_fill(N, Vn + (int64_t)j * N, orth_seed, (uint64_t)(1000 + j), s));
+              stats.n_dep_replaced++;
+            }
           int rank = 0;
           os = block_orth_impl(N, k + m, QV, N, nb, Vn, N, nullptr, nullptr, &rank, orth_seed, s);
           if (os != TP3B_OK) return os;

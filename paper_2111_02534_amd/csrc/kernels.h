@@ -139,9 +139,13 @@ hipError_t launch_convert(int64_t N, int ncol, double alpha, const TI* X, int64_
                           int64_t ldy, hipStream_t s);
 
 // Cholesky of the nx x nx Gram matrix G (column-major): R upper, flags[j] = 1
-// where the pivot falls below (drop_tol * norm0[j])^2.  Single thread.
+// where the pivot falls below (drop_tol * norm0[j])^2.  A flagged column gets a
+// unit pivot and a zero row, so it is left unscaled and the other columns are
+// factored as if it were absent.  skip (device, nx ints, optional): columns
+// with skip[j] != 0 are treated as flagged (the second factorisation of a
+// Cholesky-QR pair passes the first one's flags).  One wavefront.
 hipError_t launch_chol_small(int nx, const double* G, const double* norm0sq, double drop_tol,
-                             double* R, int* flags, hipStream_t s);
+                             double* R, int* flags, hipStream_t s, const int* skip = nullptr);
 // n0[j] = G[j + j nx] for j < nx (the diagonal of a Gram matrix); flag[0] = 1 if
 // any of them is not finite, 0 otherwise.  Single thread.
 hipError_t launch_gram_diag(int nx, const double* G, double* n0, int* flag, hipStream_t s);
@@ -155,5 +159,64 @@ hipError_t launch_hash_fill(int64_t N, double* X, uint64_t seed, uint64_t stream
 template <typename T>
 hipError_t launch_check_finite(int64_t N, int ncol, const T* X, int64_t ldx, int* flag,
                                hipStream_t s);
+
+}  // namespace tp3b
+
+namespace tp3b {
+
+// ------------------------------------------------ 2D passes on LDS-resident planes
+// The four-mode operators of eq. (8) act on 64 x 64 (or smaller) matrices cut
+// from the tensor: a y plane W_p[j1][j2] at fixed (x1, x2), or an x slab
+// W_j[i1][i2] at a fixed flattened y index j.  One workgroup holds a group of
+// J = 16 / sizeof(T) such matrices in LDS and applies a short program of mode
+// products to each of them with the constant n x n factors read in MFMA
+// fragment order (see plane2d_fragments), so that a whole 2D apply is two
+// passes over HBM and the 2D kinetic preconditioner three.
+//   P2_SUM        Out = A W + W B^T
+//   P2_SUM_V_ACC  Out = A W + W B^T + (V - shift_v) o W + Y   (Y read in place)
+//   P2_SEQ2       Out = (A W) B^T
+//   P2_SEQ4_DIV   Out = A2 ([(A1 W) B1^T] / (lamM[m] + lamR[r] + lamC[c] - sigma)) B2^T
+enum Plane2DProg { P2_SUM = 0, P2_SUM_V_ACC = 1, P2_SEQ2 = 2, P2_SEQ4_DIV = 3 };
+constexpr int P2_MAXN = 64;
+
+template <typename T>
+struct Plane2D {
+  int prog;         // Plane2DProg
+  int interleaved;  // 0: matrix m at m * js with rs = row stride, cs = 1 (y planes);
+                    // 1: the J matrices of a group are consecutive elements (js = 1)
+  int M, Nc;        // rows and columns of every matrix, each <= P2_MAXN
+  int64_t rs, cs, js;
+  int64_t nmat;     // matrices per vector
+  int nvec;
+  int64_t ldx, ldy;
+  const T* X;
+  T* Y;
+  const T* FA1;     // fragments of A (or A1), B (or B1), A2, B2 (P2_FRAG elements each)
+  const T* FB1;
+  const T* FA2;
+  const T* FB2;
+  // P2_SUM_V_ACC: the potential from a table in vector layout (V), or, when G is
+  // set, from separable Gaussian factors:
+  //   V = gscale (G[0][i1][r] G[2][i2][c] + G[1][i1][r] G[3][i2][c]),
+  // with i1 = m / mdiv, i2 = m % mdiv and each G[k] 64 x 64 row-major.
+  const T* V;
+  const T* G;
+  int mdiv;
+  double gscale;
+  const double* shifts;  // device, one per vector, or NULL
+  // P2_SEQ4_DIV
+  const T* lamM;
+  const T* lamR;
+  const T* lamC;
+  double sigma;
+};
+
+// Elements of one fragment array: F[(blk * 16 + kk) * 64 + lane] =
+// A[blk * 16 + lane % 16][4 kk + lane / 16], zero outside n x n.
+constexpr int P2_FRAG = 64 * 64;
+void plane2d_fragments(int n, const double* A_rowmajor, double* frag_out);
+
+template <typename T>
+hipError_t launch_plane2d(const Plane2D<T>& a, hipStream_t s);
 
 }  // namespace tp3b

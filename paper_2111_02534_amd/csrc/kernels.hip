@@ -441,7 +441,8 @@ template hipError_t launch_convert<float, float>(int64_t, int, double, const flo
 // serial form.
 __global__ __launch_bounds__(64) void k_chol_small(int nx, const double* __restrict__ G,
                                                    const double* __restrict__ n0, double drop_tol,
-                                                   double* __restrict__ R, int* __restrict__ flags) {
+                                                   double* __restrict__ R, int* __restrict__ flags,
+                                                   const int* __restrict__ skip) {
   __shared__ double Gs[TRSM_MAX * TRSM_MAX], Rs[TRSM_MAX * TRSM_MAX];
   const int t = threadIdx.x;
   for (int e = t; e < nx * nx; e += 64) {
@@ -452,8 +453,9 @@ __global__ __launch_bounds__(64) void k_chol_small(int nx, const double* __restr
   for (int j = 0; j < nx; ++j) {
     const double d = Gs[j + j * nx];
     const double thr = drop_tol * drop_tol * n0[j];
-    if (!(d > thr) || !(d > 0.0)) {
-      // dependent column: left unscaled (replaced later), contributes nothing
+    if ((skip && skip[j]) || !(d > thr) || !(d > 0.0)) {
+      // dependent column (or one a previous factorisation found dependent):
+      // left unscaled (replaced later), contributes nothing to the others
       if (t == 0) {
         flags[j] = 1;
         Rs[j + j * nx] = 1.0;
@@ -493,9 +495,10 @@ hipError_t launch_gram_diag(int nx, const double* G, double* n0, int* flag, hipS
 }
 
 hipError_t launch_chol_small(int nx, const double* G, const double* norm0sq, double drop_tol,
-                             double* R, int* flags, hipStream_t s) {
+                             double* R, int* flags, hipStream_t s, const int* skip) {
   if (nx < 1 || nx > TRSM_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, s, nx, G, norm0sq, drop_tol, R, flags);
+  hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, s, nx, G, norm0sq, drop_tol, R, flags,
+                     skip);
   return hipGetLastError();
 }
 

@@ -236,7 +236,12 @@ static void free_ops(tp3b::DevOps<T>& d) {
     for (T* p : ps)
       if (p) (void)hipFree(p);
   }
-  T* ps[] = {d.V, d.lamItem, d.work};
+  for (int k = 0; k < 4; ++k) {
+    T* fs[] = {d.frK[k], d.frS[k], d.frSi[k]};
+    for (T* p : fs)
+      if (p) (void)hipFree(p);
+  }
+  T* ps[] = {d.V, d.lamItem, d.work, d.G};
   for (T* p : ps)
     if (p) (void)hipFree(p);
   d = tp3b::DevOps<T>();
@@ -279,6 +284,20 @@ static tp3b_status upload_ops(tp3b_op op, tp3b::DevOps<T>& d, const std::vector<
     }
     if (op->ndim == 2) TP3B_HIP(upload(&d.lamItem, pf.lamItem));
     TP3B_HIP(hipMalloc((void**)&d.work, sizeof(T) * op->N * op->work_vecs));
+  }
+  if (op->plane2d) {
+    std::vector<double> F(tp3b::P2_FRAG);
+    for (int k = 0; k < op->nmodes; ++k) {
+      tp3b::plane2d_fragments(op->n[k], Kh[k].data(), F.data());
+      TP3B_HIP(upload(&d.frK[k], F));
+      if (op->have_prec) {
+        tp3b::plane2d_fragments(op->n[k], pf.S[k].data(), F.data());
+        TP3B_HIP(upload(&d.frS[k], F));
+        tp3b::plane2d_fragments(op->n[k], pf.Si[k].data(), F.data());
+        TP3B_HIP(upload(&d.frSi[k], F));
+      }
+    }
+    if (!op->Gh.empty()) TP3B_HIP(upload(&d.G, op->Gh));
   }
   return TP3B_OK;
 }
@@ -339,10 +358,44 @@ tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, in
     TP3B_HIP(modeprod(a, tile_for(op, f64, bf3, 0, a.M, a.Nc, nvec), s, bf3));
     return TP3B_OK;
   }
-  // 2D (eq. (11)): pass A applies the two y modes and the potential on every
-  // contiguous (y1, y2) plane; passes B1 and B2 accumulate the x2 and x1 modes.
   const int nx1 = op->n[0], nx2 = op->n[1], ny1 = op->n[2], ny2 = op->n[3];
   const int64_t Ny = (int64_t)ny1 * ny2;
+  if (op->plane2d && !bf3) {
+    // 2D (eq. (11)) in two passes over LDS-resident matrices: the x slabs at
+    // every y index get K_x1 W + W K_x2^T (written to Y), then the y planes at
+    // every (x1, x2) get K_y1 W + W K_y2^T + (V - s) o W added to it.
+    tp3b::Plane2D<T> p{};
+    p.prog = tp3b::P2_SUM;
+    p.interleaved = 1;
+    p.M = nx1; p.Nc = nx2;
+    p.rs = (int64_t)nx2 * Ny; p.cs = Ny; p.js = 1;
+    p.nmat = Ny;
+    p.nvec = nvec;
+    p.ldx = ldx; p.ldy = ldy;
+    p.X = X; p.Y = Y;
+    p.FA1 = d.frK[0]; p.FB1 = d.frK[1];
+    TP3B_HIP(tp3b::launch_plane2d(p, s));
+    tp3b::Plane2D<T> q{};
+    q.prog = tp3b::P2_SUM_V_ACC;
+    q.interleaved = 0;
+    q.M = ny1; q.Nc = ny2;
+    q.rs = ny2; q.cs = 1; q.js = Ny;
+    q.nmat = (int64_t)nx1 * nx2;
+    q.nvec = nvec;
+    q.ldx = ldx; q.ldy = ldy;
+    q.X = X; q.Y = Y;
+    q.FA1 = d.frK[2]; q.FB1 = d.frK[3];
+    q.V = d.V;
+    q.G = d.G;
+    q.mdiv = nx2;
+    q.gscale = op->gscale;
+    q.shifts = shifts;
+    TP3B_HIP(tp3b::launch_plane2d(q, s));
+    return TP3B_OK;
+  }
+  // 2D (eq. (11)) for larger modes: pass A applies the two y modes and the
+  // potential on every contiguous (y1, y2) plane; passes B1 and B2 accumulate
+  // the x2 and x1 modes.
   {
     ModeProd<T> a{};
     a.M = ny1;
@@ -411,6 +464,43 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
   tp3b::DevOps<T>& d = ops_for<T>(op);
   const bool f64 = sizeof(T) == 8;
   const int64_t N = op->N;
+  if (op->ndim == 2 && op->plane2d && !bf3) {
+    // (K - sigma)^{-1} = (S_x1 x S_x2 x S_y1 x S_y2) diag(1 / (sum_k lam_k - sigma))
+    // (S_x1^{-1} x ... x S_y2^{-1}) in three passes over LDS-resident matrices:
+    // x slabs S_x1^{-1} W S_x2^{-T}; y planes S_y1 ([S_y1^{-1} W S_y2^{-T}] / Lambda)
+    // S_y2^T; x slabs S_x1 W S_x2^T (the first writes Y, the others work in place).
+    const int nx1 = op->n[0], nx2 = op->n[1], ny1 = op->n[2], ny2 = op->n[3];
+    const int64_t Ny = (int64_t)ny1 * ny2;
+    tp3b::Plane2D<T> p{};
+    p.prog = tp3b::P2_SEQ2;
+    p.interleaved = 1;
+    p.M = nx1; p.Nc = nx2;
+    p.rs = (int64_t)nx2 * Ny; p.cs = Ny; p.js = 1;
+    p.nmat = Ny;
+    p.nvec = nvec;
+    p.ldx = ldx; p.ldy = ldy;
+    p.X = X; p.Y = Y;
+    p.FA1 = d.frSi[0]; p.FB1 = d.frSi[1];
+    TP3B_HIP(tp3b::launch_plane2d(p, s));
+    tp3b::Plane2D<T> q{};
+    q.prog = tp3b::P2_SEQ4_DIV;
+    q.interleaved = 0;
+    q.M = ny1; q.Nc = ny2;
+    q.rs = ny2; q.cs = 1; q.js = Ny;
+    q.nmat = (int64_t)nx1 * nx2;
+    q.nvec = nvec;
+    q.ldx = ldy; q.ldy = ldy;
+    q.X = Y; q.Y = Y;
+    q.FA1 = d.frSi[2]; q.FB1 = d.frSi[3];
+    q.FA2 = d.frS[2]; q.FB2 = d.frS[3];
+    q.lamM = d.lamItem; q.lamR = d.lam[2]; q.lamC = d.lam[3];
+    q.sigma = op->sigma;
+    TP3B_HIP(tp3b::launch_plane2d(q, s));
+    p.X = Y; p.ldx = ldy;
+    p.FA1 = d.frS[0]; p.FB1 = d.frS[1];
+    TP3B_HIP(tp3b::launch_plane2d(p, s));
+    return TP3B_OK;
+  }
   if (op->ndim == 2) {
     // (K - sigma)^{-1} = (S_1 x S_2 x S_3 x S_4) diag(1 / (sum_k lam_k - sigma))
     // (S_1^{-1} x ... x S_4^{-1}): eight single-mode products, the divide fused
@@ -550,7 +640,10 @@ tp3b_status block_orth_queue(int64_t N, int nq, const double* Q, int64_t ldq, in
   TP3B_HIP(launch_chol_small(nx, G, n0, kDropTol, R1, fl1, s));
   TP3B_HIP(launch_trsm_right(N, nx, R1, X, ldx, s));
   TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
-  TP3B_HIP(launch_chol_small(nx, G, n0, 0.0, R2, fl2, s));
+  // the second factorisation leaves the columns the first found dependent out,
+  // so the independent columns keep exactly their span (the flagged ones are
+  // replaced by the caller)
+  TP3B_HIP(launch_chol_small(nx, G, n0, 0.0, R2, fl2, s, fl1));
   TP3B_HIP(launch_trsm_right(N, nx, R2, X, ldx, s));
   return TP3B_OK;
 }
@@ -578,8 +671,9 @@ tp3b_status block_orth_impl(int64_t N, int nq, const double* Q, int64_t ldq, int
     // Without factors to return, the whole sequence is queued with one host
     // round trip at the end (block_orth_queue).  A dependent column (rare) is
     // replaced by a random vector and the general path below runs on the
-    // result; span(X) is unchanged by the triangular transforms (a dependent
-    // column only carries directions of earlier ones).
+    // result: both factorisations of the queued Cholesky-QR leave a dependent
+    // column out of the others' factors, so the independent columns come out
+    // as an orthonormal basis of exactly their own projected span.
     tp3b_status qs = block_orth_queue(N, nq, Q, ldq, nx, X, ldx, flags, s);
     if (qs != TP3B_OK) return qs;
     TP3B_HIP(hipMemcpyAsync(hflags.data(), flags, sizeof(int) * (nx + 1), hipMemcpyDeviceToHost, s));
@@ -811,6 +905,28 @@ tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* ou
               op->Vh[(((size_t)i1 * b + i2) * c + j1) * e + j2] =
                   pair_pot(op->pot, rm, op->v0, op->width) + pair_pot(op->pot, rp, op->v0, op->width);
             }
+    }
+    // 2D operators whose modes fit the LDS-resident passes; for the Gaussian
+    // shapes the potential is also kept as separable factors,
+    // exp(-|y -+ x/2|^2 s) = exp(-(y1 -+ x1/2)^2 s) exp(-(y2 -+ x2/2)^2 s).
+    if (desc->ndim == 2) {
+      op->plane2d = true;
+      for (int k = 0; k < nm; ++k) op->plane2d = op->plane2d && op->n[k] <= tp3b::P2_MAXN;
+      const bool gauss = desc->pot == TP3B_POT_GAUSS || desc->pot == TP3B_POT_GAUSS_PAPER;
+      if (op->plane2d && gauss) {
+        const double sc = desc->pot == TP3B_POT_GAUSS ? 1.0 / (2.0 * op->width * op->width) : 1.0;
+        const int P = tp3b::P2_MAXN;
+        op->Gh.assign((size_t)4 * P * P, 0.0);
+        for (int h = 0; h < 2; ++h)  // h = 0: (x1, y1) -> G[0], G[1]; h = 1: (x2, y2) -> G[2], G[3]
+          for (int i = 0; i < op->n[h]; ++i)
+            for (int j = 0; j < op->n[2 + h]; ++j) {
+              const double xi = x[h][i], yj = x[2 + h][j];
+              const double dm = yj - 0.5 * xi, dp = yj + 0.5 * xi;
+              op->Gh[(size_t)(2 * h) * P * P + (size_t)i * P + j] = std::exp(-dm * dm * sc);
+              op->Gh[(size_t)(2 * h + 1) * P * P + (size_t)i * P + j] = std::exp(-dp * dp * sc);
+            }
+        op->gscale = -op->v0;
+      }
     }
     // Scaled kinetic factors K_k = -c D2_k.
     std::vector<double> Kh[4];

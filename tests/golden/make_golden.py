@@ -6,6 +6,7 @@ CPU oracle only (block JDQR with the Bartels-Stewart preconditioner, FP64).
     python tests/golden/make_golden.py c4 [--procs 8]
     python tests/golden/make_golden.py c4dense [--procs 8]
     python tests/golden/make_golden.py c5r
+    python tests/golden/make_golden.py samples
 
 Each output file holds the nev converged eigenvalues of the named workload
 (ascending) and the oracle's final residual norms.  For the batched workload c4
@@ -17,7 +18,11 @@ c3 (n = 1024 per mode) is computed from its four parity sectors
 (oracle.parity: each sector has n/2 unknowns per mode and is solved by the same
 block JDQR; the spectrum of H is the union of the sectors' spectra).
 c5r: the 2D workload c5 at n = 20 per mode (N = 160,000), the reduced size at
-which the oracle's four-mode preconditioned JDQR finishes in minutes."""
+which the oracle's four-mode preconditioned JDQR finishes in minutes.
+samples: for the apply inputs of c2, c3 and c5 (the seeded N(0,1) blocks of
+their seed_apply, in their solve block widths), H w and |H||w| at 300 seeded
+random entries of the first and the last vector, each entry computed from the
+operator's definition (oracle.operator.apply_1d_at / apply_2d_at)."""
 import os
 import sys
 import time
@@ -94,6 +99,35 @@ def run_parity(name, per_sector, block):
                     f.write(f"{e:.17g} {sec[0]} {sec[1]} {rns[hit[0]]:.3e}\n")
                     break
     print(name, ev, f"{dt:.1f}s", flush=True)
+
+
+def run_samples(names=("c2", "c3", "c5"), count=300):
+    from oracle import operator
+    from workloads import normal_block
+    for name in names:
+        c = config(name)
+        P = problem.make_problem(**c)
+        b = c["block"]
+        X = normal_block(P.N, b, c["seed_apply"])
+        rng = np.random.Generator(np.random.PCG64(4242))
+        out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_apply_samples.txt")
+        with open(out, "w") as f:
+            f.write(f"# Samples of H w for workload {name}: w = vector v of normal_block(N={P.N}, "
+                    f"{b}, seed={c['seed_apply']}),\n")
+            f.write("# entries drawn by PCG64(4242); H w and |H||w| from the operator's "
+                    "definition (CPU FP64 oracle).\n")
+            f.write("# vector index Hw absH_absw\n")
+            for v in (0, b - 1):
+                idx = rng.integers(0, P.N, count)
+                W = X[v].reshape(P.n)
+                if P.ndim == 1:
+                    ref, sc = operator.apply_1d_at(P.D2[0], P.D2[1], P.cx, P.cy, P.V, W, idx)
+                else:
+                    ref, sc = operator.apply_2d_at(P.D2, P.cx, P.cy, P.V, W, idx)
+                for e, r, q in zip(idx, ref, sc):
+                    f.write(f"{v} {e} {r:.17g} {q:.17g}\n")
+        del X
+        print("samples", name, flush=True)
 
 
 def _c4_one(args):
@@ -182,6 +216,8 @@ if __name__ == "__main__":
             run_c4(procs)
         elif name == "c4dense":
             run_c4_dense(procs)
+        elif name == "samples":
+            run_samples()
         elif name == "c3":
             run_parity("c3", {(1, 1): 10, (-1, 1): 10, (1, -1): 4, (-1, -1): 4}, 8)
         else:

@@ -55,6 +55,52 @@ def test_block_orth_rank_deficient():
         assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(X[:, j])
 
 
+def test_block_orth_dependent_middle_column_without_factors():
+    """A dependent column followed by independent ones, queued path: the
+    independent input columns keep exactly their projected span (the dependent
+    column's rounding residue must not be orthogonalised out of the later
+    columns before it is replaced)."""
+    import torch
+    t3 = need_gpu()
+    rng = np.random.default_rng(5)
+    N = 6000
+    Q = np.linalg.qr(rng.standard_normal((N, 6)))[0]
+    X = rng.standard_normal((N, 5))
+    X[:, 1] = 3 * X[:, 0] - Q @ np.arange(6.0)
+    Xd = to_dev(X.T)
+    _, _, rk = t3.block_orth(to_dev(Q.T), Xd, want_factors=False)
+    torch.cuda.synchronize()
+    Xo = Xd.cpu().numpy().T
+    assert rk == 4
+    assert np.max(np.abs(Xo.T @ Xo - np.eye(5))) <= 1e-12
+    assert np.max(np.abs(Q.T @ Xo)) <= 1e-12
+    for j in (0, 2, 3, 4):
+        r = X[:, j] - Q @ (Q.T @ X[:, j])
+        r -= Xo @ (Xo.T @ r)
+        say("  kept column", j, np.linalg.norm(r) / np.linalg.norm(X[:, j]))
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(X[:, j])
+
+
+def test_jdqr_dependent_correction_column():
+    """The eigensolver's expansion with a rank-deficient correction block
+    (testing hook: the second correction column copies the first at outer
+    iterations 2 and 3): the dependent column is replaced, the Schur vectors stay
+    orthonormal and the eigenvalues equal the dense ones (c1)."""
+    t3 = need_gpu()
+    cfg = config("c1")
+    P = problem.make_problem(**cfg)
+    op = t3.Operator.from_config(cfg)
+    ref = dense.lowest_eigenvalues(P.kron(), cfg["nev"]).real
+    for outer in (2, 3):
+        r = op.jdqr(cfg["nev"], cfg["block"], seed=cfg["seed_start"], test_dup_column=outer)
+        Q = r.Q.cpu().numpy()
+        err = np.max(np.abs(r.evals - ref) / np.abs(ref))
+        say("dup column at", outer, "replaced", r.stats["n_dep_replaced"], "err", err)
+        assert r.stats["n_dep_replaced"] >= 1
+        assert np.max(np.abs(Q @ Q.T - np.eye(Q.shape[0]))) <= 1e-12
+        assert err <= 1e-10
+
+
 def test_block_orth_rank_deficient_without_factors():
     """Without factors the orthogonalisation runs queued with one read-back; a
     dependent column is found at the end, replaced and the block redone."""
