@@ -681,3 +681,17 @@ def test_apply_at_entries_equals_tensor_apply():
     Y2 = operator.apply_2d(D2, 0.9, 2.2, V2, W2.ravel())
     assert np.max(np.abs(ref - Y2)) <= 1e-13 * np.max(np.abs(Y2))
     assert np.all(sc >= np.abs(ref))
+
+
+def test_c4_stored_values_match_dense_at_n64():
+    """The stored eigenvalues of the batched workload (the oracle's JDQR, with
+    its steering readings) against the plain definition, dense eigenvalues of
+    the explicit Kronecker matrix, for every instance with n = 64 (N = 4096):
+    within 1e-10 relative, state by state (both files written by
+    tests/golden/make_golden.py from the oracle only)."""
+    d = np.loadtxt(os.path.join(GOLDEN, "c4_dense_n64.txt"), ndmin=2)
+    g = np.loadtxt(os.path.join(GOLDEN, "c4_evals.txt"), ndmin=2)
+    idx = d[:, 0].astype(int)
+    assert idx.size == 50 and np.all(g[idx, 1] == 64)
+    rel = np.abs(g[idx, 5:9] - d[:, 1:5]) / np.abs(d[:, 1:5])
+    assert np.max(rel) <= 1e-10, (idx[np.argmax(rel.max(axis=1))], np.max(rel))
