@@ -1,34 +1,35 @@
 #!/usr/bin/env python3
 """Benchmark of the tensor-product three-body eigensolver on one MI355X.
 
-One step is one complete block Jacobi-Davidson QR solve of the workload, from a
-seeded start block to the wanted eigenpairs at the FP64 residual tolerance: it
-runs every stage of the hot path (Hamiltonian applies with the fused potential,
-the kinetic Sylvester preconditioner, GMRES on the correction equation, FP64
-block orthogonalisation and Rayleigh-Ritz).  Operator set-up (grids, potential
-table, preconditioner eigen-factors) happens before the timed region; the start
-block is generated on the device.
+One step is one complete block Jacobi-Davidson QR solve of the 2D workload c5
+(four tensor modes, n = 64 per mode, N = 16,777,216 unknowns per vector; the
+largest workload that one GPU holds), from a seeded start block to the 6 wanted
+eigenpairs at the FP64 residual tolerance, with the 2D kinetic preconditioner:
+it runs every stage of the hot path (2D Hamiltonian applies with the fused
+potential, the preconditioner, GMRES on the correction equation, FP64 block
+orthogonalisation and Rayleigh-Ritz).  Operator set-up happens before the
+timed region; the start block is generated on the device; no step is
+PCIe-inclusive (the boundary takes device buffers).
 
-Printed: one JSON line with the solve time (value), the Hamiltonian-apply
-throughput of the dominant kernel measured with HIP events inside the timed
-solves against the FP64 MFMA peak (roofline), the eigenvalue error against the
-CPU oracle's stored values, the same solve with FP32 inner GMRES ("mixed"), the
-H apply at the precision-form grid c3 (h_apply_c3, context: n = 1024 fills the
-matrix cores where c2's n = 256 is latency-bound), the 256-instance batched
-workload (batched_c4), and the CPU oracle timed on this host (cpu_baseline).
+Printed: one JSON line with the seconds per FP64 solve (value); the same solve
+with FP32 inner GMRES (mixed); the 2D Hamiltonian apply against the FP64 MFMA
+roofline (HIP events on the library's stream, 8 vectors per apply) and the
+other applies; the H-apply error of every precision at sampled entries against
+the oracle's stored values; the eigenvalue error against the oracle at the
+reduced 2D size c5r; the 1D workloads c2 and c3 (solve times, applies, errors
+against the oracle's stored eigenvalues) and the 256-instance batch c4; and the
+CPU oracle timed on this host (cpu_baseline).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2] [--gmres-steps 3]
-
-The GMRES step count per correction equation is a solver setting, not part of
-the workload: on c2 the solve is bound by per-launch latency, and 3 steps per
-outer iteration reach the same eigenvalues in less time than the library
-default of 10 (more, cheaper outer iterations).
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--gmres-steps S]
+    python bench.py --apply-sweep c3 [--prec fp64 fp32 bf16x3]   # per-tile apply times
+    python bench.py --counters c5 --prec fp64                     # for rocprofv3 --pmc runs
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -36,123 +37,226 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "H-apply GFLOP/s (% MFMA peak); JDQR s to k eigenpairs @1e-10, mixed vs FP64"
-# HBM bytes per launch of the FP64 H apply at n = 256, 8 vectors (32 x 32 tile
-# split over eight waves, K-chunks of 64), from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE scaled by a 256 MiB copy (profiles/hbm_traffic_c2_H_apply_fp64.md):
-# 16508 KiB read + 4096 KiB written.  None for other workloads.
-TRAFFIC_BYTES = {"c2": 16508 * 1024 + 4096 * 1024}
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the 2D Hamiltonian apply at c5 (8 vectors, FP64), the
+# two plane passes together: rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by
+# what the counter reads for a 256 MiB device copy in the same run
+# (profiles/hbm_traffic_c5_H_apply_fp64.md).  None until measured for the
+# current kernels.
+TRAFFIC_BYTES = {"c5": None}
 
 
-def apply_flops(n):
-    """Algorithmic flops of one 1D Hamiltonian apply to one vector: two dense
-    mode products (2 n_x n_y (n_x + n_y)) plus the potential term (3 n_x n_y)."""
-    nx, ny = n
-    return 2.0 * nx * ny * (nx + ny) + 3.0 * nx * ny
+def apply_flops(ndim, n, kind="H"):
+    """Algorithmic flops of one apply to one vector: 2D H 8n^5 + 3n^4 (four
+    mode products of 2 n^5 each, potential 3 n^4); 1D H 4n^3 + 3n^2; 1D
+    preconditioner 8n^3 + n^2; 2D preconditioner 16 n^5 + n^4."""
+    if ndim == 2:
+        return 8.0 * n ** 5 + 3.0 * n ** 4 if kind == "H" else 16.0 * n ** 5 + 1.0 * n ** 4
+    return 4.0 * n ** 3 + 3.0 * n ** 2 if kind == "H" else 8.0 * n ** 3 + 1.0 * n ** 2
 
 
-def golden(name):
+def apply_bytes(ndim, n, es, kind="H"):
+    """Algorithmic HBM bytes per vector of the applies as implemented: 2D H in
+    two passes, read X + write Y, then read X + read Y + write Y (the Gaussian
+    potential from separable factors): 5 N es; 2D preconditioner in four passes
+    of one read and one write: 8 N es; 1D: read X (+ V), write Y."""
+    N = n ** (2 * ndim)
+    if ndim == 2:
+        return (5 if kind == "H" else 8) * N * es
+    return 3 * N * es
+
+
+def golden_evals(name):
     import numpy as np
     path = os.path.join(ROOT, "tests", "golden", f"{name}_evals.txt")
     if not os.path.exists(path):
-        return None, None
-    iters = None
-    with open(path) as f:
-        for line in f:
-            if "outer iterations" in line:
-                for tok in line.replace(";", " ").replace(",", " ").split():
-                    if tok.isdigit():
-                        iters = int(tok)
-                        break
-    return np.loadtxt(path)[:, 0], iters
+        return None
+    return np.loadtxt(path, ndmin=2)[:, 0]
 
 
-def cpu_baseline(cfg, name, sample_iters, full_iters, gmres_steps):
-    """The oracle's block JDQR on the same workload and settings, timed for its
-    first `sample_iters` outer iterations and scaled to a full solve of
-    `full_iters` outer iterations."""
+def golden_samples(name):
     import numpy as np
-    from oracle import jdqr, problem
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_apply_samples.txt")
+    if not os.path.exists(path):
+        return None
+    return np.loadtxt(path, ndmin=2)
+
+
+def rel_err(a, ref):
+    import numpy as np
+    a, ref = np.asarray(a, dtype=float), np.asarray(ref, dtype=float)
+    return float(np.max(np.abs(a - ref) / np.abs(ref)))
+
+
+def host_info():
+    model = platform.processor() or ""
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count()
-    P = problem.make_problem(**cfg)
-    pc = P.preconditioner()
-    sig = P.two_body_shift()
-    t0 = time.perf_counter()
-    r = jdqr.jdqr(P.apply, P.N, cfg["nev"], cfg["block"], precond=pc.apply,
-                  seed=cfg["seed_start"], target=sig, target_low=P.spectrum_lower_bound(),
-                  max_outer=sample_iters, gmres_steps=gmres_steps)
-    dt = time.perf_counter() - t0
-    n_done = max(r.n_outer, 1)
-    per_iter = dt / n_done
-    full = full_iters if full_iters else n_done
-    return {"value": per_iter * full, "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"first {n_done} outer iterations of the oracle's {name} solve with "
-                       f"{gmres_steps} GMRES steps per correction ({dt:.1f} s measured), scaled to "
-                       f"the {full} outer iterations of the full solve; "
-                       f"NumPy/SciPy FP64, {threads} BLAS threads")}
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
 
 
-def apply_c3_leg(reps=20):
-    """Context for the H-apply metric at the precision-form grid c3 (n = 1024,
-    16 vectors): for each precision every tile shape is timed (HIP events
-    around `reps` launches on the stream the library uses) and the fastest is
-    reported, against the MFMA peak of the precision (BF16x3: FP32-equivalent
-    flops against the 2.5 PFLOP/s dense bf16 peak divided by its three bf16
-    products per FP32 product)."""
+def time_applies(op, X, Y, prec, kind, reps):
+    """Microseconds per apply: HIP events on the stream the library launches
+    on (torch's current stream, passed to every call) around `reps` applies."""
+    import torch
+    f = op.apply_H if kind == "H" else op.apply_prec
+    f(X, Y, prec=prec)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        f(X, Y, prec=prec)
+    e1.record()
+    torch.cuda.synchronize()
+    return 1e3 * e0.elapsed_time(e1) / reps
+
+
+def sampled_apply_errors(t3, op, name, cfg, reps):
+    """H-apply error at the oracle's stored sample entries for every precision
+    (componentwise |dY| / (|H||w|)), on the seeded input block; plus the apply
+    timings on that block."""
+    import numpy as np
     import torch
 
-    import paper_2111_02534_amd as t3
-    from workloads import config
-    cfg = config("c3")
-    n, b = cfg["n"], cfg["block"]
-    op = t3.Operator.from_config(cfg)
-    out = {"workload": f"c3: 1D, n={n} (N={op.N}), {b} vectors per apply"}
-    tiles = {0: "32x32", 1: "64x64", 2: "128x128", 3: "64x128", 4: "32x32 (8 waves)"}
-    for name, pk, dt, peak in (("fp64", t3.FP64, torch.float64, PEAK_TFLOPS["f64"]),
-                               ("fp32", t3.FP32, torch.float32, PEAK_TFLOPS["f32"]),
-                               ("bf16x3", t3.BF16X3, torch.float32, 2500.0 / 3.0)):
-        X = torch.randn((b, op.N), dtype=dt, device="cuda")
+    from workloads import normal_block
+    smp = golden_samples(name)
+    b = cfg["block"]
+    Xn = normal_block(op.N, b, cfg["seed_apply"])
+    X64 = torch.from_numpy(Xn).cuda()
+    del Xn
+    out = {}
+    for pname, pk, dt in (("fp64", t3.FP64, torch.float64), ("fp32", t3.FP32, torch.float32),
+                          ("bf16x3", t3.BF16X3, torch.float32)):
+        X = X64 if dt == torch.float64 else X64.float()
         Y = torch.empty_like(X)
-        best = None
-        for tile in tiles:
-            if pk == t3.BF16X3 and tile in (0, 4):
-                continue  # runs as 64 x 64
-            op.set_tile(tile)
-            op.apply_H(X, Y, prec=pk)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
-                op.apply_H(X, Y, prec=pk)
-            e1.record()
-            torch.cuda.synchronize()
-            us = 1e3 * e0.elapsed_time(e1) / reps
-            if best is None or us < best[0]:
-                best = (us, tiles[tile])
-        op.set_tile(-1)
-        us, tile = best
-        tf = b * apply_flops((n, n)) / (us * 1e-6) / 1e12
-        out[name] = {"us_per_apply": us, "tile": tile, "tflops": tf, "peak": peak, "frac": tf / peak}
+        op.apply_H(X, Y, prec=pk)
+        torch.cuda.synchronize()
+        ent = {}
+        if smp is not None:
+            vs, idx = smp[:, 0].astype(int), smp[:, 1].astype(int)
+            got = Y[torch.from_numpy(vs).cuda(), torch.from_numpy(idx).cuda()].double().cpu().numpy()
+            ent["err_componentwise_vs_oracle"] = float(np.max(np.abs(got - smp[:, 2]) / smp[:, 3]))
+            ent["err_normwise_samples_vs_oracle"] = float(np.linalg.norm(got - smp[:, 2]) /
+                                                          np.linalg.norm(smp[:, 2]))
+            ent["samples"] = int(smp.shape[0])
+        us = time_applies(op, X, Y, pk, "H", reps)
+        tf = b * apply_flops(cfg["ndim"], cfg["n"]) / (us * 1e-6) / 1e12
+        ent.update({"us_per_apply": us, "vectors": b, "tflops": tf, "peak_tflops": PEAK_TFLOPS[pname],
+                    "frac": tf / PEAK_TFLOPS[pname]})
+        usp = time_applies(op, X, Y, pk, "P", reps)
+        tfp = b * apply_flops(cfg["ndim"], cfg["n"], "P") / (usp * 1e-6) / 1e12
+        ent["prec"] = {"us_per_apply": usp, "tflops": tfp, "frac": tfp / PEAK_TFLOPS[pname]}
+        out[pname] = ent
+        del X, Y
+    del X64
+    torch.cuda.empty_cache()
+    return out
+
+
+def solve_leg(op, cfg, inner, steps, gmres_steps, nev=None, block=None, want_Q=False):
+    import torch
+    nev = nev or cfg["nev"]
+    block = block or cfg["block"]
+    res = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res.append(op.jdqr(nev, block, inner_prec=inner, seed=cfg["seed_start"], want_Q=want_Q,
+                           gmres_steps=gmres_steps))
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / max(steps, 1), res
+
+
+def stats_brief(r):
+    st = r.stats
+    return {"outer_iters": st["n_outer"], "restarts": st["n_restart"],
+            "apply_H_vectors_fp64": st["n_apply_H_fp64"], "apply_H_vectors_low": st["n_apply_H_low"],
+            "apply_prec_vectors": st["n_apply_prec"], "stall_locked_pairs": st["n_stall_lock"],
+            "dependent_columns_replaced": st["n_dep_replaced"]}
+
+
+def c5r_leg(t3, gmres_steps):
+    """The 2D problem at n = 20 per mode against the oracle's stored eigenvalues."""
+    from workloads import config
+    cfg = config("c5r")
+    ref = golden_evals("c5r")
+    op = t3.Operator.from_config(cfg)
+    out = {"workload": f"c5r: 2D, n={cfg['n']} per mode (N={op.N}), lowest {cfg['nev']}, "
+                       f"block {cfg['block']}"}
+    for name, pk in (("fp64", t3.FP64), ("fp32_inner", t3.FP32), ("bf16x3_inner", t3.BF16X3)):
+        t0 = time.perf_counter()
+        r = op.jdqr(cfg["nev"], cfg["block"], inner_prec=pk, seed=cfg["seed_start"], want_Q=False,
+                    gmres_steps=gmres_steps, tol=cfg["tol"])
+        ent = {"s_per_solve": time.perf_counter() - t0, "outer_iters": r.stats["n_outer"],
+               "tol": cfg["tol"]}
+        if ref is not None:
+            ent["eig_max_rel_err_vs_oracle"] = rel_err(r.evals, ref)
+        out[name] = ent
     op.close()
     return out
 
 
-def batched_leg(reps, n_seq, gmres_steps):
-    """The 256-instance workload c4: one batched JDQR solve (grouped persistent
-    launches, GMRES iteration replayed as a HIP graph) per repetition, for each
-    inner precision; eigenvalues against the oracle's stored values; and the
-    first `n_seq` instances solved one by one with the single-instance solver
-    (FP32 inner) for comparison."""
+def c2_leg(t3, reps, gmres_steps):
+    from workloads import config
+    cfg = config("c2")
+    ref = golden_evals("c2")
+    op = t3.Operator.from_config(cfg)
+    out = {"workload": f"c2: 1D, n={cfg['n']} (N={op.N}), lowest {cfg['nev']}, block {cfg['block']}, "
+                       f"{gmres_steps} GMRES steps"}
+    for name, pk in (("fp64", t3.FP64), ("fp32_inner", t3.FP32)):
+        solve_leg(op, cfg, pk, 1, gmres_steps)
+        t, res = solve_leg(op, cfg, pk, reps, gmres_steps)
+        ent = {"s_per_solve": t, **stats_brief(res[-1])}
+        if ref is not None:
+            ent["eig_max_rel_err_vs_oracle"] = max(rel_err(r.evals, ref) for r in res)
+        out[name] = ent
+    out["mixed_speedup"] = out["fp64"]["s_per_solve"] / out["fp32_inner"]["s_per_solve"]
+    op.close()
+    return out
+
+
+def c3_leg(t3, gmres_steps, reps):
+    """n = 1024, 16 vectors: applies per precision with their sampled error,
+    and full solves (FP64, FP32-inner, BF16x3-inner) against the oracle."""
+    from workloads import config
+    cfg = config("c3")
+    ref = golden_evals("c3")
+    op = t3.Operator.from_config(cfg)
+    out = {"workload": f"c3: 1D, n={cfg['n']} (N={op.N}), {cfg['block']} vectors per apply; "
+                       f"lowest {cfg['nev']}, {gmres_steps} GMRES steps"}
+    out["apply"] = sampled_apply_errors(t3, op, "c3", cfg, reps)
+    for name, pk in (("fp64", t3.FP64), ("fp32_inner", t3.FP32), ("bf16x3_inner", t3.BF16X3)):
+        t, res = solve_leg(op, cfg, pk, 1, gmres_steps)
+        ent = {"s_per_solve": t, **stats_brief(res[-1])}
+        if ref is not None:
+            ent["eig_max_rel_err_vs_oracle"] = rel_err(res[-1].evals, ref)
+        out[name] = ent
+    for name in ("fp32_inner", "bf16x3_inner"):
+        out[name]["speedup_vs_fp64"] = out["fp64"]["s_per_solve"] / out[name]["s_per_solve"]
+    op.close()
+    return out
+
+
+def batched_leg(t3, reps, n_seq, gmres_steps):
+    """The 256-instance workload c4: one batched JDQR solve per repetition and
+    inner precision; eigenvalues against the oracle's stored values (plain
+    relative error |dE| / |E| per state); the first n_seq instances solved one
+    by one (FP32 inner) for comparison."""
     import numpy as np
     import torch
 
-    import paper_2111_02534_amd as t3
     from workloads import C4_TOL, c4_instances
     inst = c4_instances()
     path = os.path.join(ROOT, "tests", "golden", "c4_evals.txt")
@@ -163,24 +267,26 @@ def batched_leg(reps, n_seq, gmres_steps):
     t0 = time.perf_counter()
     for pk in (t3.FP64, t3.FP32, t3.BF16X3):
         t3.autotune_batched(ops, pk, nvec=4, reps=2)
-    t_tune = time.perf_counter() - t0
     res = {"instances": len(ops), "nev": 4, "block": 4, "gmres_steps": gmres_steps,
-           "create_s": t_create, "autotune_s": t_tune}
+           "create_s": t_create, "autotune_s": time.perf_counter() - t0}
     kw = dict(seed=1000, tol=C4_TOL, gmres_steps=gmres_steps)
     for name, pk in (("fp64", t3.FP64), ("fp32", t3.FP32), ("bf16x3", t3.BF16X3)):
-        t3.jdqr_batched(ops, 4, 4, inner_prec=pk, **kw)  # warm-up
+        t3.jdqr_batched(ops, 4, 4, inner_prec=pk, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(reps):
             r = t3.jdqr_batched(ops, 4, 4, inner_prec=pk, **kw)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t1) / reps
-        err = (float(np.max(np.abs(r.evals - gold) / np.maximum(np.abs(gold), 1.0)))
-               if gold is not None else None)
-        res[name] = {"s_per_batch": dt, "instances_per_s": len(ops) / dt,
-                     "outer_iters_max": int(r.n_outer.max()),
-                     "outer_iters_mean": float(r.n_outer.mean()),
-                     "eig_max_err_vs_oracle_rel_to_max_abs_1": err}
+        ent = {"s_per_batch": dt, "instances_per_s": len(ops) / dt,
+               "outer_iters_max": int(r.n_outer.max()), "outer_iters_mean": float(r.n_outer.mean()),
+               "stall_locked_pairs": int(r.stats["n_stall_lock"])}
+        if gold is not None:
+            rel = np.abs(r.evals - gold) / np.abs(gold)
+            ent["eig_max_rel_err_vs_oracle"] = float(rel.max())
+            ent["states_above_1e-10"] = int((rel > 1e-10).sum())
+            ent["instances_above_1e-10"] = sorted({int(i) for i in np.nonzero(rel > 1e-10)[0]})
+        res[name] = ent
     if n_seq > 0:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -197,124 +303,224 @@ def batched_leg(reps, n_seq, gmres_steps):
     return res
 
 
+def cpu_baseline(cfg, gpu_stats):
+    """The CPU oracle on this host: one 2D Hamiltonian apply and one 2D
+    preconditioner apply (Bartels-Stewart over four modes) of one vector of the
+    c5 workload, at one BLAS thread and at all of them; the solve projected from
+    the apply counts of the GPU's FP64 solve (orthogonalisation and
+    Rayleigh-Ritz left out, so the projection is a lower bound)."""
+    import numpy as np
+
+    from oracle import problem
+    from workloads import normal_block
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+        threadpool_info = None
+    model, ncpu, avail = host_info()
+    P = problem.make_problem(**cfg)
+    pc = P.preconditioner()
+    x = normal_block(P.N, 1, cfg["seed_apply"])[0]
+    out = {}
+    nthreads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1]) if threadpool_info else avail
+    for label, limit in (("1_thread", 1), ("all_threads", None)):
+        ctx = threadpool_limits(limits=limit) if (threadpool_limits and limit) else None
+        try:
+            if ctx:
+                ctx.__enter__()
+            t0 = time.perf_counter()
+            P.apply(x)
+            ta = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            pc.apply(x)
+            tp = time.perf_counter() - t0
+        finally:
+            if ctx:
+                ctx.__exit__(None, None, None)
+        out[label] = {"s_apply_H_per_vector": ta, "s_apply_prec_per_vector": tp}
+    nH = gpu_stats["apply_H_vectors_fp64"] + gpu_stats["apply_H_vectors_low"]
+    nP = gpu_stats["apply_prec_vectors"]
+    proj = {k: v["s_apply_H_per_vector"] * nH + v["s_apply_prec_per_vector"] * nP for k, v in out.items()}
+    return {"value": proj["all_threads"], "unit": "s", "cores": int(nthreads), "kind": "oracle",
+            "projected": True,
+            "sample": (f"oracle (NumPy/SciPy FP64) 2D H apply and 2D Bartels-Stewart preconditioner of "
+                       f"one c5 vector (N={P.N}), timed once each at 1 and at {nthreads} BLAS threads; "
+                       f"value = per-vector times x the {nH} H-apply and {nP} preconditioner vectors of "
+                       f"the GPU's FP64 solve (projected; orthogonalisation and Rayleigh-Ritz excluded)"),
+            "host_cpu": model, "host_cpus": ncpu, "host_cpus_available": avail,
+            "per_vector": out, "projected_s_1_thread": proj["1_thread"]}
+
+
+def apply_sweep(args):
+    """Per-tile timing of the 1D applies (set_tile), then the autotuner."""
+    import torch
+
+    import paper_2111_02534_amd as t3
+    from workloads import config
+    tiles = {0: "32x32", 1: "64x64", 2: "128x128", 3: "64x128", 4: "32x32w8"}
+    for name in args.apply_sweep:
+        cfg = config(name)
+        n, b = cfg["n"], cfg["block"]
+        op = t3.Operator.from_config(cfg)
+        print(f"== {name}: ndim={cfg['ndim']} n={n} N={op.N} block={b}", flush=True)
+        for pname, pk, dt in (("fp64", t3.FP64, torch.float64), ("fp32", t3.FP32, torch.float32),
+                              ("bf16x3", t3.BF16X3, torch.float32)):
+            if args.prec and pname not in args.prec:
+                continue
+            X = torch.randn((b, op.N), dtype=dt, device="cuda")
+            Y = torch.empty_like(X)
+            for tile, tname in tiles.items():
+                if cfg["ndim"] == 1 and tile in (1, 2, 3) and n < (64 if tile == 1 else 128):
+                    continue
+                if pk == t3.BF16X3 and tile in (0, 4):
+                    continue
+                op.set_tile(tile)
+                for kind in ("H", "P"):
+                    us = time_applies(op, X, Y, pk, kind, args.reps)
+                    tf = b * apply_flops(cfg["ndim"], n, kind) / (us * 1e-6) / 1e12
+                    print(f"  {pname} tile {tname:8s} {kind}: {us:10.1f} us {tf:8.2f} TFLOP/s "
+                          f"{100 * tf / PEAK_TFLOPS[pname]:5.1f}% of peak", flush=True)
+            op.set_tile(-1)
+            if cfg["ndim"] == 1:
+                best = op.autotune(pk, b, 5)
+                print(f"  autotuned: H {1e3 * best[0]:.1f} us, P {1e3 * best[1]:.1f} us", flush=True)
+        op.close()
+
+
+def counters(args):
+    """For hardware-counter runs: the workload's Hamiltonian apply (or, with
+    --kind P, its preconditioner) in the first listed precision, repeated
+    --reps times, then a device-to-device copy of --copy-mb MiB (the
+    calibration kernel for byte counters)."""
+    import torch
+
+    import paper_2111_02534_amd as t3
+    from workloads import config
+    pname = (args.prec or ["fp64"])[0]
+    pk = {"fp64": t3.FP64, "fp32": t3.FP32, "bf16x3": t3.BF16X3}[pname]
+    dt = torch.float64 if pname == "fp64" else torch.float32
+    for name in args.counters:
+        cfg = config(name)
+        op = t3.Operator.from_config(cfg)
+        X = torch.randn((cfg["block"], op.N), dtype=dt, device="cuda")
+        Y = torch.empty_like(X)
+        f = op.apply_H if args.kind == "H" else op.apply_prec
+        for _ in range(args.reps):
+            f(X, Y, prec=pk)
+        torch.cuda.synchronize()
+        print(f"{name} {pname} {args.kind}: {args.reps} applies of {cfg['block']} vectors, N = {op.N}; "
+              f"block {cfg['block'] * op.N * X.element_size()} bytes", flush=True)
+        op.close()
+        del X, Y
+    n = args.copy_mb * (1 << 20) // 4
+    A = torch.ones(n, dtype=torch.float32, device="cuda")
+    B = torch.empty_like(A)
+    B.copy_(A)
+    torch.cuda.synchronize()
+    print(f"copy: {n * 4} bytes read, {n * 4} bytes written", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--gmres-steps", type=int, default=5,
+                    help="GMRES steps per correction equation in the timed c5 solves")
+    ap.add_argument("--mixed-steps", type=int, default=0, help="timed mixed solves (0: steps // 2)")
+    ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--no-extras", action="store_true", help="only the c5 legs and the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=3)
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--gmres-steps", type=int, default=3,
-                    help="GMRES steps per correction equation in the timed solves")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-c3-apply", action="store_true")
-    ap.add_argument("--batched-reps", type=int, default=3)
-    ap.add_argument("--batched-seq", type=int, default=32,
-                    help="instances of the batch solved one by one for comparison")
+    ap.add_argument("--batched-reps", type=int, default=2)
+    ap.add_argument("--batched-seq", type=int, default=16)
+    ap.add_argument("--apply-sweep", nargs="*", default=None, metavar="WORKLOAD")
+    ap.add_argument("--counters", nargs="*", default=None, metavar="WORKLOAD")
+    ap.add_argument("--kind", default="H", choices=["H", "P"])
+    ap.add_argument("--prec", nargs="*", default=None)
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--copy-mb", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: the library has no multi-GPU path "
+        print(f"bench.py measures one GPU: this build has no multi-GPU path "
               f"(--gpus {args.gpus} requested); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.apply_sweep:
+        return apply_sweep(args)
+    if args.counters:
+        return counters(args)
 
-    import numpy as np
     import torch
 
     import paper_2111_02534_amd as t3
     from workloads import config
 
     torch.cuda.init()
-    cfg = config(args.config)
-    nev, b = cfg["nev"], cfg["block"]
+    cfg = config("c5")
+    nev, b, n = cfg["nev"], cfg["block"], cfg["n"]
     op = t3.Operator.from_config(cfg)
-    n = (cfg["n"], cfg["n"])
-    ref, _ = golden(args.config)
+    gs = args.gmres_steps
 
-    def solve(inner, profile=False):
-        return op.jdqr(nev, b, inner_prec=inner, seed=cfg["seed_start"], want_Q=False,
-                       profile=profile, gmres_steps=args.gmres_steps)
+    # ---- the timed FP64 solves (the step)
+    if args.warmup > 0:
+        solve_leg(op, cfg, t3.FP64, args.warmup, gs)
+    s_fp64, res = solve_leg(op, cfg, t3.FP64, args.steps, gs)
+    fp64_stats = stats_brief(res[-1])
+    # ---- the same solve with FP32 inner GMRES
+    msteps = args.mixed_steps or max(1, args.steps // 2)
+    solve_leg(op, cfg, t3.FP32, 1, gs)
+    s_mixed, mres = solve_leg(op, cfg, t3.FP32, msteps, gs)
+    agree = max(rel_err(r.evals, res[-1].evals) for r in mres)
 
-    for _ in range(args.warmup):
-        solve(t3.FP64)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = []
-    for _ in range(args.steps):
-        res.append(solve(t3.FP64, profile=True))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    s_per_solve = elapsed / args.steps
-
-    # Dominant kernel: the FP64 Hamiltonian apply (b vectors per launch).  The
-    # events bracket the launches made outside the replayed GMRES graph (the
-    # applies that extend the search space), which run the same kernel on the
-    # same block width.
-    t_k = sum(r.stats["t_kernel"][0] for r in res)
-    n_k = sum(r.stats["n_kernel"][0] for r in res)
-    n_vec = sum(r.stats["v_kernel"][0] for r in res)
-    vec_per_launch = n_vec / max(n_k, 1)
-    flops_launch = vec_per_launch * apply_flops(n)
-    avg_launch_s = t_k / max(n_k, 1)
-    achieved_tf = flops_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
-    t_prec = sum(r.stats["t_kernel"][2] for r in res)
-    err = None
-    if ref is not None:
-        err = float(max(np.max(np.abs(r.evals - ref) / np.abs(ref)) for r in res))
+    # ---- applies: roofline of the Hamiltonian apply, sampled errors
+    applies = sampled_apply_errors(t3, op, "c5", cfg, args.apply_reps)
+    h64 = applies["fp64"]
+    launch_flops = b * apply_flops(2, n)
+    achieved = launch_flops / (h64["us_per_apply"] * 1e-6) / 1e12
+    op.close()
+    torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC,
-        "value": s_per_solve,
+        "value": s_fp64,
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * s_per_solve,
+        "ms_per_step": 1e3 * s_fp64,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": (f"{args.config}: 1D three-body, n={cfg['n']} per Jacobi coordinate "
-                                f"(N={op.N}), M/m={cfg['alpha']}, Gaussian V0={cfg['v0']}, "
-                                f"w={cfg['width']}, lowest {nev} eigenpairs, block {b}, "
-                                f"FP64 JDQR + Sylvester preconditioner, "
-                                f"{args.gmres_steps} GMRES steps per correction"),
-                   "n": cfg["n"], "nev": nev, "block": b, "gmres_steps": args.gmres_steps},
-        "roofline": {"bound": "mfma", "achieved": achieved_tf, "peak": PEAK_TFLOPS["f64"],
-                     "unit": "TFLOP/s", "frac": achieved_tf / PEAK_TFLOPS["f64"],
-                     "traffic": TRAFFIC_BYTES.get(args.config),
-                     "kernel": "k_modeprod_sk8<double, 0> (H apply, fused potential)",
-                     "launch_flops": flops_launch, "avg_launch_us": 1e6 * avg_launch_s,
-                     "launches": n_k},
-        "h_apply_gflops": achieved_tf * 1e3,
-        "jdqr": {"s_per_solve": s_per_solve, "outer_iters": res[-1].stats["n_outer"],
-                 "apply_H_vectors": res[-1].stats["n_apply_H_fp64"],
-                 "apply_prec_vectors": res[-1].stats["n_apply_prec"],
-                 "kernel_time_frac_H": t_k / elapsed, "kernel_time_frac_prec": t_prec / elapsed,
-                 "eig_max_rel_err_vs_oracle": err},
+        "config": {"workload": (f"c5: 2D three-body (four tensor modes), n={n} per mode "
+                                f"(N={16777216} per vector), M/m={cfg['alpha']}, Gaussian V0={cfg['v0']}, "
+                                f"w={cfg['width']}, lowest {nev} eigenpairs, block {b}, FP64 JDQR with "
+                                f"the 2D kinetic preconditioner, {gs} GMRES steps per correction"),
+                   "n": n, "nev": nev, "block": b, "gmres_steps": gs},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["fp64"],
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp64"],
+                     "traffic": TRAFFIC_BYTES.get("c5"),
+                     "kernel": ("2D Hamiltonian apply, FP64: k_plane2d<double, P2_SUM> (x slabs) + "
+                                "k_plane2d<double, P2_SUM_V_ACC> (y planes with the potential)"),
+                     "launch_flops": launch_flops, "avg_launch_us": h64["us_per_apply"],
+                     "algorithmic_bytes": b * apply_bytes(2, n, 8),
+                     "achieved_GBs": b * apply_bytes(2, n, 8) / (h64["us_per_apply"] * 1e-6) / 1e9},
+        "h_apply_gflops": achieved * 1e3,
+        "jdqr": {"s_per_solve": s_fp64, **fp64_stats,
+                 "eig_agreement_fp64_vs_mixed": agree},
+        "mixed_vs_fp64": {"fp64_s": s_fp64, "mixed_s": s_mixed, "speedup": s_fp64 / s_mixed,
+                          "mixed_outer_iters": mres[-1].stats["n_outer"],
+                          "eig_max_rel_diff_vs_fp64": agree},
+        "applies_c5": applies,
     }
-    if not args.no_mixed:
-        solve(t3.FP32)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        mres = [solve(t3.FP32) for _ in range(max(1, args.steps // 2))]
-        torch.cuda.synchronize()
-        m_s = (time.perf_counter() - t1) / len(mres)
-        m_err = None
-        if ref is not None:
-            m_err = float(max(np.max(np.abs(r.evals - ref) / np.abs(ref)) for r in mres))
-        out["mixed_vs_fp64"] = {"fp64_s": s_per_solve, "mixed_s": m_s, "speedup": s_per_solve / m_s,
-                                "mixed_outer_iters": mres[-1].stats["n_outer"],
-                                "mixed_eig_max_rel_err_vs_oracle": m_err}
-    if not args.no_c3_apply:
-        out["h_apply_c3"] = apply_c3_leg()
-    if not args.no_batched:
-        out["batched_c4"] = batched_leg(args.batched_reps, args.batched_seq, args.gmres_steps)
+    out["c5r_vs_oracle"] = c5r_leg(t3, gs)
+    if not args.no_extras:
+        out["c2"] = c2_leg(t3, max(3, args.steps), 3)
+        out["c3"] = c3_leg(t3, 10, args.apply_reps)
+        out["batched_c4"] = batched_leg(t3, args.batched_reps, args.batched_seq, 3)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.config, args.cpu_sample_iters,
-                                           res[-1].stats["n_outer"], args.gmres_steps)
+        out["cpu_baseline"] = cpu_baseline(cfg, fp64_stats)
     print(json.dumps(out), flush=True)
 
 

@@ -171,12 +171,13 @@ namespace tp3b {
 // J = 16 / sizeof(T) such matrices in LDS and applies a short program of mode
 // products to each of them with the constant n x n factors read in MFMA
 // fragment order (see plane2d_fragments), so that a whole 2D apply is two
-// passes over HBM and the 2D kinetic preconditioner three.
+// passes over HBM and the 2D kinetic preconditioner four.
 //   P2_SUM        Out = A W + W B^T
 //   P2_SUM_V_ACC  Out = A W + W B^T + (V - shift_v) o W + Y   (Y read in place)
 //   P2_SEQ2       Out = (A W) B^T
-//   P2_SEQ4_DIV   Out = A2 ([(A1 W) B1^T] / (lamM[m] + lamR[r] + lamC[c] - sigma)) B2^T
-enum Plane2DProg { P2_SUM = 0, P2_SUM_V_ACC = 1, P2_SEQ2 = 2, P2_SEQ4_DIV = 3 };
+//   P2_SEQ2_DIV   Out = [(A W) B^T] / (lamM[m] + lamR[r] + lamC[c] - sigma)
+// Matrices that are x slabs (interleaved layout) take P2_SUM and P2_SEQ2.
+enum Plane2DProg { P2_SUM = 0, P2_SUM_V_ACC = 1, P2_SEQ2 = 2, P2_SEQ2_DIV = 3 };
 constexpr int P2_MAXN = 64;
 
 template <typename T>
@@ -191,10 +192,8 @@ struct Plane2D {
   int64_t ldx, ldy;
   const T* X;
   T* Y;
-  const T* FA1;     // fragments of A (or A1), B (or B1), A2, B2 (P2_FRAG elements each)
+  const T* FA1;     // fragments of A and B (P2_FRAG elements each)
   const T* FB1;
-  const T* FA2;
-  const T* FB2;
   // P2_SUM_V_ACC: the potential from a table in vector layout (V), or, when G is
   // set, from separable Gaussian factors:
   //   V = gscale (G[0][i1][r] G[2][i2][c] + G[1][i1][r] G[3][i2][c]),
@@ -204,7 +203,7 @@ struct Plane2D {
   int mdiv;
   double gscale;
   const double* shifts;  // device, one per vector, or NULL
-  // P2_SEQ4_DIV
+  // P2_SEQ2_DIV
   const T* lamM;
   const T* lamR;
   const T* lamC;

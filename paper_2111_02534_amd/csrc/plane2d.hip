@@ -10,19 +10,18 @@
 //   Hamiltonian     pass 1 (x slabs): Y = K_x1 W + W K_x2^T
 //                   pass 2 (y planes): Y = K_y1 W + W K_y2^T + (V - s) o W + Y
 //   preconditioner  pass 1 (x slabs): Y = S_x1^{-1} W S_x2^{-T}
-//                   pass 2 (y planes): Y = S_y1 ([S_y1^{-1} W S_y2^{-T}] / Lambda) S_y2^T
-//                   pass 3 (x slabs): Y = S_x1 W S_x2^T
+//                   pass 2 (y planes): Y = [S_y1^{-1} W S_y2^{-T}] / Lambda
+//                   pass 3 (y planes): Y = S_y1 W S_y2^T
+//                   pass 4 (x slabs): Y = S_x1 W S_x2^T
 // (the mode operators of different modes commute, so the eigenbasis divide by
 // Lambda = lam_x1 + lam_x2 + lam_y1 + lam_y2 - sigma can sit between the y
 // transforms).  HBM traffic is one read and one write per pass (plus the read
 // of the x part in the Hamiltonian's second pass), 40 B per entry for the FP64
-// Hamiltonian instead of 72 B for three single-mode passes.
+// Hamiltonian instead of 72 B for three single-mode passes, 64 B for the
+// preconditioner instead of 128 B for eight.
 //
-// The constant factors are read from global memory (L2-resident, 32 KB each in
-// FP64) in MFMA fragment order, one coalesced 512-byte load per fragment.
-// Work split: wave w of the 256-thread workgroup computes output row block w
-// (rows 16w .. 16w + 15) of every matrix of the group; its accumulators hold
-// 4 column blocks x J matrices.
+// Every pass applies two constant n x n factors, held in LDS in MFMA fragment
+// order (32 KB each in FP64) next to the work item (J matrices, 65 KB).
 #include <hip/hip_runtime.h>
 
 #include "device_bodies.h"
@@ -41,277 +40,452 @@ void plane2d_fragments(int n, const double* A, double* F) {
 
 template <typename T>
 struct P2Shape {
-  static constexpr int J = 16 / (int)sizeof(T);  // matrices per workgroup
+  static constexpr int J = 16 / (int)sizeof(T);  // matrices per work item
+  static constexpr int JW = J / 2;               // matrices per wave
   static constexpr int LD = P2_MAXN + 1;         // padded LDS row
+  static constexpr int NT = 512;                 // threads per workgroup
+  static constexpr int CH = P2_MAXN * P2_MAXN;   // 16-byte chunks of J elements per item
+  static constexpr int PER = CH / NT;            // chunks per thread
 };
 
-// acc[jj][bj] += A(row block w) * W_jj(:, column block bj)
+template <typename T>
+using P2Buf = T[P2Shape<T>::J][P2_MAXN][P2Shape<T>::LD];
+template <typename T>
+using P2Acc = typename Mma<T>::acc_t[P2Shape<T>::JW][4];
+
+// acc[j][bj] += A(row block bi) * W_{j0 + j}(:, column block bj); A in fragment
+// order in LDS
 template <typename T, bool FULL>
-__device__ __forceinline__ void p2_left(typename Mma<T>::acc_t (&acc)[P2Shape<T>::J][4],
-                                        const T* __restrict__ FA,
-                                        T (&w)[P2Shape<T>::J][P2_MAXN][P2Shape<T>::LD], int wave,
-                                        int lane, int KA, int BN) {
-  constexpr int J = P2Shape<T>::J;
+__device__ __forceinline__ void p2_left(P2Acc<T>& acc, const T* FA, const P2Buf<T>& w, int j0,
+                                        int bi, int lane, int KA, int BN) {
+  constexpr int JW = P2Shape<T>::JW;
   const int lr = lane & 15, lk = lane >> 4;
-  const T* fa = FA + (wave * 16) * 64 + lane;
-  const int kend = FULL ? 16 : KA;
-  T af_next = fa[0];
 #pragma unroll 4
-  for (int kk = 0; kk < kend; ++kk) {
-    const T af = af_next;
-    if (kk + 1 < kend) af_next = fa[(kk + 1) * 64];
+  for (int kk = 0; kk < (FULL ? 16 : KA); ++kk) {
+    const T af = FA[(bi * 16 + kk) * 64 + lane];
 #pragma unroll
-    for (int jj = 0; jj < J; ++jj)
+    for (int j = 0; j < JW; ++j)
 #pragma unroll
       for (int bj = 0; bj < 4; ++bj)
-        if (FULL || bj < BN) {
-          const T bf = w[jj][4 * kk + lk][bj * 16 + lr];
-          acc[jj][bj] = Mma<T>::mma(af, bf, acc[jj][bj]);
-        }
+        if (FULL || bj < BN)
+          acc[j][bj] = Mma<T>::mma(af, w[j0 + j][4 * kk + lk][bj * 16 + lr], acc[j][bj]);
   }
 }
 
-// acc[jj][bj] += W_jj(row block w, :) * B^T(:, column block bj)
+// acc[j][bj] += W_{j0 + j}(row block bi, :) * B^T(:, column block bj)
 template <typename T, bool FULL>
-__device__ __forceinline__ void p2_right(typename Mma<T>::acc_t (&acc)[P2Shape<T>::J][4],
-                                         const T* __restrict__ FB,
-                                         T (&w)[P2Shape<T>::J][P2_MAXN][P2Shape<T>::LD], int wave,
-                                         int lane, int KB, int BN) {
-  constexpr int J = P2Shape<T>::J;
+__device__ __forceinline__ void p2_right(P2Acc<T>& acc, const T* FB, const P2Buf<T>& w, int j0,
+                                         int bi, int lane, int KB, int BN) {
+  constexpr int JW = P2Shape<T>::JW;
   const int lr = lane & 15, lk = lane >> 4;
-  const int kend = FULL ? 16 : KB;
-  T bn[4];
+#pragma unroll 4
+  for (int kk = 0; kk < (FULL ? 16 : KB); ++kk) {
+    T a[JW];
 #pragma unroll
-  for (int bj = 0; bj < 4; ++bj) bn[bj] = (FULL || bj < BN) ? FB[(bj * 16) * 64 + lane] : T(0);
-#pragma unroll 2
-  for (int kk = 0; kk < kend; ++kk) {
-    T bf[4];
+    for (int j = 0; j < JW; ++j) a[j] = w[j0 + j][bi * 16 + lr][4 * kk + lk];
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) bf[bj] = bn[bj];
-    if (kk + 1 < kend) {
+    for (int bj = 0; bj < 4; ++bj)
+      if (FULL || bj < BN) {
+        const T bf = FB[(bj * 16 + kk) * 64 + lane];
 #pragma unroll
-      for (int bj = 0; bj < 4; ++bj)
-        if (FULL || bj < BN) bn[bj] = FB[(bj * 16 + kk + 1) * 64 + lane];
+        for (int j = 0; j < JW; ++j) acc[j][bj] = Mma<T>::mma(a[j], bf, acc[j][bj]);
+      }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void p2_zero(P2Acc<T>& acc) {
+#pragma unroll
+  for (int j = 0; j < P2Shape<T>::JW; ++j)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[j][bj] = typename Mma<T>::acc_t{0, 0, 0, 0};
+}
+
+// Chunk q of a work item (J elements that are contiguous in memory):
+//   interleaved (x slabs): position (r, c) = (q / 64, q % 64), element t is
+//                          matrix m0 + t;
+//   planes:                matrix jj = q / (64 * 64 / J), row r, columns
+//                          c0 .. c0 + J - 1.
+template <typename T, bool INTERLEAVED>
+__device__ __forceinline__ void p2_chunk(int q, int& jj, int& r, int& c0) {
+  constexpr int J = P2Shape<T>::J;
+  if (INTERLEAVED) {
+    jj = 0;
+    r = q / P2_MAXN;
+    c0 = q % P2_MAXN;
+  } else {
+    constexpr int CPR = P2_MAXN / J;  // chunks per row
+    jj = q / (P2_MAXN * CPR);
+    r = (q / CPR) % P2_MAXN;
+    c0 = (q % CPR) * J;
+  }
+}
+
+template <typename T>
+struct P2Vec;
+template <>
+struct P2Vec<double> {
+  typedef double2 v;
+  static __device__ __forceinline__ double get(const v& x, int t) { return t == 0 ? x.x : x.y; }
+  static __device__ __forceinline__ void set(v& x, int t, double e) {
+    if (t == 0) x.x = e; else x.y = e;
+  }
+};
+template <>
+struct P2Vec<float> {
+  typedef float4 v;
+  static __device__ __forceinline__ float get(const v& x, int t) {
+    return t == 0 ? x.x : (t == 1 ? x.y : (t == 2 ? x.z : x.w));
+  }
+  static __device__ __forceinline__ void set(v& x, int t, float e) {
+    if (t == 0) x.x = e; else if (t == 1) x.y = e; else if (t == 2) x.z = e; else x.w = e;
+  }
+};
+
+// Global offset of element t of chunk (jj, r, c0) of the item starting at
+// matrix m0, and whether it exists.
+template <typename T, bool INTERLEAVED, bool FULL>
+__device__ __forceinline__ bool p2_elem(const Plane2D<T>& a, int64_t m0, int jj, int r, int c0, int t,
+                                        int64_t& off) {
+  int64_t m;
+  int c;
+  if (INTERLEAVED) {
+    m = m0 + t;
+    c = c0;
+  } else {
+    m = m0 + jj;
+    c = c0 + t;
+  }
+  off = m * a.js + (int64_t)r * a.rs + (int64_t)c * a.cs;
+  return FULL ? (m < a.nmat) : (m < a.nmat && r < a.M && c < a.Nc);
+}
+
+template <typename T, bool INTERLEAVED, bool FULL, bool VEC>
+__device__ __forceinline__ void p2_fetch(const Plane2D<T>& a, const T* X, int64_t m0, int tid,
+                                         typename P2Vec<T>::v (&buf)[P2Shape<T>::PER]) {
+  constexpr int J = P2Shape<T>::J;
+#pragma unroll
+  for (int u = 0; u < P2Shape<T>::PER; ++u) {
+    int jj, r, c0;
+    p2_chunk<T, INTERLEAVED>(tid + u * P2Shape<T>::NT, jj, r, c0);
+    int64_t off;
+    const bool ok0 = p2_elem<T, INTERLEAVED, FULL>(a, m0, jj, r, c0, 0, off);
+    if (VEC) {
+      // the whole chunk exists when its first element does (checked on the host)
+      if (ok0) {
+        buf[u] = *(const typename P2Vec<T>::v*)(X + off);
+      } else {
+#pragma unroll
+        for (int t = 0; t < J; ++t) P2Vec<T>::set(buf[u], t, T(0));
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < J; ++t) {
+        int64_t o;
+        const bool ok = p2_elem<T, INTERLEAVED, FULL>(a, m0, jj, r, c0, t, o);
+        P2Vec<T>::set(buf[u], t, ok ? X[o] : T(0));
+      }
     }
+  }
+}
+
+template <typename T, bool INTERLEAVED>
+__device__ __forceinline__ void p2_put(P2Buf<T>& w, int tid,
+                                       const typename P2Vec<T>::v (&buf)[P2Shape<T>::PER]) {
+  constexpr int J = P2Shape<T>::J;
 #pragma unroll
-    for (int jj = 0; jj < J; ++jj) {
-      const T af = w[jj][wave * 16 + lr][4 * kk + lk];
+  for (int u = 0; u < P2Shape<T>::PER; ++u) {
+    int jj, r, c0;
+    p2_chunk<T, INTERLEAVED>(tid + u * P2Shape<T>::NT, jj, r, c0);
 #pragma unroll
-      for (int bj = 0; bj < 4; ++bj)
-        if (FULL || bj < BN) acc[jj][bj] = Mma<T>::mma(af, bf[bj], acc[jj][bj]);
+    for (int t = 0; t < J; ++t) {
+      if (INTERLEAVED) w[t][r][c0] = P2Vec<T>::get(buf[u], t);
+      else w[jj][r][c0 + t] = P2Vec<T>::get(buf[u], t);
     }
   }
 }
 
 template <typename T>
-__device__ __forceinline__ void p2_zero(typename Mma<T>::acc_t (&acc)[P2Shape<T>::J][4]) {
-#pragma unroll
-  for (int jj = 0; jj < P2Shape<T>::J; ++jj)
-#pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[jj][bj] = typename Mma<T>::acc_t{0, 0, 0, 0};
-}
+struct P2Smem {
+  P2Buf<T> w;                 // the current work item
+  T fa[P2_FRAG], fb[P2_FRAG];  // the two constant factors, fragment order
+};
 
-// Element (jj, r, c) of a group: matrix m0 + jj, row r, column c.
-template <bool INTERLEAVED, int J>
-__device__ __forceinline__ void p2_index(int e, int& jj, int& r, int& c) {
-  if (INTERLEAVED) {
-    jj = e % J;
-    c = (e / J) % P2_MAXN;
-    r = e / (J * P2_MAXN);
-  } else {
-    c = e % P2_MAXN;
-    r = (e / P2_MAXN) % P2_MAXN;
-    jj = e / (P2_MAXN * P2_MAXN);
-  }
-}
-
-template <typename T, int PROG, bool INTERLEAVED, bool FULL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_plane2d(
+// Persistent workgroups of 512 threads (eight waves, two per SIMD), one per
+// CU.  The two constant factors of the pass are copied to LDS once.  Work
+// items are the groups of J matrices of every vector; the items of XCD
+// x = blockIdx % 8 are the contiguous range [x T / 8, (x + 1) T / 8), taken in
+// turn by that XCD's workgroups, so that neighbouring items (which share cache
+// lines in the interleaved layout) run together on one L2.  While item i is
+// multiplied out of LDS, item i + 1 is fetched into registers; it is stored
+// into LDS once item i has been written out.  Wave w computes row block w % 4
+// of matrices (w / 4) * JW .. (w / 4 + 1) * JW - 1.
+template <typename T, int PROG, bool INTERLEAVED, bool FULL, bool VEC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_plane2d(
     Plane2D<T> a) {
-  constexpr int J = P2Shape<T>::J;
-  constexpr int NE = J * P2_MAXN * P2_MAXN;  // elements of a group
-  constexpr int UNR = 8;
-  static_assert(NE % (256 * UNR) == 0, "group not divisible among the threads");
-  __shared__ T w[J][P2_MAXN][P2Shape<T>::LD];
-  typedef typename Mma<T>::acc_t acc_t;
+  typedef P2Shape<T> S;
+  constexpr int J = S::J, JW = S::JW;
+  typedef typename P2Vec<T>::v vec_t;
+  __shared__ P2Smem<T> sm;
+  P2Buf<T>& w = sm.w;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t groups = (a.nmat + J - 1) / J;
-  const int64_t item = xcd_remap(blockIdx.x, groups * a.nvec);
-  const int64_t v = item / groups, m0 = (item - v * groups) * J;
+  const int bi = wave & 3, j0 = (wave >> 2) * JW;
+  const int lr = lane & 15, lk = lane >> 4;
   const int M = a.M, Nc = a.Nc;
-  // no __restrict__: the preconditioner's second and third passes work in place
-  // (each workgroup reads all of its matrices before it writes any of them)
-  const T* X = a.X + v * a.ldx;
-  T* Y = a.Y + v * a.ldy;
+  const int BM = FULL ? 4 : (M + 15) / 16, BN = FULL ? 4 : (Nc + 15) / 16;
+  const int KA = FULL ? 16 : (M + 3) / 4, KB = FULL ? 16 : (Nc + 3) / 4;
+  const bool active = bi < BM;
 
-  // ---- load the group (zero outside M x Nc and past the last matrix)
-  for (int e0 = tid; e0 < NE; e0 += 256 * UNR) {
-    T val[UNR];
+  const int64_t groups = (a.nmat + J - 1) / J;
+  const int64_t total = groups * a.nvec;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int nslot = (int)((gridDim.x - xcd + 7) >> 3);
+  const int64_t lo = (int64_t)xcd * total / 8, hi = (int64_t)(xcd + 1) * total / 8;
+
+  for (int e = tid; e < P2_FRAG; e += S::NT) {
+    sm.fa[e] = a.FA1[e];
+    sm.fb[e] = a.FB1[e];
+  }
+  // the divide's row and column eigenvalues of this lane's output elements
+  // (the same for every item)
+  T lamr[4], lamc[4];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      int jj, r, c;
-      p2_index<INTERLEAVED, J>(e0 + u * 256, jj, r, c);
-      const int64_t m = m0 + jj;
-      const bool ok = FULL ? (m < a.nmat) : (r < M && c < Nc && m < a.nmat);
-      val[u] = ok ? X[m * a.js + r * a.rs + c * a.cs] : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      int jj, r, c;
-      p2_index<INTERLEAVED, J>(e0 + u * 256, jj, r, c);
-      w[jj][r][c] = val[u];
-    }
+  for (int q = 0; q < 4; ++q) {
+    const int r = bi * 16 + Mma<T>::row(lk, q), c = q * 16 + lr;
+    lamr[q] = (PROG == P2_SEQ2_DIV && r < M) ? a.lamR[r] : T(0);
+    lamc[q] = (PROG == P2_SEQ2_DIV && c < Nc) ? a.lamC[c] : T(0);
+  }
+  vec_t pre[S::PER];
+  int64_t item = lo + slot;
+  if (item < hi) {
+    const int64_t v = item / groups, m0 = (item - v * groups) * J;
+    p2_fetch<T, INTERLEAVED, FULL, VEC>(a, a.X + v * a.ldx, m0, tid, pre);
+    p2_put<T, INTERLEAVED>(w, tid, pre);
   }
   __syncthreads();
 
-  const int BM = FULL ? 4 : (M + 15) / 16, BN = FULL ? 4 : (Nc + 15) / 16;
-  const int KA = FULL ? 16 : (M + 3) / 4, KB = FULL ? 16 : (Nc + 3) / 4;
-  const bool active = wave < BM;
-  const int lr = lane & 15, lk = lane >> 4;
-  acc_t acc[J][4];
-  p2_zero<T>(acc);
-
-  // accumulators -> LDS (optionally divided by the eigenvalue sums)
-  auto to_lds = [&](bool divide) {
-    __syncthreads();  // every wave has finished reading the previous contents
-    if (active) {
+  for (; item < hi; item += nslot) {
+    const int64_t v = item / groups, m0 = (item - v * groups) * J;
+    const int64_t nxt = item + nslot;
+    if (nxt < hi) {
+      const int64_t v2 = nxt / groups, m2 = (nxt - v2 * groups) * J;
+      p2_fetch<T, INTERLEAVED, FULL, VEC>(a, a.X + v2 * a.ldx, m2, tid, pre);
+    }
+    T* Y = a.Y + v * a.ldy;
+    // the epilogue's global operands, read before the products so that their
+    // latency is hidden: the x part of the Hamiltonian (Y in place) and the
+    // potential's separable factors
+    T tacc[JW][4][4], g1[JW][2][4], g2[JW][2][4];
+    if (PROG == P2_SUM_V_ACC && active) {
 #pragma unroll
-      for (int jj = 0; jj < J; ++jj)
+      for (int j = 0; j < JW; ++j) {
+        const int64_t m = m0 + j0 + j;
+        const int md = a.mdiv > 0 ? a.mdiv : 1;
+        const int i1 = (int)(m / md), i2 = (int)(m % md);
+        const bool mok = m < a.nmat;
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int r = wave * 16 + Mma<T>::row(lk, q), c = bj * 16 + lr;
-            T val = acc[jj][bj][q];
-            if (divide) {
-              const int64_t m = m0 + jj;
-              const bool ok = r < M && c < Nc && m < a.nmat;
-              val = ok ? val / (a.lamM[m] + a.lamR[r] + a.lamC[c] - T(a.sigma)) : T(0);
-            }
-            w[jj][r][c] = val;
+            const int r = bi * 16 + Mma<T>::row(lk, q), c = bj * 16 + lr;
+            const bool ok = mok && (FULL || (r < M && c < Nc));
+            tacc[j][bj][q] = ok ? Y[m * a.js + (int64_t)r * a.rs + c] : T(0);
           }
+        if (a.G) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = bi * 16 + Mma<T>::row(lk, q);
+            g1[j][0][q] = mok ? a.G[i1 * P2_MAXN + r] : T(0);
+            g1[j][1][q] = mok ? a.G[P2_MAXN * P2_MAXN + i1 * P2_MAXN + r] : T(0);
+          }
+#pragma unroll
+          for (int bj = 0; bj < 4; ++bj) {
+            const int c = bj * 16 + lr;
+            g2[j][0][bj] = mok ? a.G[2 * P2_MAXN * P2_MAXN + i2 * P2_MAXN + c] : T(0);
+            g2[j][1][bj] = mok ? a.G[3 * P2_MAXN * P2_MAXN + i2 * P2_MAXN + c] : T(0);
+          }
+        }
+      }
+    }
+    P2Acc<T> acc;
+    p2_zero<T>(acc);
+    if (active) p2_left<T, FULL>(acc, sm.fa, w, j0, bi, lane, KA, BN);
+    if (PROG == P2_SEQ2 || PROG == P2_SEQ2_DIV) {
+      // A W -> LDS, then (A W) B^T
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int j = 0; j < JW; ++j)
+#pragma unroll
+          for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              w[j0 + j][bi * 16 + Mma<T>::row(lk, q)][bj * 16 + lr] = acc[j][bj][q];
+      }
+      __syncthreads();
+      p2_zero<T>(acc);
+    }
+    if (active) p2_right<T, FULL>(acc, sm.fb, w, j0, bi, lane, KB, BN);
+
+    // Results are formed in registers; the next item is put into LDS before
+    // they are stored, so that waiting for its loads does not also wait for
+    // this item's stores (the vector-memory counter covers both).
+    vec_t outv[S::PER];
+    if (INTERLEAVED) {
+      // staged through LDS so that the stores are as contiguous as the loads
+      // (J consecutive y indices per (i1, i2))
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int j = 0; j < JW; ++j)
+#pragma unroll
+          for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              w[j0 + j][bi * 16 + Mma<T>::row(lk, q)][bj * 16 + lr] = acc[j][bj][q];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < S::PER; ++u) {
+        int jj, r, c0;
+        p2_chunk<T, INTERLEAVED>(tid + u * S::NT, jj, r, c0);
+#pragma unroll
+        for (int t = 0; t < J; ++t) P2Vec<T>::set(outv[u], t, w[t][r][c0]);
+      }
+    } else if (active) {
+      const double shift = (PROG == P2_SUM_V_ACC && a.shifts) ? a.shifts[v] : 0.0;
+#pragma unroll
+      for (int j = 0; j < JW; ++j) {
+        const int64_t m = m0 + j0 + j;
+        const T lm = (PROG == P2_SEQ2_DIV && m < a.nmat) ? a.lamM[m] - T(a.sigma) : T(0);
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+          const int c = bj * 16 + lr;
+          const T lc = lamc[bj];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = bi * 16 + Mma<T>::row(lk, q);
+            if (PROG == P2_SUM_V_ACC) {
+              const T pot = a.G ? T(a.gscale) * (g1[j][0][q] * g2[j][0][bj] + g1[j][1][q] * g2[j][1][bj])
+                                : T(0);
+              acc[j][bj][q] += (pot - T(shift)) * w[j0 + j][r][c] + tacc[j][bj][q];
+            } else if (PROG == P2_SEQ2_DIV) {
+              const bool ok = m < a.nmat && (FULL || (r < M && c < Nc));
+              acc[j][bj][q] = ok ? acc[j][bj][q] / (lm + lamr[q] + lc) : T(0);
+            }
+          }
+        }
+      }
+      if (PROG == P2_SUM_V_ACC && !a.G && a.V) {
+        // potential from the table
+#pragma unroll
+        for (int j = 0; j < JW; ++j) {
+          const int64_t m = m0 + j0 + j;
+#pragma unroll
+          for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int r = bi * 16 + Mma<T>::row(lk, q), c = bj * 16 + lr;
+              const bool ok = m < a.nmat && (FULL || (r < M && c < Nc));
+              if (ok) acc[j][bj][q] += a.V[m * a.js + (int64_t)r * a.rs + c] * w[j0 + j][r][c];
+            }
+        }
+      }
+    }
+    // the next item goes into LDS once every wave is done with this one
+    __syncthreads();
+    if (nxt < hi) p2_put<T, INTERLEAVED>(w, tid, pre);
+    if (INTERLEAVED) {
+#pragma unroll
+      for (int u = 0; u < S::PER; ++u) {
+        int jj, r, c0;
+        p2_chunk<T, INTERLEAVED>(tid + u * S::NT, jj, r, c0);
+        int64_t off;
+        const bool ok0 = p2_elem<T, INTERLEAVED, FULL>(a, m0, jj, r, c0, 0, off);
+        if (VEC) {
+          if (ok0) *(vec_t*)(Y + off) = outv[u];
+        } else {
+#pragma unroll
+          for (int t = 0; t < J; ++t) {
+            int64_t o2;
+            if (p2_elem<T, INTERLEAVED, FULL>(a, m0, jj, r, c0, t, o2)) Y[o2] = P2Vec<T>::get(outv[u], t);
+          }
+        }
+      }
+    } else if (active) {
+#pragma unroll
+      for (int j = 0; j < JW; ++j) {
+        const int64_t m = m0 + j0 + j;
+        if (m >= a.nmat) break;
+        const int64_t base = m * a.js;
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+          const int c = bj * 16 + lr;
+          if (!FULL && c >= Nc) continue;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = bi * 16 + Mma<T>::row(lk, q);
+            if (!FULL && r >= M) continue;
+            Y[base + (int64_t)r * a.rs + c] = acc[j][bj][q];
+          }
+        }
+      }
     }
     __syncthreads();
-  };
-
-  if (PROG == P2_SUM || PROG == P2_SUM_V_ACC) {
-    if (active) {
-      p2_left<T, FULL>(acc, a.FA1, w, wave, lane, KA, BN);
-      p2_right<T, FULL>(acc, a.FB1, w, wave, lane, KB, BN);
-    }
-  } else if (PROG == P2_SEQ2) {
-    if (active) p2_left<T, FULL>(acc, a.FA1, w, wave, lane, KA, BN);
-    to_lds(false);
-    p2_zero<T>(acc);
-    if (active) p2_right<T, FULL>(acc, a.FB1, w, wave, lane, KB, BN);
-  } else {  // P2_SEQ4_DIV
-    if (active) p2_left<T, FULL>(acc, a.FA1, w, wave, lane, KA, BN);
-    to_lds(false);
-    p2_zero<T>(acc);
-    if (active) p2_right<T, FULL>(acc, a.FB1, w, wave, lane, KB, BN);
-    to_lds(true);
-    p2_zero<T>(acc);
-    if (active) p2_left<T, FULL>(acc, a.FA2, w, wave, lane, KA, BN);
-    to_lds(false);
-    p2_zero<T>(acc);
-    if (active) p2_right<T, FULL>(acc, a.FB2, w, wave, lane, KB, BN);
-  }
-
-  if (INTERLEAVED) {
-    // stage the result through LDS so that the stores are as contiguous as the
-    // loads (J consecutive y indices per (i1, i2))
-    to_lds(false);
-    for (int e0 = tid; e0 < NE; e0 += 256 * UNR) {
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        int jj, r, c;
-        p2_index<INTERLEAVED, J>(e0 + u * 256, jj, r, c);
-        const int64_t m = m0 + jj;
-        const bool ok = FULL ? (m < a.nmat) : (r < M && c < Nc && m < a.nmat);
-        if (ok) Y[m * a.js + r * a.rs + c * a.cs] = w[jj][r][c];
-      }
-    }
-    return;
-  }
-
-  // planes: store from the accumulators (16 consecutive columns per lane group)
-  if (!active) return;
-  const double shift = (PROG == P2_SUM_V_ACC && a.shifts) ? a.shifts[v] : 0.0;
-#pragma unroll
-  for (int jj = 0; jj < J; ++jj) {
-    const int64_t m = m0 + jj;
-    if (m >= a.nmat) break;
-    const int64_t base = m * a.js;
-    const int i1 = (int)(m / (a.mdiv > 0 ? a.mdiv : 1)), i2 = (int)(m % (a.mdiv > 0 ? a.mdiv : 1));
-#pragma unroll
-    for (int bj = 0; bj < 4; ++bj) {
-      const int c = bj * 16 + lr;
-      if (!FULL && c >= Nc) continue;
-      T g2m = T(0), g2p = T(0);
-      if (PROG == P2_SUM_V_ACC && a.G) {
-        g2m = a.G[2 * P2_MAXN * P2_MAXN + i2 * P2_MAXN + c];
-        g2p = a.G[3 * P2_MAXN * P2_MAXN + i2 * P2_MAXN + c];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = wave * 16 + Mma<T>::row(lk, q);
-        if (!FULL && r >= M) continue;
-        const int64_t off = base + r * a.rs + c;
-        T val = acc[jj][bj][q];
-        if (PROG == P2_SUM_V_ACC) {
-          T pot;
-          if (a.G) {
-            pot = T(a.gscale) * (a.G[i1 * P2_MAXN + r] * g2m +
-                                 a.G[P2_MAXN * P2_MAXN + i1 * P2_MAXN + r] * g2p);
-          } else {
-            pot = a.V ? a.V[off] : T(0);
-          }
-          val += (pot - T(shift)) * w[jj][r][c] + Y[off];
-        }
-        Y[off] = val;
-      }
-    }
   }
 }
 
 template <typename T, int PROG, bool INTERLEAVED>
-static void launch_p2(const Plane2D<T>& a, bool full, unsigned grid, hipStream_t s) {
-  if (full)
-    hipLaunchKernelGGL((k_plane2d<T, PROG, INTERLEAVED, true>), dim3(grid), dim3(256), 0, s, a);
+static void launch_p2(const Plane2D<T>& a, bool full, bool vec, unsigned grid, hipStream_t s) {
+  if (full && vec)
+    hipLaunchKernelGGL((k_plane2d<T, PROG, INTERLEAVED, true, true>), dim3(grid), dim3(512), 0, s, a);
+  else if (full)
+    hipLaunchKernelGGL((k_plane2d<T, PROG, INTERLEAVED, true, false>), dim3(grid), dim3(512), 0, s, a);
   else
-    hipLaunchKernelGGL((k_plane2d<T, PROG, INTERLEAVED, false>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_plane2d<T, PROG, INTERLEAVED, false, false>), dim3(grid), dim3(512), 0, s, a);
 }
+
+// Persistent grid: one workgroup per CU (the LDS holds up to 130 KB).
+constexpr int P2_GRID = 256;
 
 template <typename T>
 hipError_t launch_plane2d(const Plane2D<T>& a, hipStream_t s) {
   if (a.nvec <= 0 || a.nmat <= 0) return hipSuccess;
   if (a.M < 1 || a.Nc < 1 || a.M > P2_MAXN || a.Nc > P2_MAXN) return hipErrorInvalidValue;
-  if (!a.FA1 || !a.FB1 || (a.prog == P2_SEQ4_DIV && (!a.FA2 || !a.FB2))) return hipErrorInvalidValue;
-  if (a.interleaved && a.js != 1) return hipErrorInvalidValue;
+  if (!a.FA1 || !a.FB1) return hipErrorInvalidValue;
+  if (a.interleaved && (a.js != 1 || a.prog == P2_SUM_V_ACC || a.prog == P2_SEQ2_DIV))
+    return hipErrorInvalidValue;
   if (!a.interleaved && a.cs != 1) return hipErrorInvalidValue;
+  if (a.prog == P2_SEQ2_DIV && (!a.lamM || !a.lamR || !a.lamC)) return hipErrorInvalidValue;
   constexpr int J = P2Shape<T>::J;
   const int64_t groups = (a.nmat + J - 1) / J;
-  const int64_t g = groups * a.nvec;
-  if (g > 0x7fffffff) return hipErrorInvalidValue;
+  const int64_t items = groups * a.nvec;
   const bool full = a.M == P2_MAXN && a.Nc == P2_MAXN;
-  const unsigned grid = (unsigned)g;
+  // 16-byte chunks: every chunk starts at a multiple of J elements of a
+  // 16-byte aligned vector and either exists whole or not at all
+  const bool aligned = ((uintptr_t)a.X % 16 == 0) && ((uintptr_t)a.Y % 16 == 0) &&
+                       a.ldx % J == 0 && a.ldy % J == 0;
+  const bool vec = full && aligned &&
+                   (a.interleaved ? (a.nmat % J == 0 && a.rs % J == 0 && a.cs % J == 0)
+                                  : (a.js % J == 0 && a.rs % J == 0));
+  // at least one workgroup per XCD (each XCD owns an eighth of the items)
+  const int64_t g8 = (items + 7) / 8 * 8;
+  const unsigned grid = (unsigned)(g8 < P2_GRID ? g8 : P2_GRID);
   switch (a.prog) {
     case P2_SUM:
-      if (a.interleaved) launch_p2<T, P2_SUM, true>(a, full, grid, s);
-      else launch_p2<T, P2_SUM, false>(a, full, grid, s);
+      if (a.interleaved) launch_p2<T, P2_SUM, true>(a, full, vec, grid, s);
+      else launch_p2<T, P2_SUM, false>(a, full, vec, grid, s);
       break;
     case P2_SUM_V_ACC:
-      if (a.interleaved) return hipErrorInvalidValue;
-      launch_p2<T, P2_SUM_V_ACC, false>(a, full, grid, s);
+      launch_p2<T, P2_SUM_V_ACC, false>(a, full, vec, grid, s);
       break;
     case P2_SEQ2:
-      if (a.interleaved) launch_p2<T, P2_SEQ2, true>(a, full, grid, s);
-      else launch_p2<T, P2_SEQ2, false>(a, full, grid, s);
+      if (a.interleaved) launch_p2<T, P2_SEQ2, true>(a, full, vec, grid, s);
+      else launch_p2<T, P2_SEQ2, false>(a, full, vec, grid, s);
       break;
-    case P2_SEQ4_DIV:
-      if (a.interleaved) return hipErrorInvalidValue;
-      launch_p2<T, P2_SEQ4_DIV, false>(a, full, grid, s);
+    case P2_SEQ2_DIV:
+      launch_p2<T, P2_SEQ2_DIV, false>(a, full, vec, grid, s);
       break;
     default:
       return hipErrorInvalidValue;

@@ -466,9 +466,10 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
   const int64_t N = op->N;
   if (op->ndim == 2 && op->plane2d && !bf3) {
     // (K - sigma)^{-1} = (S_x1 x S_x2 x S_y1 x S_y2) diag(1 / (sum_k lam_k - sigma))
-    // (S_x1^{-1} x ... x S_y2^{-1}) in three passes over LDS-resident matrices:
-    // x slabs S_x1^{-1} W S_x2^{-T}; y planes S_y1 ([S_y1^{-1} W S_y2^{-T}] / Lambda)
-    // S_y2^T; x slabs S_x1 W S_x2^T (the first writes Y, the others work in place).
+    // (S_x1^{-1} x ... x S_y2^{-1}) in four passes over LDS-resident matrices:
+    // x slabs S_x1^{-1} W S_x2^{-T}; y planes [S_y1^{-1} W S_y2^{-T}] / Lambda;
+    // y planes S_y1 W S_y2^T; x slabs S_x1 W S_x2^T (the first writes Y, the
+    // others work in place).
     const int nx1 = op->n[0], nx2 = op->n[1], ny1 = op->n[2], ny2 = op->n[3];
     const int64_t Ny = (int64_t)ny1 * ny2;
     tp3b::Plane2D<T> p{};
@@ -483,7 +484,7 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
     p.FA1 = d.frSi[0]; p.FB1 = d.frSi[1];
     TP3B_HIP(tp3b::launch_plane2d(p, s));
     tp3b::Plane2D<T> q{};
-    q.prog = tp3b::P2_SEQ4_DIV;
+    q.prog = tp3b::P2_SEQ2_DIV;
     q.interleaved = 0;
     q.M = ny1; q.Nc = ny2;
     q.rs = ny2; q.cs = 1; q.js = Ny;
@@ -492,9 +493,11 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
     q.ldx = ldy; q.ldy = ldy;
     q.X = Y; q.Y = Y;
     q.FA1 = d.frSi[2]; q.FB1 = d.frSi[3];
-    q.FA2 = d.frS[2]; q.FB2 = d.frS[3];
     q.lamM = d.lamItem; q.lamR = d.lam[2]; q.lamC = d.lam[3];
     q.sigma = op->sigma;
+    TP3B_HIP(tp3b::launch_plane2d(q, s));
+    q.prog = tp3b::P2_SEQ2;
+    q.FA1 = d.frS[2]; q.FB1 = d.frS[3];
     TP3B_HIP(tp3b::launch_plane2d(q, s));
     p.X = Y; p.ldx = ldy;
     p.FA1 = d.frS[0]; p.FB1 = d.frS[1];

@@ -48,9 +48,10 @@ def run(name):
         print(f"  {name} outer {outer} locked {nlock} theta0 {theta[0]:.12g} "
               f"res0 {rn[0]:.3e} ({time.time() - t0:.0f} s)", flush=True)
 
+    tol = c.get("tol", 1e-12)
     r = jdqr.jdqr(P.apply, P.N, c["nev"], c["block"], precond=pc.apply, seed=c["seed_start"],
                   target=sig, target_low=P.spectrum_lower_bound(), max_outer=400,
-                  progress=progress)
+                  progress=progress, tol=tol)
     dt = time.time() - t
     assert r.converged, name
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_evals.txt")
@@ -58,7 +59,7 @@ def run(name):
         f.write(f"# Lowest {c['nev']} eigenvalues of workload {name} "
                 f"(n={c['n']}, L={c['L']}, M/m={c['alpha']}, V0={c['v0']}, w={c['width']}),\n")
         f.write("# computed by the CPU FP64 oracle (block JDQR, Bartels-Stewart preconditioner,\n")
-        f.write(f"# residual tolerance 1e-12); {r.n_outer} outer iterations, {dt:.1f} s.\n")
+        f.write(f"# residual tolerance {tol:g} max(|theta|, 1)); {r.n_outer} outer iterations, {dt:.1f} s.\n")
         f.write(f"# two-body shift sigma = {sig:.17g}\n")
         for e, rn in zip(r.evals.real, r.resnorm):
             f.write(f"{e:.17g} {rn:.3e}\n")

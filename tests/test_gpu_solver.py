@@ -182,7 +182,9 @@ def test_jdqr_c2_matches_oracle(inner, steps):
 
 def test_jdqr_c3_full_size():
     """c3 at full size (n = 1024, N = 1,048,576, 16 eigenpairs, block 16), with
-    FP64 and with FP32 inner solves; properties that hold at any size: the two
+    FP64, FP32 and BF16x3 inner solves: each within 1e-10 of the oracle's stored
+    eigenvalues (|dE| / |E|; the oracle's values come from its four parity
+    sectors).  Properties that hold at any size: the FP64 and FP32-inner
     solves' eigenvalues agree to 1e-10 (|dE| / max(|E|, 1), R21); the Schur
     vectors are orthonormal to 1e-12; and the oracle's own apply of H to them
     gives partial-Schur residuals ||H q_j - Q R[:, j]|| within the loosest
@@ -217,6 +219,36 @@ def test_jdqr_c3_full_size():
     assert dE <= 1e-10
     assert orth <= 1e-12
     assert np.all(res <= bar)
+    ref = _golden("c3")
+    say("jdqr c3 bf16x3 inner")
+    rb = op.jdqr(cfg["nev"], cfg["block"], inner_prec=t3.BF16X3, seed=cfg["seed_start"],
+                 want_Q=False)
+    for name, r in (("fp64", r64), ("fp32 inner", r32), ("bf16x3 inner", rb)):
+        err = np.max(np.abs(r.evals - ref) / np.abs(ref))
+        say("  vs oracle", name, err, "outer", r.stats["n_outer"], "stall-locked",
+            r.stats["n_stall_lock"])
+        assert err <= 1e-10
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "bf16x3"])
+def test_jdqr_2d_c5r_matches_oracle(inner):
+    """The 2D workload at the reduced size n = 20 per mode (N = 160,000; 6
+    eigenpairs, block 8, the 2D kinetic preconditioner, residual tolerance
+    1e-14 max(|theta|, 1) on both sides since the ground state lies at
+    E = -3.2e-3) against the oracle's stored eigenvalues (its four-mode
+    Bartels-Stewart preconditioned JDQR): |dE| / |E| <= 1e-10 for every inner
+    precision."""
+    t3 = need_gpu()
+    cfg = config("c5r")
+    ref = _golden("c5r")
+    op = t3.Operator.from_config(cfg)
+    pk = {"fp64": t3.FP64, "fp32": t3.FP32, "bf16x3": t3.BF16X3}[inner]
+    say("jdqr c5r", inner)
+    r = op.jdqr(cfg["nev"], cfg["block"], inner_prec=pk, seed=cfg["seed_start"], want_Q=False,
+                tol=cfg["tol"])
+    err = np.max(np.abs(r.evals - ref) / np.abs(ref))
+    say("  evals", r.evals, "err", err, "outer", r.stats["n_outer"])
+    assert err <= 1e-10
 
 
 @pytest.mark.parametrize("seed", [0, 5, 26, 34])
