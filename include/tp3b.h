@@ -158,6 +158,25 @@ tp3b_status tp3b_block_orth(int64_t N, int32_t nq, const double* Q, int64_t ldq,
                             double* X, int64_t ldx, double* C_qx, double* R_xx, int32_t* rank,
                             uint64_t seed, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): tp3b_block_orth without
+ * the factors, with its scratch (the partial sums of the block dots, the small
+ * Gram and Cholesky factors and the dependence flags) taken from a fixed array
+ * of 16.25 MiB that the library holds in device memory, one per GPU, until the
+ * process ends.  The call allocates nothing; the caller passes Q and X as for
+ * tp3b_block_orth, and the result is what tp3b_block_orth with
+ * C_qx = R_xx = NULL computes (the same kernels in the same order while no
+ * column is dependent).  A dependent column is replaced by a pseudo-random
+ * vector and the queued sequence is run again.  Sizes: nx <= 32 and nq such
+ * that the partial sums fit (nq <= 64 always does); larger requests return
+ * TP3B_ENOMEM before any launch.  Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents: calls that overlap on one GPU
+ * (other threads, other streams) race and must be serialised by the caller.
+ * Synchronous (one read-back of the dependence flags). */
+tp3b_status tp3b_block_orth_noalloc(int64_t N, int32_t nq, const double* Q, int64_t ldq, int32_t nx,
+                                    double* X, int64_t ldx, int32_t* rank, uint64_t seed,
+                                    void* stream);
+
 /* Eigensolver options (Sec. 4.1).  Zero/negative fields select defaults
  * (except stall_tol; start from tp3b_jdqr_default_opts). */
 typedef struct {

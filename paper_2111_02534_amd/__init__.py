@@ -78,7 +78,7 @@ EXPORTS = ["tp3b_create", "tp3b_destroy", "tp3b_op_info", "tp3b_get_D2", "tp3b_g
            "tp3b_jdqr_default_opts", "tp3b_jdqr_solve", "tp3b_host_schur", "tp3b_last_error",
            "tp3b_set_tile", "tp3b_autotune", "tp3b_apply_H_batched", "tp3b_apply_prec_batched",
            "tp3b_autotune_batched", "tp3b_jdqr_solve_batched", "tp3b_two_body_depth",
-           "tp3b_homotopy_solve"]
+           "tp3b_homotopy_solve", "tp3b_block_orth_noalloc"]
 
 _lib = None
 
@@ -104,6 +104,8 @@ def lib():
         L.tp3b_apply_prec.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp]
         L.tp3b_block_orth.argtypes = [i64, i32, vp, i64, i32, vp, i64, vp, vp,
                                       ctypes.POINTER(i32), ctypes.c_uint64, vp]
+        L.tp3b_block_orth_noalloc.argtypes = [i64, i32, vp, i64, i32, vp, i64,
+                                              ctypes.POINTER(i32), ctypes.c_uint64, vp]
         L.tp3b_jdqr_default_opts.argtypes = [ctypes.POINTER(JdqrOpts)]
         L.tp3b_jdqr_solve.argtypes = [vp, ctypes.POINTER(JdqrOpts), vp, i32, dp, vp, dp, dp,
                                       ctypes.POINTER(JdqrStats)]
@@ -418,6 +420,17 @@ def block_orth(Q, X, seed=0, want_factors=True, stream=None):
     Cm = C.T[:nq] if (want_factors and nq) else None
     Rm = R.T if want_factors else None
     return Cm, Rm, rank.value
+
+
+def block_orth_noalloc(Q, X, seed=0, stream=None):
+    """tp3b_block_orth_noalloc: orthonormalise X (nx, N) in place against Q
+    (nq, N) without factors, the library allocating nothing.  Returns the rank."""
+    nx, N = X.shape
+    nq = 0 if Q is None else Q.shape[0]
+    rank = ctypes.c_int32()
+    _check(lib().tp3b_block_orth_noalloc(N, nq, _ptr(Q), Q.stride(0) if nq else N, nx, _ptr(X),
+                                         X.stride(0), ctypes.byref(rank), seed, _stream(stream)))
+    return rank.value
 
 
 def _ptr_array(items):

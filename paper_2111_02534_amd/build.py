@@ -12,7 +12,7 @@ LIB = os.path.join(LIBDIR, "libtp3b.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels.hip", "grouped.hip", "plane2d.hip", "tp3b.cpp", "jdqr.cpp", "batched.cpp", "twobody.cpp",
+SOURCES = ["kernels.hip", "grouped.hip", "plane2d.hip", "noalloc.hip", "tp3b.cpp", "jdqr.cpp", "batched.cpp", "twobody.cpp",
            "dense_la.cpp"]
 # packed-FP32 instructions are disabled for every device compilation.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -157,7 +157,11 @@ tp3b_status block_orth_impl(int64_t N, int nq, const double* Q, int64_t ldq, int
 // caller replaces the flagged columns and runs block_orth_impl on X.  Xin
 // (optional, same leading dimension, not aliasing X) is the input block when it
 // lives elsewhere: the first projection writes its result into X.
+// scr (optional): scratch of at least orth_scratch_doubles(N, nq, nx) doubles
+// to use instead of the library's growing dot scratch.
 tp3b_status block_orth_queue(int64_t N, int nq, const double* Q, int64_t ldq, int nx, double* X,
-                             int64_t ldx, int* dflags, hipStream_t s, const double* Xin = nullptr);
+                             int64_t ldx, int* dflags, hipStream_t s, const double* Xin = nullptr,
+                             double* scr = nullptr);
+int64_t orth_scratch_doubles(int64_t N, int nq, int nx);
 
 }  // namespace tp3b

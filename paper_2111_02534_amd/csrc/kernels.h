@@ -219,3 +219,13 @@ template <typename T>
 hipError_t launch_plane2d(const Plane2D<T>& a, hipStream_t s);
 
 }  // namespace tp3b
+
+namespace tp3b {
+
+// The static device scratch of the allocation-free entry point (noalloc.hip):
+// kStaticScratchDoubles doubles (16.25 MiB) per device.  static_scratch()
+// returns its device address on the current device.
+constexpr int64_t kStaticScratchDoubles = ((int64_t)1 << 21) + ((int64_t)1 << 15);
+hipError_t static_scratch(double** out);
+
+}  // namespace tp3b

@@ -603,21 +603,22 @@ constexpr double kDropTol = 1e-7;
 // The scratch layout shared by block_orth_queue and block_orth_impl: dot
 // partials, C1, C2 ((nq+1) x nx each), G, R1, R2 (nx x nx), n0 (nx + 1), then
 // 2 nx + 1 ints of flags.
-static int64_t orth_scratch_doubles(int64_t N, int nq, int nx) {
+int64_t orth_scratch_doubles(int64_t N, int nq, int nx) {
   const int pmax = nq > nx ? nq : nx;
   return dot_scratch_doubles(N, pmax, nx) + 4 * (int64_t)(nq + 1) * nx + 6 * (int64_t)nx * nx +
          2 * nx + 64;
 }
 
 tp3b_status block_orth_queue(int64_t N, int nq, const double* Q, int64_t ldq, int nx, double* X,
-                             int64_t ldx, int* dflags, hipStream_t s, const double* Xin) {
+                             int64_t ldx, int* dflags, hipStream_t s, const double* Xin,
+                             double* scr_in) {
   if (!Xin) Xin = X;
   if (Xin != X && nq <= 0)
     TP3B_HIP(hipMemcpy2DAsync(X, sizeof(double) * ldx, Xin, sizeof(double) * ldx, sizeof(double) * N,
                               nx, hipMemcpyDeviceToDevice, s));
   if (nq <= 0) Xin = X;
   const int pmax = nq > nx ? nq : nx;
-  double* scr = dot_scratch(orth_scratch_doubles(N, nq, nx));
+  double* scr = scr_in ? scr_in : dot_scratch(orth_scratch_doubles(N, nq, nx));
   if (!scr) return fail(TP3B_ENOMEM, "block_orth: scratch allocation failed");
   double* part = scr;
   double* C1 = part + dot_scratch_doubles(N, pmax, nx);
@@ -1157,6 +1158,58 @@ tp3b_status tp3b_block_orth(int64_t N, int32_t nq, const double* Q, int64_t ldq,
     if (ldx < N || (nq > 0 && ldq < N)) return fail(TP3B_EINVAL, "leading dimension smaller than N");
     if (N < nq + nx) return fail(TP3B_EINVAL, "N must be >= nq + nx");
     return block_orth_impl(N, nq, Q, ldq, nx, X, ldx, C_qx, R_xx, rank, seed, (hipStream_t)stream);
+  } catch (...) {
+    return exception_status();
+  }
+}
+
+tp3b_status tp3b_block_orth_noalloc(int64_t N, int32_t nq, const double* Q, int64_t ldq, int32_t nx,
+                                    double* X, int64_t ldx, int32_t* rank, uint64_t seed,
+                                    void* stream) {
+  try {
+    if (N < 0 || nq < 0 || nx < 0) return fail(TP3B_EINVAL, "negative size");
+    if (nx > 32) return fail(TP3B_EINVAL, "nx must be <= 32");
+    if (nx == 0) {
+      if (rank) *rank = 0;
+      return TP3B_OK;
+    }
+    if (!X || (nq > 0 && !Q)) return fail(TP3B_EINVAL, "null X or Q");
+    if (ldx < N || (nq > 0 && ldq < N)) return fail(TP3B_EINVAL, "leading dimension smaller than N");
+    if (N < nq + nx) return fail(TP3B_EINVAL, "N must be >= nq + nx");
+    // the flags sit in the last 64 doubles of the static scratch, the rest
+    // holds the orthogonalisation's partial sums and small factors
+    const int64_t room = kStaticScratchDoubles - 64;
+    if (orth_scratch_doubles(N, nq, nx) > room)
+      return fail(TP3B_ENOMEM, "block_orth_noalloc: N, nq and nx need more than the static scratch "
+                               "(about nq <= 64 for nx <= 32 at any N)");
+    hipStream_t s = (hipStream_t)stream;
+    double* scr = nullptr;
+    TP3B_HIP(static_scratch(&scr));
+    int* dflags = (int*)(scr + room);
+    int hflags[33];
+    int replaced[32] = {0};
+    int deficient = 0;
+    for (int attempt = 0;; ++attempt) {
+      tp3b_status qs = block_orth_queue(N, nq, Q, ldq, nx, X, ldx, dflags, s, nullptr, scr);
+      if (qs != TP3B_OK) return qs;
+      TP3B_HIP(hipMemcpyAsync(hflags, dflags, sizeof(int) * (nx + 1), hipMemcpyDeviceToHost, s));
+      TP3B_HIP(hipStreamSynchronize(s));
+      if (hflags[nx]) return fail(TP3B_ENONFINITE, "block_orth_noalloc: non-finite input");
+      int bad = 0;
+      for (int j = 0; j < nx; ++j) bad += hflags[j] != 0;
+      if (!bad) break;
+      if (attempt == 3) return fail(TP3B_EDEVICE, "block_orth_noalloc: could not complete the basis");
+      // dependent columns: pseudo-random replacements, then the queued
+      // sequence again (the independent columns are already orthonormal)
+      for (int j = 0; j < nx; ++j) {
+        if (!hflags[j]) continue;
+        if (!replaced[j]) ++deficient;
+        replaced[j] = 1;
+        TP3B_HIP(launch_hash_fill(N, X + (int64_t)j * ldx, seed, (uint64_t)(attempt * 64 + j), s));
+      }
+    }
+    if (rank) *rank = nx - deficient;
+    return TP3B_OK;
   } catch (...) {
     return exception_status();
   }
