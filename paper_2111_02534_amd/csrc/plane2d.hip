@@ -41,9 +41,10 @@ void plane2d_fragments(int n, const double* A, double* F) {
 template <typename T>
 struct P2Shape {
   static constexpr int J = 16 / (int)sizeof(T);  // matrices per work item
-  static constexpr int JW = J / 2;               // matrices per wave
+  static constexpr int JW = 1;                   // matrices per wave
+  static constexpr int WB = J;                   // 16-column blocks per wave (FP64 2, FP32 4)
   static constexpr int LD = P2_MAXN + 1;         // padded LDS row
-  static constexpr int NT = 512;                 // threads per workgroup
+  static constexpr int NT = 1024;                // threads per workgroup (16 waves)
   static constexpr int CH = P2_MAXN * P2_MAXN;   // 16-byte chunks of J elements per item
   static constexpr int PER = CH / NT;            // chunks per thread
 };
@@ -51,14 +52,14 @@ struct P2Shape {
 template <typename T>
 using P2Buf = T[P2Shape<T>::J][P2_MAXN][P2Shape<T>::LD];
 template <typename T>
-using P2Acc = typename Mma<T>::acc_t[P2Shape<T>::JW][4];
+using P2Acc = typename Mma<T>::acc_t[P2Shape<T>::JW][P2Shape<T>::WB];
 
-// acc[j][bj] += A(row block bi) * W_{j0 + j}(:, column block bj); A in fragment
-// order in LDS
+// acc[j][b] += A(row block bi) * W_{j0 + j}(:, column block bj0 + b); A in
+// fragment order in LDS
 template <typename T, bool FULL>
 __device__ __forceinline__ void p2_left(P2Acc<T>& acc, const T* FA, const P2Buf<T>& w, int j0,
-                                        int bi, int lane, int KA, int BN) {
-  constexpr int JW = P2Shape<T>::JW;
+                                        int bj0, int bi, int lane, int KA, int BN) {
+  constexpr int JW = P2Shape<T>::JW, WB = P2Shape<T>::WB;
   const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll 4
   for (int kk = 0; kk < (FULL ? 16 : KA); ++kk) {
@@ -66,17 +67,17 @@ __device__ __forceinline__ void p2_left(P2Acc<T>& acc, const T* FA, const P2Buf<
 #pragma unroll
     for (int j = 0; j < JW; ++j)
 #pragma unroll
-      for (int bj = 0; bj < 4; ++bj)
-        if (FULL || bj < BN)
-          acc[j][bj] = Mma<T>::mma(af, w[j0 + j][4 * kk + lk][bj * 16 + lr], acc[j][bj]);
+      for (int b = 0; b < WB; ++b)
+        if (FULL || bj0 + b < BN)
+          acc[j][b] = Mma<T>::mma(af, w[j0 + j][4 * kk + lk][(bj0 + b) * 16 + lr], acc[j][b]);
   }
 }
 
-// acc[j][bj] += W_{j0 + j}(row block bi, :) * B^T(:, column block bj)
+// acc[j][b] += W_{j0 + j}(row block bi, :) * B^T(:, column block bj0 + b)
 template <typename T, bool FULL>
 __device__ __forceinline__ void p2_right(P2Acc<T>& acc, const T* FB, const P2Buf<T>& w, int j0,
-                                         int bi, int lane, int KB, int BN) {
-  constexpr int JW = P2Shape<T>::JW;
+                                         int bj0, int bi, int lane, int KB, int BN) {
+  constexpr int JW = P2Shape<T>::JW, WB = P2Shape<T>::WB;
   const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll 4
   for (int kk = 0; kk < (FULL ? 16 : KB); ++kk) {
@@ -84,11 +85,11 @@ __device__ __forceinline__ void p2_right(P2Acc<T>& acc, const T* FB, const P2Buf
 #pragma unroll
     for (int j = 0; j < JW; ++j) a[j] = w[j0 + j][bi * 16 + lr][4 * kk + lk];
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj)
-      if (FULL || bj < BN) {
-        const T bf = FB[(bj * 16 + kk) * 64 + lane];
+    for (int b = 0; b < WB; ++b)
+      if (FULL || bj0 + b < BN) {
+        const T bf = FB[((bj0 + b) * 16 + kk) * 64 + lane];
 #pragma unroll
-        for (int j = 0; j < JW; ++j) acc[j][bj] = Mma<T>::mma(a[j], bf, acc[j][bj]);
+        for (int j = 0; j < JW; ++j) acc[j][b] = Mma<T>::mma(a[j], bf, acc[j][b]);
       }
   }
 }
@@ -98,7 +99,7 @@ __device__ __forceinline__ void p2_zero(P2Acc<T>& acc) {
 #pragma unroll
   for (int j = 0; j < P2Shape<T>::JW; ++j)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[j][bj] = typename Mma<T>::acc_t{0, 0, 0, 0};
+    for (int b = 0; b < P2Shape<T>::WB; ++b) acc[j][b] = typename Mma<T>::acc_t{0, 0, 0, 0};
 }
 
 // Chunk q of a work item (J elements that are contiguous in memory):
@@ -211,26 +212,28 @@ struct P2Smem {
   T fa[P2_FRAG], fb[P2_FRAG];  // the two constant factors, fragment order
 };
 
-// Persistent workgroups of 512 threads (eight waves, two per SIMD), one per
-// CU.  The two constant factors of the pass are copied to LDS once.  Work
+// Persistent workgroups of 1024 threads (sixteen waves, four per SIMD), one
+// per CU.  The two constant factors of the pass are copied to LDS once.  Work
 // items are the groups of J matrices of every vector; the items of XCD
 // x = blockIdx % 8 are the contiguous range [x T / 8, (x + 1) T / 8), taken in
 // turn by that XCD's workgroups, so that neighbouring items (which share cache
 // lines in the interleaved layout) run together on one L2.  While item i is
 // multiplied out of LDS, item i + 1 is fetched into registers; it is stored
 // into LDS once item i has been written out.  Wave w computes row block w % 4
-// of matrices (w / 4) * JW .. (w / 4 + 1) * JW - 1.
+// of one matrix, column blocks bj0 .. bj0 + WB - 1 (FP64: two per wave,
+// FP32: all four).
 template <typename T, int PROG, bool INTERLEAVED, bool FULL, bool VEC>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_plane2d(
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void k_plane2d(
     Plane2D<T> a) {
   typedef P2Shape<T> S;
-  constexpr int J = S::J, JW = S::JW;
+  constexpr int J = S::J, JW = S::JW, WB = S::WB;
   typedef typename P2Vec<T>::v vec_t;
   __shared__ P2Smem<T> sm;
   P2Buf<T>& w = sm.w;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int bi = wave & 3, j0 = (wave >> 2) * JW;
+  constexpr int NCB = 4 / WB;  // column-block groups per matrix
+  const int bi = wave & 3, j0 = ((wave >> 2) / NCB) * JW, bj0 = ((wave >> 2) % NCB) * WB;
   const int lr = lane & 15, lk = lane >> 4;
   const int M = a.M, Nc = a.Nc;
   const int BM = FULL ? 4 : (M + 15) / 16, BN = FULL ? 4 : (Nc + 15) / 16;
@@ -249,12 +252,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
   // the divide's row and column eigenvalues of this lane's output elements
   // (the same for every item)
-  T lamr[4], lamc[4];
+  T lamr[4], lamc[WB];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int r = bi * 16 + Mma<T>::row(lk, q), c = q * 16 + lr;
+    const int r = bi * 16 + Mma<T>::row(lk, q);
     lamr[q] = (PROG == P2_SEQ2_DIV && r < M) ? a.lamR[r] : T(0);
-    lamc[q] = (PROG == P2_SEQ2_DIV && c < Nc) ? a.lamC[c] : T(0);
+  }
+#pragma unroll
+  for (int b = 0; b < WB; ++b) {
+    const int c = (bj0 + b) * 16 + lr;
+    lamc[b] = (PROG == P2_SEQ2_DIV && c < Nc) ? a.lamC[c] : T(0);
   }
   vec_t pre[S::PER];
   int64_t item = lo + slot;
@@ -276,7 +283,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     // the epilogue's global operands, read before the products so that their
     // latency is hidden: the x part of the Hamiltonian (Y in place) and the
     // potential's separable factors
-    T tacc[JW][4][4], g1[JW][2][4], g2[JW][2][4];
+    T tacc[JW][WB][4], g1[JW][2][4], g2[JW][2][WB];
     if (PROG == P2_SUM_V_ACC && active) {
 #pragma unroll
       for (int j = 0; j < JW; ++j) {
@@ -285,12 +292,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int i1 = (int)(m / md), i2 = (int)(m % md);
         const bool mok = m < a.nmat;
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
+        for (int b = 0; b < WB; ++b)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int r = bi * 16 + Mma<T>::row(lk, q), c = bj * 16 + lr;
+            const int r = bi * 16 + Mma<T>::row(lk, q), c = (bj0 + b) * 16 + lr;
             const bool ok = mok && (FULL || (r < M && c < Nc));
-            tacc[j][bj][q] = ok ? Y[m * a.js + (int64_t)r * a.rs + c] : T(0);
+            tacc[j][b][q] = ok ? Y[m * a.js + (int64_t)r * a.rs + c] : T(0);
           }
         if (a.G) {
 #pragma unroll
@@ -300,17 +307,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
             g1[j][1][q] = mok ? a.G[P2_MAXN * P2_MAXN + i1 * P2_MAXN + r] : T(0);
           }
 #pragma unroll
-          for (int bj = 0; bj < 4; ++bj) {
-            const int c = bj * 16 + lr;
-            g2[j][0][bj] = mok ? a.G[2 * P2_MAXN * P2_MAXN + i2 * P2_MAXN + c] : T(0);
-            g2[j][1][bj] = mok ? a.G[3 * P2_MAXN * P2_MAXN + i2 * P2_MAXN + c] : T(0);
+          for (int b = 0; b < WB; ++b) {
+            const int c = (bj0 + b) * 16 + lr;
+            g2[j][0][b] = mok ? a.G[2 * P2_MAXN * P2_MAXN + i2 * P2_MAXN + c] : T(0);
+            g2[j][1][b] = mok ? a.G[3 * P2_MAXN * P2_MAXN + i2 * P2_MAXN + c] : T(0);
           }
         }
       }
     }
     P2Acc<T> acc;
     p2_zero<T>(acc);
-    if (active) p2_left<T, FULL>(acc, sm.fa, w, j0, bi, lane, KA, BN);
+    if (active) p2_left<T, FULL>(acc, sm.fa, w, j0, bj0, bi, lane, KA, BN);
     if (PROG == P2_SEQ2 || PROG == P2_SEQ2_DIV) {
       // A W -> LDS, then (A W) B^T
       __syncthreads();
@@ -318,15 +325,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int j = 0; j < JW; ++j)
 #pragma unroll
-          for (int bj = 0; bj < 4; ++bj)
+          for (int b = 0; b < WB; ++b)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-              w[j0 + j][bi * 16 + Mma<T>::row(lk, q)][bj * 16 + lr] = acc[j][bj][q];
+              w[j0 + j][bi * 16 + Mma<T>::row(lk, q)][(bj0 + b) * 16 + lr] = acc[j][b][q];
       }
       __syncthreads();
       p2_zero<T>(acc);
     }
-    if (active) p2_right<T, FULL>(acc, sm.fb, w, j0, bi, lane, KB, BN);
+    if (active) p2_right<T, FULL>(acc, sm.fb, w, j0, bj0, bi, lane, KB, BN);
 
     // Results are formed in registers; the next item is put into LDS before
     // they are stored, so that waiting for its loads does not also wait for
@@ -340,10 +347,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int j = 0; j < JW; ++j)
 #pragma unroll
-          for (int bj = 0; bj < 4; ++bj)
+          for (int b = 0; b < WB; ++b)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-              w[j0 + j][bi * 16 + Mma<T>::row(lk, q)][bj * 16 + lr] = acc[j][bj][q];
+              w[j0 + j][bi * 16 + Mma<T>::row(lk, q)][(bj0 + b) * 16 + lr] = acc[j][b][q];
       }
       __syncthreads();
 #pragma unroll
@@ -360,19 +367,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int64_t m = m0 + j0 + j;
         const T lm = (PROG == P2_SEQ2_DIV && m < a.nmat) ? a.lamM[m] - T(a.sigma) : T(0);
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-          const int c = bj * 16 + lr;
-          const T lc = lamc[bj];
+        for (int b = 0; b < WB; ++b) {
+          const int c = (bj0 + b) * 16 + lr;
+          const T lc = lamc[b];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int r = bi * 16 + Mma<T>::row(lk, q);
             if (PROG == P2_SUM_V_ACC) {
-              const T pot = a.G ? T(a.gscale) * (g1[j][0][q] * g2[j][0][bj] + g1[j][1][q] * g2[j][1][bj])
+              const T pot = a.G ? T(a.gscale) * (g1[j][0][q] * g2[j][0][b] + g1[j][1][q] * g2[j][1][b])
                                 : T(0);
-              acc[j][bj][q] += (pot - T(shift)) * w[j0 + j][r][c] + tacc[j][bj][q];
+              acc[j][b][q] += (pot - T(shift)) * w[j0 + j][r][c] + tacc[j][b][q];
             } else if (PROG == P2_SEQ2_DIV) {
               const bool ok = m < a.nmat && (FULL || (r < M && c < Nc));
-              acc[j][bj][q] = ok ? acc[j][bj][q] / (lm + lamr[q] + lc) : T(0);
+              acc[j][b][q] = ok ? acc[j][b][q] / (lm + lamr[q] + lc) : T(0);
             }
           }
         }
@@ -383,12 +390,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
         for (int j = 0; j < JW; ++j) {
           const int64_t m = m0 + j0 + j;
 #pragma unroll
-          for (int bj = 0; bj < 4; ++bj)
+          for (int b = 0; b < WB; ++b)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              const int r = bi * 16 + Mma<T>::row(lk, q), c = bj * 16 + lr;
+              const int r = bi * 16 + Mma<T>::row(lk, q), c = (bj0 + b) * 16 + lr;
               const bool ok = m < a.nmat && (FULL || (r < M && c < Nc));
-              if (ok) acc[j][bj][q] += a.V[m * a.js + (int64_t)r * a.rs + c] * w[j0 + j][r][c];
+              if (ok) acc[j][b][q] += a.V[m * a.js + (int64_t)r * a.rs + c] * w[j0 + j][r][c];
             }
         }
       }
@@ -420,14 +427,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (m >= a.nmat) break;
         const int64_t base = m * a.js;
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-          const int c = bj * 16 + lr;
+        for (int b = 0; b < WB; ++b) {
+          const int c = (bj0 + b) * 16 + lr;
           if (!FULL && c >= Nc) continue;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int r = bi * 16 + Mma<T>::row(lk, q);
             if (!FULL && r >= M) continue;
-            Y[base + (int64_t)r * a.rs + c] = acc[j][bj][q];
+            Y[base + (int64_t)r * a.rs + c] = acc[j][b][q];
           }
         }
       }
@@ -439,11 +446,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
 template <typename T, int PROG, bool INTERLEAVED>
 static void launch_p2(const Plane2D<T>& a, bool full, bool vec, unsigned grid, hipStream_t s) {
   if (full && vec)
-    hipLaunchKernelGGL((k_plane2d<T, PROG, INTERLEAVED, true, true>), dim3(grid), dim3(512), 0, s, a);
+    hipLaunchKernelGGL((k_plane2d<T, PROG, INTERLEAVED, true, true>), dim3(grid), dim3(1024), 0, s, a);
   else if (full)
-    hipLaunchKernelGGL((k_plane2d<T, PROG, INTERLEAVED, true, false>), dim3(grid), dim3(512), 0, s, a);
+    hipLaunchKernelGGL((k_plane2d<T, PROG, INTERLEAVED, true, false>), dim3(grid), dim3(1024), 0, s, a);
   else
-    hipLaunchKernelGGL((k_plane2d<T, PROG, INTERLEAVED, false, false>), dim3(grid), dim3(512), 0, s, a);
+    hipLaunchKernelGGL((k_plane2d<T, PROG, INTERLEAVED, false, false>), dim3(grid), dim3(1024), 0, s, a);
 }
 
 // Persistent grid: one workgroup per CU (the LDS holds up to 130 KB).
