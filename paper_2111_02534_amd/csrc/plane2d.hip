@@ -206,6 +206,27 @@ __device__ __forceinline__ void p2_put(P2Buf<T>& w, int tid,
   }
 }
 
+// Work item t -> (vector, first matrix of the group).
+template <int J>
+__device__ __forceinline__ void p2_decode(int64_t t, int64_t groups, int64_t& v, int64_t& m0) {
+  v = t / groups;
+  m0 = (t - v * groups) * J;
+}
+
+// Schedule: in step k the grid processes the items k G .. k G + G - 1 (G =
+// gridDim.x).  With G a multiple of 64, position i of a step belongs to
+// workgroup (XCD x, slot l), i = (l / 8) 64 + 8 x + l % 8: eight consecutive
+// items (one 128-byte line of the interleaved x-slab layout) go to eight
+// workgroups of one XCD, which share the line in that XCD's L2, and the whole
+// grid works on one contiguous range of items, so that the slab elements in
+// flight at a tensor position are neighbours in memory (DRAM pages are reused
+// instead of opened once per 16-byte piece).
+__device__ __forceinline__ int64_t p2_slot(int g, int G) {
+  if (G % 64 != 0) return g;
+  const int x = g & 7, l = g >> 3;
+  return (int64_t)((l >> 3) * 64 + x * 8 + (l & 7));
+}
+
 template <typename T>
 struct P2Smem {
   P2Buf<T> w;                 // the current work item
@@ -242,9 +263,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
 
   const int64_t groups = (a.nmat + J - 1) / J;
   const int64_t total = groups * a.nvec;
-  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-  const int nslot = (int)((gridDim.x - xcd + 7) >> 3);
-  const int64_t lo = (int64_t)xcd * total / 8, hi = (int64_t)(xcd + 1) * total / 8;
+  const int64_t G = gridDim.x, i0 = p2_slot(blockIdx.x, (int)G);
 
   for (int e = tid; e < P2_FRAG; e += S::NT) {
     sm.fa[e] = a.FA1[e];
@@ -264,25 +283,25 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
     lamc[b] = (PROG == P2_SEQ2_DIV && c < Nc) ? a.lamC[c] : T(0);
   }
   vec_t pre[S::PER];
-  int64_t item = lo + slot;
-  if (item < hi) {
-    const int64_t v = item / groups, m0 = (item - v * groups) * J;
+  int64_t item = i0;
+  if (item < total) {
+    int64_t v, m0;
+    p2_decode<J>(item, groups, v, m0);
     p2_fetch<T, INTERLEAVED, FULL, VEC>(a, a.X + v * a.ldx, m0, tid, pre);
     p2_put<T, INTERLEAVED>(w, tid, pre);
   }
   __syncthreads();
 
-  for (; item < hi; item += nslot) {
-    const int64_t v = item / groups, m0 = (item - v * groups) * J;
-    const int64_t nxt = item + nslot;
-    if (nxt < hi) {
-      const int64_t v2 = nxt / groups, m2 = (nxt - v2 * groups) * J;
-      p2_fetch<T, INTERLEAVED, FULL, VEC>(a, a.X + v2 * a.ldx, m2, tid, pre);
-    }
+  for (; item < total; item += G) {
+    int64_t v, m0;
+    p2_decode<J>(item, groups, v, m0);
+    const int64_t nxt = item + G;
     T* Y = a.Y + v * a.ldy;
     // the epilogue's global operands, read before the products so that their
     // latency is hidden: the x part of the Hamiltonian (Y in place) and the
-    // potential's separable factors
+    // potential's separable factors.  They are issued before the next item's
+    // fetch, so that waiting for them does not wait for the fetch as well (the
+    // vector-memory counter drains in issue order).
     T tacc[JW][WB][4], g1[JW][2][4], g2[JW][2][WB];
     if (PROG == P2_SUM_V_ACC && active) {
 #pragma unroll
@@ -314,6 +333,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
           }
         }
       }
+    }
+    if (nxt < total) {
+      int64_t v2, m2;
+      p2_decode<J>(nxt, groups, v2, m2);
+      p2_fetch<T, INTERLEAVED, FULL, VEC>(a, a.X + v2 * a.ldx, m2, tid, pre);
     }
     P2Acc<T> acc;
     p2_zero<T>(acc);
@@ -402,7 +426,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
     }
     // the next item goes into LDS once every wave is done with this one
     __syncthreads();
-    if (nxt < hi) p2_put<T, INTERLEAVED>(w, tid, pre);
+    if (nxt < total) p2_put<T, INTERLEAVED>(w, tid, pre);
     if (INTERLEAVED) {
 #pragma unroll
       for (int u = 0; u < S::PER; ++u) {
@@ -476,23 +500,22 @@ hipError_t launch_plane2d(const Plane2D<T>& a, hipStream_t s) {
   const bool vec = full && aligned &&
                    (a.interleaved ? (a.nmat % J == 0 && a.rs % J == 0 && a.cs % J == 0)
                                   : (a.js % J == 0 && a.rs % J == 0));
-  // at least one workgroup per XCD (each XCD owns an eighth of the items)
-  const int64_t g8 = (items + 7) / 8 * 8;
-  const unsigned grid = (unsigned)(g8 < P2_GRID ? g8 : P2_GRID);
+  Plane2D<T> b = a;
+  const unsigned grid = (unsigned)(items < P2_GRID ? items : P2_GRID);
   switch (a.prog) {
     case P2_SUM:
-      if (a.interleaved) launch_p2<T, P2_SUM, true>(a, full, vec, grid, s);
-      else launch_p2<T, P2_SUM, false>(a, full, vec, grid, s);
+      if (a.interleaved) launch_p2<T, P2_SUM, true>(b, full, vec, grid, s);
+      else launch_p2<T, P2_SUM, false>(b, full, vec, grid, s);
       break;
     case P2_SUM_V_ACC:
-      launch_p2<T, P2_SUM_V_ACC, false>(a, full, vec, grid, s);
+      launch_p2<T, P2_SUM_V_ACC, false>(b, full, vec, grid, s);
       break;
     case P2_SEQ2:
-      if (a.interleaved) launch_p2<T, P2_SEQ2, true>(a, full, vec, grid, s);
-      else launch_p2<T, P2_SEQ2, false>(a, full, vec, grid, s);
+      if (a.interleaved) launch_p2<T, P2_SEQ2, true>(b, full, vec, grid, s);
+      else launch_p2<T, P2_SEQ2, false>(b, full, vec, grid, s);
       break;
     case P2_SEQ2_DIV:
-      launch_p2<T, P2_SEQ2_DIV, false>(a, full, vec, grid, s);
+      launch_p2<T, P2_SEQ2_DIV, false>(b, full, vec, grid, s);
       break;
     default:
       return hipErrorInvalidValue;
