@@ -695,3 +695,33 @@ def test_c4_stored_values_match_dense_at_n64():
     assert idx.size == 50 and np.all(g[idx, 1] == 64)
     rel = np.abs(g[idx, 5:9] - d[:, 1:5]) / np.abs(d[:, 1:5])
     assert np.max(rel) <= 1e-10, (idx[np.argmax(rel.max(axis=1))], np.max(rel))
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c5"])
+def test_stored_apply_samples_match_tensor_apply(name):
+    """The stored samples of H w at full size (written entry by entry by
+    tests/golden/make_golden.py) against the oracle's tensor-form apply of the
+    whole vector: a second route through eq. (9) / eq. (11).  For c5 only
+    vector 0 is regenerated (the first N normal draws of the block's stream)."""
+    from workloads import config, normal_block
+    c = config(name)
+    P = problem.make_problem(**c)
+    s = np.loadtxt(os.path.join(GOLDEN, f"{name}_apply_samples.txt"), ndmin=2)
+    vecs = sorted(set(s[:, 0].astype(int)))
+    if name == "c5":
+        # row 0 of normal_block is the first N draws of its generator
+        assert np.array_equal(normal_block(100, 3, 9)[0],
+                              np.random.Generator(np.random.PCG64(9)).standard_normal(100))
+        X = {0: np.random.Generator(np.random.PCG64(c["seed_apply"])).standard_normal(P.N)}
+    else:
+        B = normal_block(P.N, c["block"], c["seed_apply"])
+        X = {v: B[v] for v in vecs}
+    checked = 0
+    for v, w in X.items():
+        Y = P.apply(w)
+        rows = s[s[:, 0] == v]
+        idx = rows[:, 1].astype(np.int64)
+        err = np.abs(Y[idx] - rows[:, 2]) / rows[:, 3]
+        assert np.max(err) <= 1e-13, (v, np.max(err))
+        checked += len(idx)
+    assert checked >= 300
