@@ -165,7 +165,7 @@ def sampled_apply_errors(t3, op, name, cfg, reps):
     return out
 
 
-def solve_leg(op, cfg, inner, steps, gmres_steps, nev=None, block=None, want_Q=False):
+def solve_leg(op, cfg, inner, steps, gmres_steps, nev=None, block=None, want_Q=False, m_max=0):
     import torch
     nev = nev or cfg["nev"]
     block = block or cfg["block"]
@@ -174,7 +174,7 @@ def solve_leg(op, cfg, inner, steps, gmres_steps, nev=None, block=None, want_Q=F
     t0 = time.perf_counter()
     for _ in range(steps):
         res.append(op.jdqr(nev, block, inner_prec=inner, seed=cfg["seed_start"], want_Q=want_Q,
-                           gmres_steps=gmres_steps))
+                           gmres_steps=gmres_steps, m_max=m_max, m_min=m_max // 2))
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / max(steps, 1), res
 
@@ -426,8 +426,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--gmres-steps", type=int, default=5,
+    ap.add_argument("--gmres-steps", type=int, default=3,
                     help="GMRES steps per correction equation in the timed c5 solves")
+    ap.add_argument("--m-max", type=int, default=48,
+                    help="search-space size before a restart in the timed c5 solves (m_min = m_max / 2; "
+                         "0: the library's default)")
     ap.add_argument("--mixed-steps", type=int, default=0, help="timed mixed solves (0: steps // 2)")
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true", help="only the c5 legs and the CPU baseline")
@@ -459,17 +462,17 @@ def main():
     cfg = config("c5")
     nev, b, n = cfg["nev"], cfg["block"], cfg["n"]
     op = t3.Operator.from_config(cfg)
-    gs = args.gmres_steps
+    gs, mm = args.gmres_steps, args.m_max
 
     # ---- the timed FP64 solves (the step)
     if args.warmup > 0:
-        solve_leg(op, cfg, t3.FP64, args.warmup, gs)
-    s_fp64, res = solve_leg(op, cfg, t3.FP64, args.steps, gs)
+        solve_leg(op, cfg, t3.FP64, args.warmup, gs, m_max=mm)
+    s_fp64, res = solve_leg(op, cfg, t3.FP64, args.steps, gs, m_max=mm)
     fp64_stats = stats_brief(res[-1])
     # ---- the same solve with FP32 inner GMRES
     msteps = args.mixed_steps or max(1, args.steps // 2)
-    solve_leg(op, cfg, t3.FP32, 1, gs)
-    s_mixed, mres = solve_leg(op, cfg, t3.FP32, msteps, gs)
+    solve_leg(op, cfg, t3.FP32, 1, gs, m_max=mm)
+    s_mixed, mres = solve_leg(op, cfg, t3.FP32, msteps, gs, m_max=mm)
     agree = max(rel_err(r.evals, res[-1].evals) for r in mres)
 
     # ---- applies: roofline of the Hamiltonian apply, sampled errors
@@ -496,8 +499,9 @@ def main():
         "config": {"workload": (f"c5: 2D three-body (four tensor modes), n={n} per mode "
                                 f"(N={16777216} per vector), M/m={cfg['alpha']}, Gaussian V0={cfg['v0']}, "
                                 f"w={cfg['width']}, lowest {nev} eigenpairs, block {b}, FP64 JDQR with "
-                                f"the 2D kinetic preconditioner, {gs} GMRES steps per correction"),
-                   "n": n, "nev": nev, "block": b, "gmres_steps": gs},
+                                f"the 2D kinetic preconditioner, {gs} GMRES steps per correction, "
+                                f"restart from m_max={mm or 'default'} to m_min={mm // 2 or 'default'}"),
+                   "n": n, "nev": nev, "block": b, "gmres_steps": gs, "m_max": mm or None},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["fp64"],
                      "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp64"],
                      "traffic": TRAFFIC_BYTES.get("c5"),

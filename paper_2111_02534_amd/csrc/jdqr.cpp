@@ -175,8 +175,12 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   const int qv_cols = nev + m_max + b;
   const int av_cols = m_max + b + nev;
   const int qt_max = nev + b;
-  DevBuf QVb, AVb, TMPb, Rresb, PQb, Ypb, Qtwb, Ypwb, Vgb, Wb, Zb, Tcb, smallb;
+  DevBuf QVb, AVb, TMPb, Rresb, PQb, Ypb, Qtwb, Ypwb, Vgb, Wb, Zb, Tcb, smallb, Qtb, AUb;
   TP3B_HIP(dalloc(QVb, sizeof(double) * N * qv_cols));
+  // Q~ = [Q_lock, U] contiguous (U = V s_1..s_nb, plus one column for the
+  // residual when a 2 x 2 block straddles the block edge), and A U
+  TP3B_HIP(dalloc(Qtb, sizeof(double) * N * (qt_max + 1)));
+  TP3B_HIP(dalloc(AUb, sizeof(double) * N * b));
   TP3B_HIP(dalloc(AVb, sizeof(double) * N * av_cols));
   // same capacity as A V: the two buffers swap roles after a rotation
   TP3B_HIP(dalloc(TMPb, sizeof(double) * N * av_cols));
@@ -228,9 +232,11 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   const int hld = steps + 2;
   const size_t n_small = (size_t)(m_max + b) * (m_max + b) * 2 + (size_t)qt_max * qt_max +
                          (size_t)qt_max * b * 2 + (size_t)steps * b * hld * 2 + (size_t)steps * b +
-                         (size_t)b * 4 + (size_t)hld * b + (size_t)b + 64;
+                         (size_t)b * 4 + (size_t)hld * b + (size_t)b + (size_t)(b + 1) * b + 64;
   TP3B_HIP(dalloc(smallb, sizeof(double) * n_small));
   double* QV = QVb.as<double>();
+  double* Qt = Qtb.as<double>();
+  double* AU = AUb.as<double>();
   double* AVbase = AVb.as<double>();
   double* TMP = TMPb.as<double>();
   double* Rres = Rresb.as<double>();
@@ -252,7 +258,8 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   double* dNrm = dShift + b;                                         // b
   double* dBeta = dNrm + b;                                          // b
   double* dY = dBeta + 2 * b;                                        // b*hld
-  int* dFlag = (int*)(dY + (size_t)b * hld);  // singular projected preconditioner
+  double* dTb = dY + (size_t)b * hld;                                // (b+1)*b
+  int* dFlag = (int*)(dTb + (size_t)(b + 1) * b);  // singular projected preconditioner
   int* dOFlags = dFlag + 2;                    // expansion block: b dependence flags, non-finite
   TP3B_HIP(hipMemsetAsync(dFlag, 0, sizeof(int), s));
   const int64_t dscr = dot_scratch_doubles(N, qt_max + m_max + b, qt_max + m_max + b) +
@@ -340,7 +347,10 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   double prev_rn0 = INFINITY;  // leading residual of the last outer iteration
   int stall = 0;               // consecutive outer iterations without progress
   while (k < nev && outer < o.max_outer) {
-    // ---- 1. ordered Schur form of the projected matrix, rotate V and A V
+    // ---- 1. ordered Schur form M = S T S^T of the projected matrix.  V and
+    // A V are not rotated here: the leading Schur vectors U = V S[:, :nb] and
+    // A U are formed on their own (N x m x nb instead of N x m x m), and the
+    // whole basis is rotated only where it changes (locking, restart).
     double t0 = now();
     S.assign((size_t)m * m, 0.0);
     T.assign((size_t)m * m, 0.0);
@@ -351,26 +361,36 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     for (int i = 0; i < m && ident; ++i)
       for (int j = 0; j < m; ++j)
         if (S[(size_t)i * m + j] != (i == j ? 1.0 : 0.0)) { ident = false; break; }
-    if (!ident) {
-      std::vector<double> Sc = colmajor(S, m, 0, 0, m, m);
-      std::memcpy(P(r_upS), Sc.data(), sizeof(double) * m * m);
-      TP3B_HIP(hipMemcpyAsync(dS, P(r_upS), sizeof(double) * m * m, hipMemcpyHostToDevice, s));
-      TP3B_HIP(launch_gemm_nn<double>(N, m, m, 1.0, V(), N, dS, m, 0.0, TMP, N, s));
-      TP3B_HIP(hipMemcpyAsync(V(), TMP, sizeof(double) * N * m, hipMemcpyDeviceToDevice, s));
-      TP3B_HIP(launch_gemm_nn<double>(N, m, m, 1.0, AV(), N, dS, m, 0.0, TMP, N, s));
+    // V <- V S[:, :q], A V <- A V S[:, :q] (q = m: the full rotation)
+    auto rotate = [&](int q) -> tp3b_status {
+      std::vector<double> Sc = colmajor(S, m, 0, 0, m, q);
+      std::memcpy(P(r_upS), Sc.data(), sizeof(double) * m * q);
+      TP3B_HIP(hipMemcpyAsync(dS, P(r_upS), sizeof(double) * m * q, hipMemcpyHostToDevice, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, m, q, 1.0, V(), N, dS, m, 0.0, TMP, N, s));
+      TP3B_HIP(hipMemcpyAsync(V(), TMP, sizeof(double) * N * q, hipMemcpyDeviceToDevice, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, m, q, 1.0, AV(), N, dS, m, 0.0, TMP, N, s));
       // the rotated A V stays where it was written (no copy back)
       std::swap(AVbase, TMP);
       av0 = 0;
-    }
-    M = T;
+      return TP3B_OK;
+    };
     const int nb = std::min(b, m);
-    // ---- 2. residuals R = (I - Q Q^T)(A U - V T[:, :nb])
+    // a 2 x 2 block across the block edge couples u_nb into the residual of
+    // column nb - 1
+    const int nu = std::min(m, nb + 1);
+    // ---- 2. U = V S[:, :nu] (into Q~ after the locked vectors), A U, and the
+    // residuals R = (I - Q Q^T)(A U - U T[:nu, :nb])
     {
-      std::vector<double> Tc_ = colmajor(T, m, 0, 0, m, nb);
-      std::memcpy(P(r_upT), Tc_.data(), sizeof(double) * m * nb);
-      TP3B_HIP(hipMemcpyAsync(dS, P(r_upT), sizeof(double) * m * nb, hipMemcpyHostToDevice, s));
-      // Rres = A U - V T[:, :nb], A U being the first nb columns of A V
-      TP3B_HIP(launch_gemm_nn_x0<double>(N, m, nb, -1.0, V(), N, dS, m, 1.0, AV(), N, Rres, N, s));
+      std::vector<double> Sc = colmajor(S, m, 0, 0, m, nu);
+      std::memcpy(P(r_upS), Sc.data(), sizeof(double) * m * nu);
+      TP3B_HIP(hipMemcpyAsync(dS, P(r_upS), sizeof(double) * m * nu, hipMemcpyHostToDevice, s));
+      std::vector<double> Tc_ = colmajor(T, m, 0, 0, nu, nb);
+      std::memcpy(P(r_upT), Tc_.data(), sizeof(double) * nu * nb);
+      TP3B_HIP(hipMemcpyAsync(dTb, P(r_upT), sizeof(double) * nu * nb, hipMemcpyHostToDevice, s));
+      double* U = Qt + (int64_t)k * N;
+      TP3B_HIP(launch_gemm_nn<double>(N, m, nu, 1.0, V(), N, dS, m, 0.0, U, N, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, m, nb, 1.0, AV(), N, dS, m, 0.0, AU, N, s));
+      TP3B_HIP(launch_gemm_nn_x0<double>(N, nu, nb, -1.0, U, N, dTb, nu, 1.0, AU, N, Rres, N, s));
     }
     std::vector<double> Cq((size_t)std::max(k, 1) * nb, 0.0);  // Q^T A U, column-major k x nb
     std::vector<double> c1((size_t)std::max(k, 1) * nb), c2((size_t)std::max(k, 1) * nb);
@@ -443,6 +463,14 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
         lock_pair.push_back(pair[j]);
         lockres.push_back(rn[j]);
       }
+      // the basis is rotated into Schur order: its first p columns are the
+      // locked vectors, the rest spans the remaining search space
+      if (!ident) {
+        tp3b_status rs = rotate(m);
+        if (rs != TP3B_OK) return rs;
+      }
+      // Q~ holds the same locked vectors as QV
+      TP3B_HIP(hipMemcpyAsync(Qt + (int64_t)k * N, V(), sizeof(double) * N * p, hipMemcpyDeviceToDevice, s));
       if (use_prec) {
         double tp = now();
         tp3b_status ps = apply_prec_impl<double>(op, p, V(), N, PQ + (int64_t)k * N, N, s);
@@ -465,6 +493,10 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     // ---- restart
     if (m + nb > m_max) {
       const int keep = std::max(m_min, nb);
+      if (!ident) {
+        tp3b_status rs = rotate(keep);
+        if (rs != TP3B_OK) return rs;
+      }
       m = keep;
       // Recompute the projected matrix from the kept vectors (limits drift).
       tp3b_status ds = dot(m, m, V(), AV(), M, m);
@@ -479,12 +511,11 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       shift[j] = (rn[j] > o.switch_tol * std::fabs(theta[j])) ? tfar : theta[j];
     std::memcpy(P(r_upShift), shift.data(), sizeof(double) * nb);
     TP3B_HIP(hipMemcpyAsync(dShift, P(r_upShift), sizeof(double) * nb, hipMemcpyHostToDevice, s));
-    const int nqt = k + nb;  // Q~ = QV[:, 0:nqt]
-    const double* Qt = QV;
+    const int nqt = k + nb;  // Q~ = Qt[:, 0:nqt]
     const double* Yq = Qt;   // P^{-1} Q~ H^{-1} (or Q~ without preconditioner)
     if (use_prec) {
       double tp = now();
-      tp3b_status ps = apply_prec_impl<double>(op, nb, V(), N, PQ + (int64_t)k * N, N, s);
+      tp3b_status ps = apply_prec_impl<double>(op, nb, Qt + (int64_t)k * N, N, PQ + (int64_t)k * N, N, s);
       if (ps != TP3B_OK) return ps;
       stats.n_apply_prec += nb;
       stats.t_prec += now() - tp;
