@@ -219,11 +219,73 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int64_t N, int p, int q, double
                       ldx0);
 }
 
+// Long blocks (N >= GEMM_LONG_N rows, p <= GEMM_PB): a fixed grid of
+// workgroups, each of which stages its QB columns of C in LDS once and then
+// strides over the rows, one row per thread over all of p (no partial rows to
+// combine, no barrier inside the loop).  Launching one workgroup per 64 rows
+// instead would stage C and reduce in LDS 2^18 times for a 2D vector of 2^24
+// entries.
+constexpr int64_t GEMM_LONG_N = 1 << 20;
+constexpr int GEMM_LONG_WG = 2048;
+
+template <typename T, int QB>
+__global__ __launch_bounds__(256) void k_gemm_nn_long(int64_t N, int p, int q, double alpha,
+                                                      const T* __restrict__ A, int64_t lda,
+                                                      const double* __restrict__ C, int ldc,
+                                                      double beta, const T* __restrict__ X0,
+                                                      int64_t ldx0, T* __restrict__ Y, int64_t ldy) {
+  __shared__ double Cs[GEMM_PB][QB];
+  const int q0 = blockIdx.y * QB;
+  const int nq = (q - q0 < QB) ? q - q0 : QB;
+  for (int e = threadIdx.x; e < GEMM_PB * QB; e += 256) {
+    const int i = e / QB, j = e % QB;
+    Cs[i][j] = (i < p && j < nq) ? C[i + (int64_t)(q0 + j) * ldc] : 0.0;
+  }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += stride) {
+    double acc[QB];
+#pragma unroll
+    for (int j = 0; j < QB; ++j) acc[j] = 0.0;
+    // eight columns of A per step, fetched before they are used
+    for (int i0 = 0; i0 < p; i0 += 8) {
+      double av[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) av[u] = (i0 + u < p) ? (double)A[r + (int64_t)(i0 + u) * lda] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < p) {
+#pragma unroll
+          for (int j = 0; j < QB; ++j) acc[j] += av[u] * Cs[i0 + u][j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      if (j < nq) {
+        T* y = Y + r + (int64_t)(q0 + j) * ldy;
+        const double old = (beta != 0.0) ? (double)(X0 ? X0[r + (int64_t)(q0 + j) * ldx0] : *y) : 0.0;
+        *y = (T)(beta * old + alpha * acc[j]);
+      }
+    }
+  }
+}
+
 template <typename T>
 hipError_t launch_gemm_nn_x0(int64_t N, int p, int q, double alpha, const T* A, int64_t lda,
                              const double* C, int ldc, double beta, const T* X0, int64_t ldx0, T* Y,
                              int64_t ldy, hipStream_t s) {
   if (N <= 0 || q <= 0) return hipSuccess;
+  if (N >= GEMM_LONG_N && p <= GEMM_PB) {
+    const int64_t rb = (N + 255) / 256;
+    const unsigned gx = (unsigned)(rb < GEMM_LONG_WG ? rb : GEMM_LONG_WG);
+    if (q <= 8)
+      hipLaunchKernelGGL((k_gemm_nn_long<T, 8>), dim3(gx, 1), dim3(256), 0, s, N, p, q, alpha, A, lda,
+                         C, ldc, beta, X0, ldx0, Y, ldy);
+    else
+      hipLaunchKernelGGL((k_gemm_nn_long<T, GEMM_QB>), dim3(gx, (q + GEMM_QB - 1) / GEMM_QB), dim3(256),
+                         0, s, N, p, q, alpha, A, lda, C, ldc, beta, X0, ldx0, Y, ldy);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((N + gemm_rows<true>() - 1) / gemm_rows<true>()), (q + GEMM_QB - 1) / GEMM_QB);
   hipLaunchKernelGGL((k_gemm_nn<T>), grid, dim3(256), 0, s, N, p, q, alpha, A, lda, C, ldc, beta, X0,
                      ldx0, Y, ldy);
@@ -356,7 +418,17 @@ __global__ __launch_bounds__(256) void k_bupdate_diag_red(int64_t N, int b, int 
                                                           T* __restrict__ W) {
   __shared__ double hs[BD_MAXNB];
   bdot_sum_column(b, nb, nchunk, blockIdx.y, part, H, hld, hs);
-  bupdate_row<T>(N, nb, alpha, V, bs, hs, 0, W, (int64_t)blockIdx.x * 256 + threadIdx.x, blockIdx.y);
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += (int64_t)gridDim.x * 256)
+    bupdate_row<T>(N, nb, alpha, V, bs, hs, 0, W, r, blockIdx.y);
+}
+
+// Workgroups per column of the fused Arnoldi kernels: every workgroup first
+// sums the column's partials, so their number is bounded and each strides
+// over many rows.
+constexpr int64_t ARN_WG_PER_COL = 512;
+inline unsigned arn_grid_x(int64_t N) {
+  const int64_t rb = (N + 255) / 256;
+  return (unsigned)(rb < ARN_WG_PER_COL ? (rb > 0 ? rb : 1) : ARN_WG_PER_COL);
 }
 
 template <typename T>
@@ -366,7 +438,7 @@ hipError_t launch_bupdate_diag_red(int64_t N, int b, int nb, double alpha, const
   if (nb > BD_MAXNB) return hipErrorInvalidValue;
   const int rows = bdot_rows(N);
   const int nchunk = (int)((N + rows - 1) / rows);
-  hipLaunchKernelGGL((k_bupdate_diag_red<T>), dim3((unsigned)((N + 255) / 256), b), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_bupdate_diag_red<T>), dim3(arn_grid_x(N), b), dim3(256), 0, s,
                      N, b, nb, nchunk, alpha, V, bs, partial, H, hld, W);
   return hipGetLastError();
 }
@@ -384,8 +456,11 @@ __global__ __launch_bounds__(256) void k_normalize_cols_red(int64_t N, int b, in
                                                             double* __restrict__ hout, int hld) {
   __shared__ double hs[1];
   bdot_sum_column(b, 1, nchunk, blockIdx.y, part, nullptr, 0, hs);
-  normalize_row_n2<T>(N, hs[0], W, Vout, hout, hld, (int64_t)blockIdx.x * 256 + threadIdx.x,
-                      blockIdx.y);
+  const int64_t r0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  // row 0 (N = 0 included) also stores the norm
+  if (r0 == 0 && N == 0) normalize_row_n2<T>(N, hs[0], W, Vout, hout, hld, 0, blockIdx.y);
+  for (int64_t r = r0; r < N; r += (int64_t)gridDim.x * 256)
+    normalize_row_n2<T>(N, hs[0], W, Vout, hout, hld, r, blockIdx.y);
 }
 
 template <typename T>
@@ -394,7 +469,7 @@ hipError_t launch_normalize_cols_red(int64_t N, int b, const double* partial, co
   if (b <= 0) return hipSuccess;
   const int rows = bdot_rows(N);
   const int nchunk = (int)((N + rows - 1) / rows);
-  hipLaunchKernelGGL((k_normalize_cols_red<T>), dim3((unsigned)((N + 255) / 256 + (N == 0)), b),
+  hipLaunchKernelGGL((k_normalize_cols_red<T>), dim3(arn_grid_x(N), b),
                      dim3(256), 0, s, N, b, nchunk, partial, W, Vout, hout, hld);
   return hipGetLastError();
 }
