@@ -20,9 +20,10 @@ reduced 2D size c5r; the 1D workloads c2 and c3 (solve times, applies, errors
 against the oracle's stored eigenvalues) and the 256-instance batch c4; and the
 CPU oracle timed on this host (cpu_baseline).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--gmres-steps S]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--gmres-steps S] [--m-max M]
     python bench.py --apply-sweep c3 [--prec fp64 fp32 bf16x3]   # per-tile apply times
-    python bench.py --counters c5 --prec fp64                     # for rocprofv3 --pmc runs
+    python bench.py --counters c5 --prec fp64 [--kind P]          # for rocprofv3 --pmc runs
+    python bench.py --leg c2                                      # one extra leg alone
 """
 from __future__ import annotations
 
@@ -428,7 +429,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--gmres-steps", type=int, default=3,
                     help="GMRES steps per correction equation in the timed c5 solves")
-    ap.add_argument("--m-max", type=int, default=48,
+    ap.add_argument("--m-max", type=int, default=64,
                     help="search-space size before a restart in the timed c5 solves (m_min = m_max / 2; "
                          "0: the library's default)")
     ap.add_argument("--mixed-steps", type=int, default=0, help="timed mixed solves (0: steps // 2)")
@@ -443,6 +444,8 @@ def main():
     ap.add_argument("--prec", nargs="*", default=None)
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-mb", type=int, default=256)
+    ap.add_argument("--leg", default=None, choices=["c2", "c3", "c4", "c5r"],
+                    help="run one of the extra legs alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
@@ -459,6 +462,13 @@ def main():
     from workloads import config
 
     torch.cuda.init()
+    if args.leg:
+        legs = {"c2": lambda: c2_leg(t3, max(3, args.steps), 3),
+                "c3": lambda: c3_leg(t3, 10, args.apply_reps),
+                "c4": lambda: batched_leg(t3, args.batched_reps, args.batched_seq, 3),
+                "c5r": lambda: c5r_leg(t3, args.gmres_steps)}
+        print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
+        return
     cfg = config("c5")
     nev, b, n = cfg["nev"], cfg["block"], cfg["n"]
     op = t3.Operator.from_config(cfg)
