@@ -43,9 +43,9 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the 2D Hamiltonian apply at c5 (8 vectors, FP64), the
 # two plane passes together: rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by
 # what the counter reads for a 256 MiB device copy in the same run
-# (profiles/hbm_traffic_c5_H_apply_fp64.md).  None until measured for the
-# current kernels.
-TRAFFIC_BYTES = {"c5": None}
+# (profiles/hbm_traffic_c5_plane_passes_fp64.md; 5,500,916 KiB).  Set to None
+# when the plane kernels change until the counters are taken again.
+TRAFFIC_BYTES = {"c5": 5500916 * 1024}
 
 
 def apply_flops(ndim, n, kind="H"):
@@ -515,6 +515,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["fp64"],
                      "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp64"],
                      "traffic": TRAFFIC_BYTES.get("c5"),
+                     "traffic_note": ("HBM bytes per launch, rocprofv3 FETCH_SIZE + WRITE_SIZE scaled "
+                                      "by a 256 MiB copy; the algorithmic bytes are below"),
                      "kernel": ("2D Hamiltonian apply, FP64: k_plane2d<double, P2_SUM> (x slabs) + "
                                 "k_plane2d<double, P2_SUM_V_ACC> (y planes with the potential)"),
                      "launch_flops": launch_flops, "avg_launch_us": h64["us_per_apply"],

@@ -278,12 +278,17 @@ hipError_t launch_gemm_nn_x0(int64_t N, int p, int q, double alpha, const T* A, 
   if (N >= GEMM_LONG_N && p <= GEMM_PB) {
     const int64_t rb = (N + 255) / 256;
     const unsigned gx = (unsigned)(rb < GEMM_LONG_WG ? rb : GEMM_LONG_WG);
+    // A is read once per column block of C: wide blocks for the basis
+    // rotations (q up to m_max), narrow ones where q is a block of vectors
     if (q <= 8)
       hipLaunchKernelGGL((k_gemm_nn_long<T, 8>), dim3(gx, 1), dim3(256), 0, s, N, p, q, alpha, A, lda,
                          C, ldc, beta, X0, ldx0, Y, ldy);
+    else if (q <= GEMM_QB)
+      hipLaunchKernelGGL((k_gemm_nn_long<T, GEMM_QB>), dim3(gx, 1), dim3(256), 0, s, N, p, q, alpha, A,
+                         lda, C, ldc, beta, X0, ldx0, Y, ldy);
     else
-      hipLaunchKernelGGL((k_gemm_nn_long<T, GEMM_QB>), dim3(gx, (q + GEMM_QB - 1) / GEMM_QB), dim3(256),
-                         0, s, N, p, q, alpha, A, lda, C, ldc, beta, X0, ldx0, Y, ldy);
+      hipLaunchKernelGGL((k_gemm_nn_long<T, 32>), dim3(gx, (q + 31) / 32), dim3(256), 0, s, N, p, q,
+                         alpha, A, lda, C, ldc, beta, X0, ldx0, Y, ldy);
     return hipGetLastError();
   }
   dim3 grid((unsigned)((N + gemm_rows<true>() - 1) / gemm_rows<true>()), (q + GEMM_QB - 1) / GEMM_QB);

@@ -182,11 +182,14 @@ int choose_tile(int M, int Nc, int64_t nbatch, bool fp64) {
   // per tile to cover the MFMA and fetch latencies of a short K loop (measured
   // at n = 256, 8 vectors: H apply 20.8 against 22.8 us in FP64, 14.4 against
   // 16.4 us in FP32).
-  (void)fp64;
+  // FP64 skips the 128-wide tiles: under the two-waves-per-SIMD bound their
+  // accumulators spill (n = 1024, 16 vectors: 64 x 64 1.23 ms, 64 x 128
+  // 1.34 ms, 128 x 128 1.41 ms per H apply).
   const int small = TILE_32W8;
   const C cfgs[] = {{TILE_128, 128, 128}, {TILE_64x128, 64, 128}, {TILE_64, 64, 64}, {small, 32, 32}};
   for (const C& c : cfgs) {
     if (c.tm > M || c.tn > Nc) continue;
+    if (fp64 && c.tn > 64) continue;
     int64_t wg = (int64_t)((M + c.tm - 1) / c.tm) * ((Nc + c.tn - 1) / c.tn) * nbatch;
     if (wg >= 1024) return c.id;
   }
