@@ -194,6 +194,7 @@ struct Plane2D {
   T* Y;
   const T* FA1;     // fragments of A and B (P2_FRAG elements each)
   const T* FB1;
+  int same_ab;      // A and B are the same matrix (equal modes): one LDS copy serves both
   // P2_SUM_V_ACC: the potential from a table in vector layout (V), or, when G is
   // set, from separable Gaussian factors:
   //   V = gscale (G[0][i1][r] G[2][i2][c] + G[1][i1][r] G[3][i2][c]),

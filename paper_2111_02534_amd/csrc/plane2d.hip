@@ -467,6 +467,141 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
   }
 }
 
+// ------------------------------------------------------------------------
+// FP64 x slabs with equal x modes: items of four matrices (32-byte pieces).
+//
+// The x-slab pass moves 16-byte pieces that lie 32 KB apart, and its speed is
+// set by that access pattern rather than by the MFMA work.  When the two x
+// modes have the same operator (equal n and L), one LDS copy of its fragments
+// serves both products, which leaves room for items of four y indices
+// (128 KB, unpadded): every position is then one 32-byte piece, read and
+// written by two neighbouring lanes.  The LDS rows are swizzled so that every
+// access of the pass is free of bank conflicts without padding: element (r, c)
+// of matrix t sits at column c ^ p2x_swz(r, t), where bit 4 of the swizzle
+// alternates with r (the two rows read together by one MFMA operand), its
+// bits 1-3 are a permutation of the sixteen rows of a block (the sixteen rows
+// read at one column), and bit 4 also flips between the matrix pairs (0, 1)
+// and (2, 3) (the two halves of a piece, put by neighbouring lanes).
+__device__ __forceinline__ int p2x_swz(int r, int t) {
+  const int q = r & 15;
+  return (((q & 1) << 4) | ((q >> 1) << 1)) ^ ((t >> 1) << 4);
+}
+
+typedef double P2XBuf[4][P2_MAXN][P2_MAXN];
+
+__device__ __forceinline__ double& p2x_at(P2XBuf& w, int t, int r, int c) {
+  return w[t][r][c ^ p2x_swz(r, t)];
+}
+
+// Chunks of an item: 8192 of 16 bytes, chunk g = tid + 1024 u at position
+// p = g / 2 = (r, c) of the 64 x 64 slab, half h = g % 2 (matrices 2h and
+// 2h + 1).  For thread tid: h = tid % 2, c = (tid / 2) % 64 and r = tid / 128
+// + 8 u, so its chunks are u * 8 rows apart.
+__device__ __forceinline__ int p2x_r0(int tid) { return tid >> 7; }
+__device__ __forceinline__ int p2x_c(int tid) { return (tid >> 1) & 63; }
+
+// Persistent workgroups of 1024 threads, one per CU, as k_plane2d; wave w
+// computes row block w % 4 of matrix w / 4 for all four column blocks.
+// Requires: full 64 x 64 slabs, js = 1, nmat % 4 == 0, 16-byte aligned vectors
+// with ldx, ldy even, and FA1 the fragments of both factors.
+template <int PROG>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void k_plane2d_x4(
+    Plane2D<double> a) {
+  __shared__ P2XBuf w;
+  __shared__ double f[P2_FRAG];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int mat = wave >> 2, bi = wave & 3;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t groups = a.nmat / 4;
+  const int64_t total = groups * a.nvec;
+  const int64_t G = gridDim.x;
+  constexpr int PER = 8;  // chunks per thread
+
+  for (int e = tid; e < P2_FRAG; e += 1024) f[e] = a.FA1[e];
+
+  const int h = tid & 1, r0 = p2x_r0(tid), c = p2x_c(tid);
+  // this thread's offset inside an item, and the step between its chunks
+  const int64_t toff = 2 * h + (int64_t)r0 * a.rs + (int64_t)c * a.cs, tstep = 8 * a.rs;
+  double2 pre[PER];
+  auto fetch = [&](int64_t item) {
+    const int64_t v = item / groups, m0 = (item - v * groups) * 4;
+    const double* X = a.X + v * a.ldx + m0 + toff;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) pre[u] = *(const double2*)(X + u * tstep);
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      p2x_at(w, 2 * h, r0 + 8 * u, c) = pre[u].x;
+      p2x_at(w, 2 * h + 1, r0 + 8 * u, c) = pre[u].y;
+    }
+  };
+
+  int64_t item = p2_slot(blockIdx.x, (int)G);
+  if (item < total) {
+    fetch(item);
+    put();
+  }
+  __syncthreads();
+
+  for (; item < total; item += G) {
+    const int64_t nxt = item + G;
+    if (nxt < total) fetch(nxt);
+    d4 acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = d4{0, 0, 0, 0};
+    // A W
+#pragma unroll 2
+    for (int kk = 0; kk < 16; ++kk) {
+      const double af = f[(bi * 16 + kk) * 64 + lane];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = Mma<double>::mma(af, p2x_at(w, mat, 4 * kk + lk, b * 16 + lr), acc[b]);
+    }
+    if (PROG == P2_SEQ2) {
+      // A W -> LDS, then (A W) B^T
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          p2x_at(w, mat, bi * 16 + Mma<double>::row(lk, q), b * 16 + lr) = acc[b][q];
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = d4{0, 0, 0, 0};
+    }
+    // (...) B^T
+#pragma unroll 2
+    for (int kk = 0; kk < 16; ++kk) {
+      const double x = p2x_at(w, mat, bi * 16 + lr, 4 * kk + lk);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = Mma<double>::mma(x, f[(b * 16 + kk) * 64 + lane], acc[b]);
+    }
+    // results staged through LDS, then stored as 32-byte pieces; the stores
+    // are issued after the next item's loads, and the put below waits only
+    // for those (the vector-memory counter drains in issue order)
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) p2x_at(w, mat, bi * 16 + Mma<double>::row(lk, q), b * 16 + lr) = acc[b][q];
+    __syncthreads();
+    {
+      const int64_t v = item / groups, m0 = (item - v * groups) * 4;
+      double* Y = a.Y + v * a.ldy + m0 + toff;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        double2 o;
+        o.x = p2x_at(w, 2 * h, r0 + 8 * u, c);
+        o.y = p2x_at(w, 2 * h + 1, r0 + 8 * u, c);
+        *(double2*)(Y + u * tstep) = o;
+      }
+    }
+    __syncthreads();
+    if (nxt < total) put();
+    __syncthreads();
+  }
+}
+
 template <typename T, int PROG, bool INTERLEAVED>
 static void launch_p2(const Plane2D<T>& a, bool full, bool vec, unsigned grid, hipStream_t s) {
   if (full && vec)
@@ -502,6 +637,20 @@ hipError_t launch_plane2d(const Plane2D<T>& a, hipStream_t s) {
                                   : (a.js % J == 0 && a.rs % J == 0));
   Plane2D<T> b = a;
   const unsigned grid = (unsigned)(items < P2_GRID ? items : P2_GRID);
+  if constexpr (sizeof(T) == 8) {
+    // equal x modes: items of four matrices (32-byte pieces)
+    const bool x4 = a.interleaved && full && vec && a.same_ab && a.nmat % 4 == 0 && a.ldx % 2 == 0 &&
+                    a.ldy % 2 == 0 && (a.prog == P2_SUM || a.prog == P2_SEQ2);
+    if (x4) {
+      const int64_t items4 = (a.nmat / 4) * a.nvec;
+      const unsigned grid4 = (unsigned)(items4 < P2_GRID ? items4 : P2_GRID);
+      if (a.prog == P2_SUM)
+        hipLaunchKernelGGL((k_plane2d_x4<P2_SUM>), dim3(grid4), dim3(1024), 0, s, b);
+      else
+        hipLaunchKernelGGL((k_plane2d_x4<P2_SEQ2>), dim3(grid4), dim3(1024), 0, s, b);
+      return hipGetLastError();
+    }
+  }
   switch (a.prog) {
     case P2_SUM:
       if (a.interleaved) launch_p2<T, P2_SUM, true>(b, full, vec, grid, s);

@@ -377,6 +377,7 @@ tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, in
     p.ldx = ldx; p.ldy = ldy;
     p.X = X; p.Y = Y;
     p.FA1 = d.frK[0]; p.FB1 = d.frK[1];
+    p.same_ab = op->x_same_K;
     TP3B_HIP(tp3b::launch_plane2d(p, s));
     tp3b::Plane2D<T> q{};
     q.prog = tp3b::P2_SUM_V_ACC;
@@ -485,6 +486,7 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
     p.ldx = ldx; p.ldy = ldy;
     p.X = X; p.Y = Y;
     p.FA1 = d.frSi[0]; p.FB1 = d.frSi[1];
+    p.same_ab = op->x_same_S;
     TP3B_HIP(tp3b::launch_plane2d(p, s));
     tp3b::Plane2D<T> q{};
     q.prog = tp3b::P2_SEQ2_DIV;
@@ -1026,6 +1028,10 @@ tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* ou
       // preconditioner work buffer: up to 64 vectors, at most 4 GiB (FP64)
       const int64_t cap = (int64_t)(1ll << 32) / (N * 8);
       op->work_vecs = (int)std::max<int64_t>(1, std::min<int64_t>(64, cap));
+    }
+    if (op->ndim == 2) {
+      op->x_same_K = Kh[0] == Kh[1];
+      op->x_same_S = op->have_prec && pf.S[0] == pf.S[1] && pf.Si[0] == pf.Si[1];
     }
     tp3b_status st = upload_ops<double>(op, op->d64, Kh, pf);
     if (st == TP3B_OK) st = upload_ops<float>(op, op->d32, Kh, pf);

@@ -225,8 +225,9 @@ def test_prec_fp32():
 @pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("fp32", 1e-4)])
 def test_prec_c3_full_size(prec, bar):
     """n = 1024 per coordinate, the 16-vector block of the c3 solves; the first
-    vector against the oracle's Bartels-Stewart solve (R7: 1e-10 in FP64; FP32
-    as at c2)."""
+    vector against the oracle's Bartels-Stewart solve (1e-10 in FP64: the GPU
+    solves in the eigenbases of the mode operators, whose eigenvector matrices
+    are well conditioned; FP32 as at c2)."""
     import torch
     cfg = config("c3")
     t3, P, op = _pair(cfg)

@@ -200,7 +200,7 @@ def test_jdqr_c4_full_batch(inner, steps):
     ref = gold[:, 5:9]
     diff = np.abs(r.evals - ref)
     scale = np.maximum(np.abs(ref), 1.0)
-    # Bars (derivation in the design notes, readings R18 and R21):
+    # Bars:
     # * eigenvalues are compared relative to max(|E|, 1), as residuals are (a
     #   state at the continuum threshold has |E| = 6e-4);
     # * an instance whose pairs all locked at the residual tolerance (both

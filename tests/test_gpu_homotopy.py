@@ -4,8 +4,8 @@
 * tp3b_homotopy_solve fixes v0 for each E0 from the two-body problem, then
   solves the three-body problem, each solve started from the previous Schur
   vectors.  The depths must match Table 1; the three-body ratios E/E0 must
-  match Table 1 (to the 5e-8 to which this grid reproduces the printed
-  values, reading R23) and the same solves started from a random block
+  match Table 1 (to the 5e-8 to which this grid, with its choice of map,
+  reproduces the printed values) and the same solves started from a random block
   (1e-10): the start block changes the path of the iteration, not the
   converged eigenvalues.
 * f_L: the Hamiltonian apply and the eigensolver against the oracle."""

@@ -1,15 +1,18 @@
 """GPU parity of the 2D applies on LDS-resident planes (operators whose four
 mode sizes are all at most 64): the Hamiltonian in two passes (x slabs, then
-y planes with the potential) and the kinetic preconditioner in three passes.
+y planes with the potential) and the kinetic preconditioner in four passes.
 
 Grids cover full 64 x 64 matrices, ragged ones (sizes that are not multiples
-of the 16 x 16 MFMA blocks), group counts that do not divide by the matrices
-a workgroup holds (odd n_y^2 for FP64, n_y^2 not a multiple of 4 for FP32),
+of the 16 x 16 MFMA blocks), equal full x modes (the FP64 x passes then take
+items of four matrices with one shared factor) and unequal ones, group counts
+that do not divide by the matrices a workgroup holds (odd n_y^2 for FP64, n_y^2
+not a multiple of 4 for FP32),
 every potential form (separable Gaussian factors, point-by-point table,
 Lorentzian cube), shifted applies, strided blocks, and the fallback of larger
 modes to the three single-mode passes.  Bars: FP64 1e-12 normwise against the
-oracle's tensor apply (1e-10 for the preconditioner against its
-Bartels-Stewart solve, R7), FP32 1e-5 / 2e-5."""
+oracle's tensor apply (1e-10 for the preconditioner, which the GPU applies in
+the eigenbases of the mode operators, against the oracle's Bartels-Stewart
+solve), FP32 1e-5 / 2e-5."""
 import numpy as np
 import pytest
 
@@ -24,6 +27,8 @@ GRIDS = [
     ((64, 64, 9, 9), (12.0, 12.0, 6.0, 6.0)),      # full x slabs, ragged y planes
     ((7, 7, 5, 5), (6.0, 6.0, 5.0, 5.0)),          # tiny
     ((16, 16, 64, 64), (6.0, 6.0, 9.0, 9.0)),      # full y planes, Ny a multiple of 4
+    ((64, 64, 8, 8), (12.0, 12.0, 6.0, 6.0)),      # equal full x modes: FP64 four-matrix x items
+    ((64, 64, 6, 6), (12.0, 11.0, 6.0, 6.0)),      # full x slabs, unequal x modes
 ]
 
 

@@ -185,11 +185,11 @@ def test_jdqr_c3_full_size():
     FP64, FP32 and BF16x3 inner solves: each within 1e-10 of the oracle's stored
     eigenvalues (|dE| / |E|; the oracle's values come from its four parity
     sectors).  Properties that hold at any size: the FP64 and FP32-inner
-    solves' eigenvalues agree to 1e-10 (|dE| / max(|E|, 1), R21); the Schur
+    solves' eigenvalues agree to 1e-10 (|dE| / max(|E|, 1)); the Schur
     vectors are orthonormal to 1e-12; and the oracle's own apply of H to them
     gives partial-Schur residuals ||H q_j - Q R[:, j]|| within the loosest
-    locking bar, 1e-8 max(|R_jj|, 1) (R18), plus the FP64 floor of forming
-    H q_j on either side: 4 (n_x + n_y + 1) eps || |H| |q_j| || (R21; at
+    locking bar, 1e-8 max(|R_jj|, 1) (the stall lock), plus the FP64 floor of
+    forming H q_j on either side: 4 (n_x + n_y + 1) eps || |H| |q_j| || (at
     n = 1024, ||H|| is about 6e9, so that floor is of the order of 1e-8)."""
     import torch
     t3 = need_gpu()

@@ -393,7 +393,7 @@ def test_mapped_parity_table1_lowest_states():
     (even under heavy exchange x -> -x) and fermionic (odd) ratios E/E0 to the
     printed 8 digits, on the paper's grid: mapped Chebyshev, parity half grids,
     N_y = N_x / 2 (128 x 64 points, map parameters 8 and 4).  This fixes the
-    Jacobi combination y -+ x/2 (R2), the paper units, the mapped second
+    Jacobi combination y -+ x/2 (x the heavy-heavy coordinate), the paper units, the mapped second
     derivative and the parity selection together."""
     row = _table1()[0]
     E0 = row[0]
