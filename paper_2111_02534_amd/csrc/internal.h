@@ -104,6 +104,8 @@ struct tp3b_op_s {
   bool plane2d = false;         // 2D with every mode size <= P2_MAXN: two-pass applies
   bool x_same_K = false;        // 2D: the two x modes have the same operator K (and
   bool x_same_S = false;        // the same eigen-factors): one LDS copy in the x passes
+  bool y_same_K = false;        // the same for the two y modes (y-plane passes)
+  bool y_same_S = false;
   std::vector<double> Gh;       // separable Gaussian factors of V (plane2d, Gaussian shapes)
   double gscale = 0;            // -v0 for those factors
   // tile choice: explicit override, else autotuned [tp3b_prec][0 = H, 1 = prec],

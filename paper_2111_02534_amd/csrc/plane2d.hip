@@ -602,6 +602,182 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
   }
 }
 
+// ------------------------------------------------------------------------
+// y planes with equal y modes: one plane per item, two workgroups per CU.
+//
+// With one workgroup per CU the MFMA pipes idle while a workgroup waits for
+// its barrier, its next item's loads and its stores.  When the two y modes
+// have the same operator one LDS copy of its fragments serves both products,
+// and a workgroup that holds one plane (padded, 33 KB) and that copy (32 KB)
+// leaves room for a second workgroup on the CU, whose products fill those
+// gaps.  Eight waves per workgroup; wave w computes row block w % 4 and the
+// column blocks 2 (w / 4), 2 (w / 4) + 1 of the plane.  Requires full,
+// contiguous 64 x 64 planes (rs = 64, cs = 1), js a multiple of
+// 16 / sizeof(T), 16-byte aligned vectors with ld a multiple of 16 / sizeof(T),
+// and FA1 the fragments of both factors.
+template <typename T>
+struct P2Y {
+  static constexpr int E = 16 / (int)sizeof(T);     // elements per 16-byte chunk
+  static constexpr int NT = 512;
+  static constexpr int PER = P2_MAXN * P2_MAXN / E / NT;  // chunks per thread
+  static constexpr int LD = P2_MAXN + 1;
+};
+
+template <typename T, int PROG>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_plane2d_y1(
+    Plane2D<T> a) {
+  typedef P2Y<T> S;
+  typedef typename P2Vec<T>::v vec_t;
+  typedef typename Mma<T>::acc_t acc_t;
+  constexpr int E = S::E, CPR = P2_MAXN / E;
+  __shared__ T w[P2_MAXN][S::LD];
+  __shared__ T f[P2_FRAG];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bi = wave & 3, bj0 = (wave >> 2) * 2;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t total = a.nmat * a.nvec;
+  const int64_t G = gridDim.x;
+
+  for (int e = tid; e < P2_FRAG; e += S::NT) f[e] = a.FA1[e];
+  T lamr[4], lamc[2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) lamr[q] = (PROG == P2_SEQ2_DIV) ? a.lamR[bi * 16 + Mma<T>::row(lk, q)] : T(0);
+#pragma unroll
+  for (int b = 0; b < 2; ++b) lamc[b] = (PROG == P2_SEQ2_DIV) ? a.lamC[(bj0 + b) * 16 + lr] : T(0);
+
+  vec_t pre[S::PER];
+  auto fetch = [&](int64_t item) {
+    const int64_t v = item / a.nmat, m = item - v * a.nmat;
+    const T* X = a.X + v * a.ldx + m * a.js;
+    // rows are contiguous (rs = 64), so chunk q starts at element E q
+#pragma unroll
+    for (int u = 0; u < S::PER; ++u) pre[u] = *(const vec_t*)(X + E * (tid + u * S::NT));
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int u = 0; u < S::PER; ++u) {
+      const int q = tid + u * S::NT, r = q / CPR, c0 = (q % CPR) * E;
+#pragma unroll
+      for (int t = 0; t < E; ++t) w[r][c0 + t] = P2Vec<T>::get(pre[u], t);
+    }
+  };
+
+  int64_t item = p2_slot(blockIdx.x, (int)G);
+  if (item < total) {
+    fetch(item);
+    put();
+  }
+  __syncthreads();
+
+  for (; item < total; item += G) {
+    const int64_t v = item / a.nmat, m = item - v * a.nmat;
+    const int64_t nxt = item + G;
+    T* Y = a.Y + v * a.ldy + m * a.js;
+    // this lane's output elements: Yl[(4 q) * 64 + 16 b]
+    T* Yl = Y + (bi * 16 + lk) * P2_MAXN + bj0 * 16 + lr;
+    // the epilogue's global operands first (their wait does not include the
+    // next item's loads, which are issued after them)
+    T tacc[2][4];
+    if (PROG == P2_SUM_V_ACC) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          tacc[b][q] = Yl[(Mma<T>::row(lk, q) - lk) * P2_MAXN + b * 16];
+    }
+    if (nxt < total) fetch(nxt);
+    acc_t acc[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[b] = acc_t{0, 0, 0, 0};
+    // A W
+#pragma unroll 2
+    for (int kk = 0; kk < 16; ++kk) {
+      const T af = f[(bi * 16 + kk) * 64 + lane];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[b] = Mma<T>::mma(af, w[4 * kk + lk][(bj0 + b) * 16 + lr], acc[b]);
+    }
+    if (PROG == P2_SEQ2 || PROG == P2_SEQ2_DIV) {
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[bi * 16 + Mma<T>::row(lk, q)][(bj0 + b) * 16 + lr] = acc[b][q];
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[b] = acc_t{0, 0, 0, 0};
+    }
+    // (...) B^T
+#pragma unroll 2
+    for (int kk = 0; kk < 16; ++kk) {
+      const T x = w[bi * 16 + lr][4 * kk + lk];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[b] = Mma<T>::mma(x, f[((bj0 + b) * 16 + kk) * 64 + lane], acc[b]);
+    }
+    // epilogue (the potential's factor tables are small and stay in the L2;
+    // they are read here rather than with the x part, which keeps the
+    // registers of the products below the bound for two workgroups per CU)
+    if (PROG == P2_SUM_V_ACC) {
+      const double shift = a.shifts ? a.shifts[v] : 0.0;
+      T g1[2][4], g2[2][2];
+      if (a.G) {
+        const int md = a.mdiv > 0 ? a.mdiv : 1;
+        const int i1 = (int)(m / md), i2 = (int)(m % md);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = bi * 16 + Mma<T>::row(lk, q);
+          g1[0][q] = a.G[i1 * P2_MAXN + r];
+          g1[1][q] = a.G[P2_MAXN * P2_MAXN + i1 * P2_MAXN + r];
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int c = (bj0 + b) * 16 + lr;
+          g2[0][b] = a.G[2 * P2_MAXN * P2_MAXN + i2 * P2_MAXN + c];
+          g2[1][b] = a.G[3 * P2_MAXN * P2_MAXN + i2 * P2_MAXN + c];
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int c = (bj0 + b) * 16 + lr;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = bi * 16 + Mma<T>::row(lk, q);
+          const T pot = a.G ? T(a.gscale) * (g1[0][q] * g2[0][b] + g1[1][q] * g2[1][b]) : T(0);
+          acc[b][q] += (pot - T(shift)) * w[r][c] + tacc[b][q];
+        }
+      }
+      if (!a.G && a.V) {
+        // potential from the table
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = bi * 16 + Mma<T>::row(lk, q), c = (bj0 + b) * 16 + lr;
+            acc[b][q] += a.V[m * a.js + r * P2_MAXN + c] * w[r][c];
+          }
+      }
+    } else if (PROG == P2_SEQ2_DIV) {
+      const T lm = a.lamM[m] - T(a.sigma);
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[b][q] = acc[b][q] / (lm + lamr[q] + lamc[b]);
+    }
+    // the next item goes into LDS once every wave is done with this one, and
+    // before this item's stores are issued
+    __syncthreads();
+    if (nxt < total) put();
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        Yl[(Mma<T>::row(lk, q) - lk) * P2_MAXN + b * 16] = acc[b][q];
+    __syncthreads();
+  }
+}
+
+// Two workgroups per CU.
+constexpr int P2Y_GRID = 512;
+
 template <typename T, int PROG, bool INTERLEAVED>
 static void launch_p2(const Plane2D<T>& a, bool full, bool vec, unsigned grid, hipStream_t s) {
   if (full && vec)
@@ -650,6 +826,20 @@ hipError_t launch_plane2d(const Plane2D<T>& a, hipStream_t s) {
         hipLaunchKernelGGL((k_plane2d_x4<P2_SEQ2>), dim3(grid4), dim3(1024), 0, s, b);
       return hipGetLastError();
     }
+  }
+  // equal y modes: one plane per item, two workgroups per CU
+  const bool y1 = !a.interleaved && full && vec && a.same_ab && a.cs == 1 && a.rs == P2_MAXN &&
+                  (a.prog == P2_SUM_V_ACC || a.prog == P2_SEQ2 || a.prog == P2_SEQ2_DIV);
+  if (y1) {
+    const int64_t items1 = a.nmat * a.nvec;
+    const unsigned grid1 = (unsigned)(items1 < P2Y_GRID ? items1 : P2Y_GRID);
+    if (a.prog == P2_SUM_V_ACC)
+      hipLaunchKernelGGL((k_plane2d_y1<T, P2_SUM_V_ACC>), dim3(grid1), dim3(512), 0, s, b);
+    else if (a.prog == P2_SEQ2)
+      hipLaunchKernelGGL((k_plane2d_y1<T, P2_SEQ2>), dim3(grid1), dim3(512), 0, s, b);
+    else
+      hipLaunchKernelGGL((k_plane2d_y1<T, P2_SEQ2_DIV>), dim3(grid1), dim3(512), 0, s, b);
+    return hipGetLastError();
   }
   switch (a.prog) {
     case P2_SUM:

@@ -389,6 +389,7 @@ tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, in
     q.ldx = ldx; q.ldy = ldy;
     q.X = X; q.Y = Y;
     q.FA1 = d.frK[2]; q.FB1 = d.frK[3];
+    q.same_ab = op->y_same_K;
     q.V = d.V;
     q.G = d.G;
     q.mdiv = nx2;
@@ -498,6 +499,7 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
     q.ldx = ldy; q.ldy = ldy;
     q.X = Y; q.Y = Y;
     q.FA1 = d.frSi[2]; q.FB1 = d.frSi[3];
+    q.same_ab = op->y_same_S;
     q.lamM = d.lamItem; q.lamR = d.lam[2]; q.lamC = d.lam[3];
     q.sigma = op->sigma;
     TP3B_HIP(tp3b::launch_plane2d(q, s));
@@ -1032,6 +1034,8 @@ tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* ou
     if (op->ndim == 2) {
       op->x_same_K = Kh[0] == Kh[1];
       op->x_same_S = op->have_prec && pf.S[0] == pf.S[1] && pf.Si[0] == pf.Si[1];
+      op->y_same_K = Kh[2] == Kh[3];
+      op->y_same_S = op->have_prec && pf.S[2] == pf.S[3] && pf.Si[2] == pf.Si[3];
     }
     tp3b_status st = upload_ops<double>(op, op->d64, Kh, pf);
     if (st == TP3B_OK) st = upload_ops<float>(op, op->d32, Kh, pf);

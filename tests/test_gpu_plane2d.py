@@ -29,6 +29,7 @@ GRIDS = [
     ((16, 16, 64, 64), (6.0, 6.0, 9.0, 9.0)),      # full y planes, Ny a multiple of 4
     ((64, 64, 8, 8), (12.0, 12.0, 6.0, 6.0)),      # equal full x modes: FP64 four-matrix x items
     ((64, 64, 6, 6), (12.0, 11.0, 6.0, 6.0)),      # full x slabs, unequal x modes
+    ((16, 16, 64, 64), (6.0, 6.0, 9.0, 8.5)),      # full y planes, unequal y modes
 ]
 
 
@@ -64,13 +65,15 @@ def test_apply_2d_planes(grid, prec):
         assert err <= bar
 
 
+@pytest.mark.parametrize("n", [(20, 20, 13, 13), (8, 8, 64, 64)])
 @pytest.mark.parametrize("shape,table", [("gauss", True), ("lorentz3", False), ("gauss_paper", False)])
-def test_apply_2d_planes_potential_forms(shape, table):
+def test_apply_2d_planes_potential_forms(shape, table, n):
     """The point-by-point table and the non-separable Lorentzian read V from the
-    table in the epilogue; the Gaussians use their separable factors."""
+    table in the epilogue; the Gaussians use their separable factors (ragged
+    planes, and full planes with equal y modes: one plane per work item)."""
     import torch
     t3 = need_gpu()
-    n, L = (20, 20, 13, 13), (8.0, 8.0, 6.0, 6.0)
+    L = (8.0, 8.0, 6.0, 6.0)
     op, P = _pair(t3, n, L, v0=2.5, width=0.8, shape=shape, table=table)
     Xn = normal_block(P.N, 4, 71)
     X = to_dev(Xn)
@@ -83,14 +86,16 @@ def test_apply_2d_planes_potential_forms(shape, table):
     assert err <= 1e-12
 
 
-def test_apply_2d_planes_shifted_and_strided():
-    """(H - s_v) X on a block whose leading dimension is N + 3 (unaligned
-    vectors), against the oracle's apply minus the shift."""
+@pytest.mark.parametrize("n,pad", [((20, 20, 13, 13), 3), ((8, 8, 64, 64), 2)])
+def test_apply_2d_planes_shifted_and_strided(n, pad):
+    """(H - s_v) X on a block whose leading dimension is N + pad (N + 3:
+    unaligned vectors; N + 2 on full equal-mode planes: aligned, the one-plane
+    y pass), against the oracle's apply minus the shift."""
     import torch
     t3 = need_gpu()
-    n, L = (20, 20, 13, 13), (15.0, 15.0, 15.0, 15.0)
+    L = (15.0, 15.0, 15.0, 15.0)
     op, P = _pair(t3, n, L)
-    nvec, ld = 3, P.N + 3
+    nvec, ld = 3, P.N + pad
     Xn = normal_block(P.N, nvec, 72)
     Xb = torch.zeros((nvec, ld), dtype=torch.float64, device="cuda")
     Xb[:, :P.N] = to_dev(Xn)
