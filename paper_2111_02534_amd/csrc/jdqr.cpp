@@ -377,7 +377,7 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     const int nb = std::min(b, m);
     // a 2 x 2 block across the block edge couples u_nb into the residual of
     // column nb - 1
-    const int nu = std::min(m, nb + 1);
+    const int nu = (nb < m && T[(size_t)nb * m + (nb - 1)] != 0.0) ? nb + 1 : nb;
     // ---- 2. U = V S[:, :nu] (into Q~ after the locked vectors), A U, and the
     // residuals R = (I - Q Q^T)(A U - U T[:nu, :nb])
     {
