@@ -40,12 +40,12 @@ sys.path.insert(0, ROOT)
 METRIC = "H-apply GFLOP/s (% MFMA peak); JDQR s to k eigenpairs @1e-10, mixed vs FP64"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the 2D Hamiltonian apply at c5 (8 vectors, FP64), the
-# two plane passes together: rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by
+# HBM bytes per 8-vector apply of the 2D Hamiltonian at c5 (FP64; the two plane
+# passes, run vector by vector): rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by
 # what the counter reads for a 256 MiB device copy in the same run
-# (profiles/hbm_traffic_c5_plane_passes_fp64.md; 5,644,280 KiB).  Set to None
+# (profiles/hbm_traffic_c5_plane_passes_fp64.md; 5,671,854 KiB).  Set to None
 # when the plane kernels change until the counters are taken again.
-TRAFFIC_BYTES = {"c5": None}
+TRAFFIC_BYTES = {"c5": 5671854 * 1024}
 
 
 def apply_flops(ndim, n, kind="H"):
@@ -525,8 +525,8 @@ def main():
                      "traffic": TRAFFIC_BYTES.get("c5"),
                      "traffic_note": ("HBM bytes per launch, rocprofv3 FETCH_SIZE + WRITE_SIZE scaled "
                                       "by a 256 MiB copy; the algorithmic bytes are below"),
-                     "kernel": ("2D Hamiltonian apply, FP64: k_plane2d<double, P2_SUM> (x slabs) + "
-                                "k_plane2d<double, P2_SUM_V_ACC> (y planes with the potential)"),
+                     "kernel": ("2D Hamiltonian apply, FP64, per vector: k_plane2d_x4<P2_SUM> (x slabs) + "
+                                "k_plane2d_y1<double, P2_SUM_V_ACC> (y planes with the potential)"),
                      "launch_flops": launch_flops, "avg_launch_us": h64["us_per_apply"],
                      "algorithmic_bytes": b * apply_bytes(2, n, 8),
                      "achieved_GBs": b * apply_bytes(2, n, 8) / (h64["us_per_apply"] * 1e-6) / 1e9},
