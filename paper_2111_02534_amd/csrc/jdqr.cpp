@@ -262,8 +262,16 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   int* dFlag = (int*)(dTb + (size_t)(b + 1) * b);  // singular projected preconditioner
   int* dOFlags = dFlag + 2;                    // expansion block: b dependence flags, non-finite
   TP3B_HIP(hipMemsetAsync(dFlag, 0, sizeof(int), s));
+  // long blocks: the Arnoldi updates are fused with the dots that follow them
+  // (two partial areas: the pass-1 dots and the norm in the first, the
+  // pass-2 dots in the second)
+  const bool arn_fused = N >= (int64_t)(1 << 20) && steps + 1 <= BDF_MAXNB;
+  const int64_t part_b_off =
+      std::max(bdot_scratch_doubles(N, b, 1), bupdate_dot_scratch_doubles(N, b));
+  const int nch_f = bupdate_dot_chunks(N);
   const int64_t dscr = dot_scratch_doubles(N, qt_max + m_max + b, qt_max + m_max + b) +
                        bdot_scratch_doubles(N, b, steps + 2) + 8 * (int64_t)(qv_cols + 1) * b +
+                       2 * bupdate_dot_scratch_doubles(N, b) +
                        8 * (int64_t)b * b + 1024;
   double* part = dot_scratch(dscr);
   if (!part) return fail(TP3B_ENOMEM, "jdqr: scratch allocation failed");
@@ -596,12 +604,25 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
         // CGS2 against the basis, then the norm; each update sums its dot's
         // partials itself (no separate reduction launch)
         TP3B_HIP(launch_bdot_partials<TW>(N, nb, kk + 1, Vg, bs, w, part, s));
-        TP3B_HIP(launch_bupdate_diag_red<TW>(N, nb, kk + 1, -1.0, Vg, bs, part, h1, hld, w, s));
-        TP3B_HIP(launch_bdot_partials<TW>(N, nb, kk + 1, Vg, bs, w, part, s));
-        TP3B_HIP(launch_bupdate_diag_red<TW>(N, nb, kk + 1, -1.0, Vg, bs, part, h2, hld, w, s));
-        TP3B_HIP(launch_bdot_partials<TW>(N, nb, 1, w, 0, w, part, s));
-        TP3B_HIP(launch_normalize_cols_red<TW>(N, nb, part, w, Vg + (int64_t)(kk + 1) * bs,
-                                               dHs + (size_t)kk * b, 1, s));
+        if (arn_fused) {
+          // each update also forms the partials of the next dots on the rows
+          // it has just written (the second pass's dots, then the norm), so
+          // the basis and w are not read again for them
+          double* part_b = part + part_b_off;
+          TP3B_HIP(launch_bupdate_dot_red<TW>(N, nb, kk + 1, -1.0, Vg, bs, part, 0, h1, hld, w, 0,
+                                               part_b, s));
+          TP3B_HIP(launch_bupdate_dot_red<TW>(N, nb, kk + 1, -1.0, Vg, bs, part_b, nch_f, h2, hld, w, 1,
+                                               part, s));
+          TP3B_HIP(launch_normalize_cols_red_n<TW>(N, nb, part, nch_f, w, Vg + (int64_t)(kk + 1) * bs,
+                                                   dHs + (size_t)kk * b, 1, s));
+        } else {
+          TP3B_HIP(launch_bupdate_diag_red<TW>(N, nb, kk + 1, -1.0, Vg, bs, part, h1, hld, w, s));
+          TP3B_HIP(launch_bdot_partials<TW>(N, nb, kk + 1, Vg, bs, w, part, s));
+          TP3B_HIP(launch_bupdate_diag_red<TW>(N, nb, kk + 1, -1.0, Vg, bs, part, h2, hld, w, s));
+          TP3B_HIP(launch_bdot_partials<TW>(N, nb, 1, w, 0, w, part, s));
+          TP3B_HIP(launch_normalize_cols_red<TW>(N, nb, part, w, Vg + (int64_t)(kk + 1) * bs,
+                                                 dHs + (size_t)kk * b, 1, s));
+        }
       }
       // least squares on the device, then t_j = V_j y_j (FP64 copy in Tc)
       TP3B_HIP(launch_gmres_lstsq(nb, b, steps, hld, dH1, dH2, dHs, dBeta, dY, s));

@@ -133,6 +133,29 @@ template <typename T>
 hipError_t launch_normalize_cols_red(int64_t N, int b, const double* partial, const T* W, T* Vout,
                                      double* hout, int hld, hipStream_t s);
 
+// One Arnoldi update fused with the dots that follow it (long blocks).
+// Sums the column's partials of the preceding dots (`part_in`, written by
+// launch_bdot_partials when nchunk_in == 0, else by this launch with
+// nchunk_in = bupdate_dot_chunks(N)), stores them to H and applies
+// W[r, j] += alpha * sum_{i<nb} Vb[i][r, j] H[j*hld + i] as
+// launch_bupdate_diag_red does; then, on the updated rows, the partials of
+// the next dots into `part_out`: with Vb[i] for i < nb when `self` is 0 (the
+// second Gram-Schmidt pass), or W[:, j] with itself when `self` is 1 (the
+// squared norm).  The consumer of `part_out` takes nchunk =
+// bupdate_dot_chunks(N).  part_out must not overlap part_in.  nb <= BDF_MAXNB.
+constexpr int BDF_MAXNB = 16;
+int bupdate_dot_chunks(int64_t N);
+int64_t bupdate_dot_scratch_doubles(int64_t N, int b);
+template <typename T>
+hipError_t launch_bupdate_dot_red(int64_t N, int b, int nb, double alpha, const T* V, int64_t bs,
+                                  const double* part_in, int nchunk_in, double* H, int hld, T* W,
+                                  int self, double* part_out, hipStream_t s);
+// launch_bupdate_diag_red / launch_normalize_cols_red with the partials of a
+// launch_bupdate_dot_red (nchunk = bupdate_dot_chunks(N)).
+template <typename T>
+hipError_t launch_normalize_cols_red_n(int64_t N, int b, const double* partial, int nchunk,
+                                       const T* W, T* Vout, double* hout, int hld, hipStream_t s);
+
 // Y[:, j] = alpha * X[:, j] (type conversion included); X == nullptr: Y = 0.
 template <typename TI, typename TO>
 hipError_t launch_convert(int64_t N, int ncol, double alpha, const TI* X, int64_t ldx, TO* Y,

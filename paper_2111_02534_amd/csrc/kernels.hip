@@ -483,6 +483,109 @@ template hipError_t launch_normalize_cols_red<double>(int64_t, int, const double
 template hipError_t launch_normalize_cols_red<float>(int64_t, int, const double*, const float*,
                                                      float*, double*, int, hipStream_t);
 
+template <typename T>
+hipError_t launch_normalize_cols_red_n(int64_t N, int b, const double* partial, int nchunk,
+                                       const T* W, T* Vout, double* hout, int hld, hipStream_t s) {
+  if (b <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_normalize_cols_red<T>), dim3(arn_grid_x(N), b), dim3(256), 0, s, N, b, nchunk,
+                     partial, W, Vout, hout, hld);
+  return hipGetLastError();
+}
+template hipError_t launch_normalize_cols_red_n<double>(int64_t, int, const double*, int, const double*,
+                                                        double*, double*, int, hipStream_t);
+template hipError_t launch_normalize_cols_red_n<float>(int64_t, int, const double*, int, const float*,
+                                                       float*, double*, int, hipStream_t);
+
+// ----------------------------- Arnoldi update fused with the following dots
+int bupdate_dot_chunks(int64_t N) { return (int)arn_grid_x(N); }
+int64_t bupdate_dot_scratch_doubles(int64_t N, int b) {
+  return (int64_t)bupdate_dot_chunks(N) * b * BD_MAXNB;
+}
+
+template <typename T, int NBM>
+__global__ __launch_bounds__(256) void k_bupdate_dot_red(int64_t N, int b, int nb, int nchunk_in,
+                                                         double alpha, const T* __restrict__ V,
+                                                         int64_t bs, const double* __restrict__ part_in,
+                                                         double* __restrict__ H, int hld,
+                                                         T* __restrict__ W, int self,
+                                                         double* __restrict__ part_out) {
+  __shared__ double hs[BD_MAXNB];
+  __shared__ double red[NBM][4];
+  const int j = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  bdot_sum_column(b, nb, nchunk_in, j, part_in, H, hld, hs);
+  double acc[NBM];
+#pragma unroll
+  for (int i = 0; i < NBM; ++i) acc[i] = 0.0;
+  T* Wj = W + (int64_t)j * N;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += (int64_t)gridDim.x * 256) {
+    // the update of bupdate_row (same terms, same order), keeping the basis
+    // values for the dots
+    double v[NBM];
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < NBM; ++i) {
+      const double h = (i < nb) ? hs[i] : 0.0;
+      v[i] = (i < nb && (h != 0.0 || !self)) ? (double)V[(int64_t)i * bs + (int64_t)j * N + r] : 0.0;
+    }
+    // ascending i, as bupdate_row adds them
+#pragma unroll
+    for (int i = 0; i < NBM; ++i) {
+      const double h = (i < nb) ? hs[i] : 0.0;
+      if (h != 0.0) sum += v[i] * h;
+    }
+    const T wn = (T)((double)Wj[r] + alpha * sum);
+    Wj[r] = wn;
+    const double wd = (double)wn;
+    if (self) {
+      acc[0] += wd * wd;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NBM; ++i)
+        if (i < nb) acc[i] += v[i] * wd;
+    }
+  }
+  const int nd = self ? 1 : nb;
+#pragma unroll
+  for (int i = 0; i < NBM; ++i) {
+    if (i < nd) {
+      double x = acc[i];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+      if (lane == 0) red[i][wave] = x;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nd)
+    part_out[((int64_t)blockIdx.x * b + j) * BD_MAXNB + threadIdx.x] =
+        red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+}
+
+template <typename T>
+hipError_t launch_bupdate_dot_red(int64_t N, int b, int nb, double alpha, const T* V, int64_t bs,
+                                  const double* part_in, int nchunk_in, double* H, int hld, T* W,
+                                  int self, double* part_out, hipStream_t s) {
+  if (N <= 0 || b <= 0) return hipSuccess;
+  if (nb < 1 || nb > BDF_MAXNB || part_in == part_out) return hipErrorInvalidValue;
+  const int nin = nchunk_in > 0 ? nchunk_in : (int)((N + bdot_rows(N) - 1) / bdot_rows(N));
+  // register arrays sized for the basis length (a few GMRES steps: 4)
+  if (nb <= 4)
+    hipLaunchKernelGGL((k_bupdate_dot_red<T, 4>), dim3(arn_grid_x(N), b), dim3(256), 0, s, N, b, nb, nin,
+                       alpha, V, bs, part_in, H, hld, W, self, part_out);
+  else if (nb <= 8)
+    hipLaunchKernelGGL((k_bupdate_dot_red<T, 8>), dim3(arn_grid_x(N), b), dim3(256), 0, s, N, b, nb, nin,
+                       alpha, V, bs, part_in, H, hld, W, self, part_out);
+  else
+    hipLaunchKernelGGL((k_bupdate_dot_red<T, BDF_MAXNB>), dim3(arn_grid_x(N), b), dim3(256), 0, s, N, b,
+                       nb, nin, alpha, V, bs, part_in, H, hld, W, self, part_out);
+  return hipGetLastError();
+}
+template hipError_t launch_bupdate_dot_red<double>(int64_t, int, int, double, const double*, int64_t,
+                                                   const double*, int, double*, int, double*, int,
+                                                   double*, hipStream_t);
+template hipError_t launch_bupdate_dot_red<float>(int64_t, int, int, double, const float*, int64_t,
+                                                  const double*, int, double*, int, float*, int,
+                                                  double*, hipStream_t);
+
 // -------------------------------------------------------------- conversions
 template <typename TI, typename TO>
 __global__ void k_convert(int64_t N, double alpha, const TI* __restrict__ X, int64_t ldx,
