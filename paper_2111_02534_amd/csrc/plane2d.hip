@@ -21,7 +21,11 @@
 // preconditioner instead of 128 B for eight.
 //
 // Every pass applies two constant n x n factors, held in LDS in MFMA fragment
-// order (32 KB each in FP64) next to the work item (J matrices, 65 KB).
+// order (32 KB each in FP64) next to the work item (J matrices, 65 KB).  When
+// the two modes of a pass have the same operator (equal n and L), one copy
+// serves both products, and two more shapes use the LDS this frees:
+// k_plane2d_x4 (FP64 x slabs, items of four matrices: 32-byte pieces) and
+// k_plane2d_y1 (y planes, one plane per item, two workgroups per CU).
 #include <hip/hip_runtime.h>
 
 #include "device_bodies.h"
