@@ -18,6 +18,7 @@
 // the converged pairs meet the FP64 residual tolerance whatever the inner
 // precision.
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 #include <chrono>
 #include <cmath>
@@ -576,10 +577,20 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
     const int64_t bs = N * nb;
     auto gmres_launch = [&]() -> tp3b_status {
       TW* rhs = W;
+      // sign of the final combination: an FP64 inner solve preconditions r
+      // itself, so it runs on -rhs; GMRES is odd in its right-hand side and
+      // negation is exact, so the negated combination is the same correction
+      double t_sign = 1.0;
       if (use_prec) {
-        TP3B_HIP((launch_convert<double, TW>(N, nb, -1.0, Rres, N, Zt, N, s)));
-        tp3b_status ps = precond_w(Zt, rhs);
-        if (ps != TP3B_OK) return ps;
+        if constexpr (std::is_same<TW, double>::value) {
+          tp3b_status ps = precond_w(Rres, rhs);
+          if (ps != TP3B_OK) return ps;
+          t_sign = -1.0;
+        } else {
+          TP3B_HIP((launch_convert<double, TW>(N, nb, -1.0, Rres, N, Zt, N, s)));
+          tp3b_status ps = precond_w(Zt, rhs);
+          if (ps != TP3B_OK) return ps;
+        }
       } else {
         TP3B_HIP((launch_convert<double, TW>(N, nb, -1.0, Rres, N, rhs, N, s)));
       }
@@ -624,11 +635,9 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
                                                  dHs + (size_t)kk * b, 1, s));
         }
       }
-      // least squares on the device, then t_j = V_j y_j (FP64 copy in Tc)
+      // least squares on the device, then t_j = V_j y_j, written in FP64 into Tc
       TP3B_HIP(launch_gmres_lstsq(nb, b, steps, hld, dH1, dH2, dHs, dBeta, dY, s));
-      TP3B_HIP((launch_convert<TW, TW>(N, nb, 0.0, (const TW*)nullptr, N, W, N, s)));
-      TP3B_HIP(launch_bupdate_diag<TW>(N, nb, steps, 1.0, Vg, bs, dY, hld, W, s));
-      TP3B_HIP((launch_convert<TW, double>(N, nb, 1.0, W, N, Tc, N, s)));
+      TP3B_HIP((launch_bcombine<TW, double>(N, nb, steps, t_sign, Vg, bs, dY, hld, Tc, N, s)));
       return TP3B_OK;
     };
     if (o.graph) {

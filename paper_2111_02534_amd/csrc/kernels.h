@@ -109,10 +109,11 @@ hipError_t launch_gmres_lstsq(int nb, int b, int steps, int hld, const double* H
 // with partial pivoting, one wavefront); *singular = 1 on an exactly zero pivot.
 constexpr int SI_MAXN = 48;
 hipError_t launch_small_inverse(int n, const double* A, double* Ainv, int* singular, hipStream_t s);
-// W[r, j] += alpha * sum_{i<nb} Vb[i][r, j] H[j*hld + i]
-template <typename T>
-hipError_t launch_bupdate_diag(int64_t N, int b, int nb, double alpha, const T* V, int64_t bs,
-                               const double* H, int hld, T* W, hipStream_t s);
+// Out[r, j] = alpha * sum_{i<nb} Vb[i][r, j] H[j*hld + i] (assigned, column
+// stride ldo, stored in the output type)
+template <typename T, typename TO>
+hipError_t launch_bcombine(int64_t N, int b, int nb, double alpha, const T* V, int64_t bs,
+                           const double* H, int hld, TO* Out, int64_t ldo, hipStream_t s);
 
 // The Arnoldi steps with the dots' second stage folded into their consumer:
 // launch_bdot_partials runs only the first stage of launch_bdot_diag into

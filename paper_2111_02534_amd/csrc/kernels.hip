@@ -357,27 +357,49 @@ template hipError_t launch_bdot_diag<double>(int64_t, int, int, const double*, i
 template hipError_t launch_bdot_diag<float>(int64_t, int, int, const float*, int64_t,
                                             const float*, double*, int, double*, hipStream_t);
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_bupdate_diag(int64_t N, int b, int nb, double alpha,
-                                                      const T* __restrict__ V, int64_t bs,
-                                                      const double* __restrict__ H, int hld,
-                                                      T* __restrict__ W) {
-  bupdate_row<T>(N, nb, alpha, V, bs, H, hld, W, (int64_t)blockIdx.x * 256 + threadIdx.x,
-                 blockIdx.y);
+// Out[r, j] = alpha * sum_{i<nb} Vb[i][r, j] H[j*hld + i], assigned (not added)
+// and stored in the output type: the combination of a GMRES basis with its
+// least-squares coefficients, written straight into the FP64 correction. The
+// terms are taken in the order bupdate_row takes them, and an exactly zero
+// coefficient again contributes nothing.
+template <typename T, typename TO>
+__global__ __launch_bounds__(256) void k_bcombine(int64_t N, int nb, double alpha,
+                                                  const T* __restrict__ V, int64_t bs,
+                                                  const double* __restrict__ H, int hld,
+                                                  TO* __restrict__ Out, int64_t ldo) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (r >= N) return;
+  double acc = 0.0;
+  for (int i0 = 0; i0 < nb; i0 += 8) {
+    double v[8], h[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u;
+      h[u] = (i < nb) ? H[(int64_t)j * hld + i] : 0.0;
+      v[u] = (h[u] != 0.0) ? (double)V[(int64_t)i * bs + (int64_t)j * N + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (h[u] != 0.0) acc += v[u] * h[u];
+  }
+  Out[(int64_t)j * ldo + r] = (TO)(alpha * acc);
 }
 
-template <typename T>
-hipError_t launch_bupdate_diag(int64_t N, int b, int nb, double alpha, const T* V, int64_t bs,
-                               const double* H, int hld, T* W, hipStream_t s) {
+template <typename T, typename TO>
+hipError_t launch_bcombine(int64_t N, int b, int nb, double alpha, const T* V, int64_t bs,
+                           const double* H, int hld, TO* Out, int64_t ldo, hipStream_t s) {
   if (N <= 0 || b <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_bupdate_diag<T>), dim3((unsigned)((N + 255) / 256), b), dim3(256), 0, s, N,
-                     b, nb, alpha, V, bs, H, hld, W);
+  hipLaunchKernelGGL((k_bcombine<T, TO>), dim3((unsigned)((N + 255) / 256), b), dim3(256), 0, s,
+                     N, nb, alpha, V, bs, H, hld, Out, ldo);
   return hipGetLastError();
 }
-template hipError_t launch_bupdate_diag<double>(int64_t, int, int, double, const double*, int64_t,
-                                                const double*, int, double*, hipStream_t);
-template hipError_t launch_bupdate_diag<float>(int64_t, int, int, double, const float*, int64_t,
-                                               const double*, int, float*, hipStream_t);
+template hipError_t launch_bcombine<double, double>(int64_t, int, int, double, const double*,
+                                                    int64_t, const double*, int, double*, int64_t,
+                                                    hipStream_t);
+template hipError_t launch_bcombine<float, double>(int64_t, int, int, double, const float*,
+                                                   int64_t, const double*, int, double*, int64_t,
+                                                   hipStream_t);
 
 // ------------------------------------- Arnoldi steps with the reduction fused
 // The per-column dots' first stage alone: partials for launch_bupdate_diag_red
