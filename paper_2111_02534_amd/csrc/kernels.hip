@@ -16,6 +16,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_bodies.h"
 
 namespace tp3b {
@@ -175,6 +177,359 @@ __global__ __launch_bounds__(256) void k_dot_reduce(int p, int q, int nchunk, in
   if (lane == 0) C[gp + (int64_t)gq * ldc] = s;
 }
 
+// Long blocks (N >= DOTL_N) whose whole product fits one tile of PI x QJ
+// MFMA blocks (p <= 16 PI <= 80, q <= 16 QJ <= 32).  The work is the block
+// dot's: the same row chunks, the same 16-row groups per wave taken in the
+// same order, the waves summed in LDS in wave order, the chunks summed by one
+// wavefront per element.  What differs is that the block counts are compile-time,
+// so no load or product sits behind a branch: lanes past the last column load
+// column 0 of their operand (their pointers are clamped there) and feed only
+// output rows or columns outside p x q, which are never stored.  With
+// straight-line loads the next batch stays in flight while the current one is
+// multiplied; S groups per batch keep enough bytes in flight when the tile
+// is narrow.
+constexpr int64_t DOTL_N = 1 << 20;
+constexpr int DOTL_PI = 5, DOTL_QJ = 2;
+
+template <typename TA, typename TB, int PI, int QJ, int S>
+__global__ __launch_bounds__(256) void k_dot_long(int64_t N, int p, int q, const TA* __restrict__ A,
+                                                  int64_t lda, const TB* __restrict__ B,
+                                                  int64_t ldb, int rc, double* __restrict__ part) {
+  constexpr int TP = 16 * PI, TQ = 16 * QJ;
+  __shared__ double red[TP * TQ];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t rbeg = (int64_t)blockIdx.x * rc;
+  const int64_t rend = (rbeg + rc < N) ? rbeg + rc : N;
+  const TA* Ac[PI];
+  const TB* Bc[QJ];
+  bool pa[PI], pb[QJ];
+#pragma unroll
+  for (int i = 0; i < PI; ++i) {
+    const int col = i * 16 + lr;
+    pa[i] = col < p;
+    Ac[i] = A + (int64_t)(pa[i] ? col : 0) * lda;
+  }
+#pragma unroll
+  for (int j = 0; j < QJ; ++j) {
+    const int col = j * 16 + lr;
+    pb[j] = col < q;
+    Bc[j] = B + (int64_t)(pb[j] ? col : 0) * ldb;
+  }
+  d4 acc[PI][QJ];
+#pragma unroll
+  for (int i = 0; i < PI; ++i)
+#pragma unroll
+    for (int j = 0; j < QJ; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  const bool vec_ok = (((uintptr_t)A | (uintptr_t)B) % 16 == 0) && (lda % 4 == 0) &&
+                      (ldb % 4 == 0) && (rbeg % 16 == 0);
+  // batch of S groups of 16 rows: group s at rows g + 64 s (lane group lk owns
+  // rows + 4 lk .. + 3 of its column, fed to K slot lk of the u-th product)
+  auto loadv = [&](int64_t g, double (&av)[S][PI][4], double (&bv)[S][QJ][4]) {
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int64_t r0 = g + 64 * t + 4 * lk;
+#pragma unroll
+      for (int i = 0; i < PI; ++i) ld4_d(Ac[i] + r0, av[t][i]);
+#pragma unroll
+      for (int j = 0; j < QJ; ++j) ld4_d(Bc[j] + r0, bv[t][j]);
+    }
+  };
+  auto mul = [&](const double (&av)[S][PI][4], const double (&bv)[S][QJ][4], int nt) {
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+      if (t < nt)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int i = 0; i < PI; ++i)
+#pragma unroll
+            for (int j = 0; j < QJ; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t][i][u], bv[t][j][u], acc[i][j],
+                                                               0, 0, 0);
+  };
+  double a0[S][PI][4], b0[S][QJ][4], a1[S][PI][4], b1[S][QJ][4];
+  int64_t g = rbeg + wave * 16;
+  constexpr int64_t STEP = 64 * S;
+  // Whole batches (every group of the batch inside the chunk), two in
+  // flight, in pairs: each pass of the loop loads the second batch of its pair
+  // and then the first of the next pair (the last batch again past the end,
+  // its values unused), so no load sits behind a branch, the number of loads
+  // in flight is the same on every path and each wait covers only the batch
+  // in use.  An odd last batch is already loaded when the loop ends.
+  if (vec_ok && g + STEP - 48 <= rend) {
+    const int64_t nbat = (rend - g + 48) / STEP;
+    const int64_t glast = g + (nbat - 1) * STEP;
+    loadv(g, a0, b0);
+    for (int64_t k = 0; k < nbat / 2; ++k) {
+      loadv(g + STEP, a1, b1);
+      mul(a0, b0, S);
+      g += STEP;
+      loadv(g + STEP < glast ? g + STEP : glast, a0, b0);
+      mul(a1, b1, S);
+      g += STEP;
+    }
+    if (nbat & 1) {
+      mul(a0, b0, S);
+      g += STEP;
+    }
+  }
+  // the remaining groups (a partial batch, the group that crosses the chunk
+  // end, or unaligned operands): element loads, zero past the last row
+  for (; g < rend; g += 64) {
+    const int64_t r0 = g + 4 * lk;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t r = r0 + u;
+      const bool rv = r < rend;
+#pragma unroll
+      for (int i = 0; i < PI; ++i) a0[0][i][u] = rv ? ld_d(Ac[i] + r) : 0.0;
+#pragma unroll
+      for (int j = 0; j < QJ; ++j) b0[0][j][u] = rv ? ld_d(Bc[j] + r) : 0.0;
+    }
+    mul(a0, b0, 1);
+  }
+  for (int wv = 0; wv < 4; ++wv) {
+    if (wave == wv) {
+#pragma unroll
+      for (int i = 0; i < PI; ++i)
+#pragma unroll
+        for (int j = 0; j < QJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int idx = (j * 16 + lr) * TP + i * 16 + Mma<double>::row(lk, r);
+            red[idx] = (wv == 0) ? acc[i][j][r] : red[idx] + acc[i][j][r];
+          }
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.x * (TP * TQ);
+  for (int e = tid; e < TP * TQ; e += 256)
+    if (e % TP < p && e / TP < q) out[e] = red[e];
+}
+
+// The same product for wider tiles (40 or more columns), staged through LDS.  Loads
+// in the MFMA operand layout put 16 columns into every load instruction,
+// which for many long columns (their starts a large power of two apart)
+// keeps the memory system well below its streaming rate; here each thread
+// instead loads two consecutive rows of one column, so a wave's instruction
+// reads 256 contiguous bytes of each of four columns, and the products take
+// their operands from LDS.  A workgroup takes the 32-row steps b, b + G,
+// b + 2G, ... (G workgroups), the next step's loads in flight while the
+// current one is multiplied; two waves multiply (16 rows each), the four
+// waves' tiles are summed in LDS in wave order as in the block dot.  Padding
+// columns load column 0 of their operand (their LDS entries feed only
+// outputs outside p x q, which are not stored).  Requires aligned pairs of
+// rows: even leading dimensions and base pointers aligned to two elements.
+constexpr int DOTS_RS = 32;
+
+template <typename T, int PI, int QJ>
+__global__ __launch_bounds__(256) void k_dot_lds(int64_t N, int p, int q, const T* __restrict__ A,
+                                                 int64_t lda, const T* __restrict__ B, int64_t ldb,
+                                                 double* __restrict__ part) {
+  constexpr int RS = DOTS_RS;
+  constexpr int TP = 16 * PI, TQ = 16 * QJ, NC = TP + TQ;
+  // row stride of the staged tile: NC + 4 doubles puts the two lane groups
+  // of a half-wave operand read on disjoint bank halves
+  constexpr int LDW = NC + 4;
+  constexpr int SEG = RS / 2;        // threads per column (two rows each)
+  constexpr int CPR = 256 / SEG;     // columns per load round
+  constexpr int NR = NC / CPR;       // load rounds (NC is a multiple of 16)
+  typedef typename std::conditional<std::is_same<T, double>::value, double2, float2>::type T2;
+  __shared__ double sm[RS * LDW];
+  __shared__ double red[TP * TQ];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int rp = 2 * (tid % SEG);  // first of this thread's two rows in a step
+  // every slot loads (a padding column reads column 0 of its operand), so no
+  // load sits behind a per-lane branch
+  const T* src[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    const int c = k * CPR + tid / SEG;
+    const bool val = c < TP ? c < p : c - TP < q;
+    const int cc = val ? (c < TP ? c : c - TP) : 0;
+    src[k] = (c < TP ? A + (int64_t)cc * lda : B + (int64_t)cc * ldb) + rp;
+  }
+  const int scol = tid / SEG;  // this thread's column in round 0
+  d4 acc[PI][QJ];
+#pragma unroll
+  for (int i = 0; i < PI; ++i)
+#pragma unroll
+    for (int j = 0; j < QJ; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  T2 v[NR];
+  auto stage = [&]() {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      sm[rp * LDW + k * CPR + scol] = (double)v[k].x;
+      sm[(rp + 1) * LDW + k * CPR + scol] = (double)v[k].y;
+    }
+  };
+  auto mul = [&]() {
+    if (wave < RS / 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = wave * 16 + 4 * lk + u;
+        double a[PI], bb[QJ];
+#pragma unroll
+        for (int i = 0; i < PI; ++i) a[i] = sm[r * LDW + i * 16 + lr];
+#pragma unroll
+        for (int j = 0; j < QJ; ++j) bb[j] = sm[r * LDW + TP + j * 16 + lr];
+#pragma unroll
+        for (int i = 0; i < PI; ++i)
+#pragma unroll
+          for (int j = 0; j < QJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+  // whole steps: workgroup b takes b, b + G, ...; the next step's loads are
+  // issued before the current step is multiplied
+  const int64_t nfull = N / RS, G = gridDim.x;
+  int64_t st = blockIdx.x;
+  if (st < nfull) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) v[k] = *(const T2*)(src[k] + st * RS);
+  }
+  for (; st < nfull; st += G) {
+    __syncthreads();
+    stage();
+    __syncthreads();
+    if (st + G < nfull) {
+      const int64_t r0 = (st + G) * RS;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) v[k] = *(const T2*)(src[k] + r0);
+    }
+    mul();
+  }
+  // the last, partial step (if any), on the workgroup next in turn: element
+  // loads, zero past the last row
+  if (nfull * RS < N && blockIdx.x == nfull % G) {
+    const int64_t r0 = nfull * RS;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      v[k].x = (r0 + rp < N) ? src[k][r0] : (T)0;
+      v[k].y = (r0 + rp + 1 < N) ? src[k][r0 + 1] : (T)0;
+    }
+    __syncthreads();
+    stage();
+    __syncthreads();
+    mul();
+  }
+  for (int wv = 0; wv < 4; ++wv) {
+    if (wave == wv) {
+#pragma unroll
+      for (int i = 0; i < PI; ++i)
+#pragma unroll
+        for (int j = 0; j < QJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int idx = (j * 16 + lr) * TP + i * 16 + Mma<double>::row(lk, r);
+            red[idx] = (wv == 0) ? acc[i][j][r] : red[idx] + acc[i][j][r];
+          }
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.x * (TP * TQ);
+  for (int e = tid; e < TP * TQ; e += 256)
+    if (e % TP < p && e / TP < q) out[e] = red[e];
+}
+
+// Sums the chunk partials of k_dot_long: one wavefront per element (p, q),
+// lanes stride over the chunks, then a fixed-order shuffle reduction.  Stores
+// C[i + j ldc] = sum, or C[j + i ldc] with `trans`.
+__global__ __launch_bounds__(256) void k_dot_long_reduce(int p, int q, int tp, int nchunk,
+                                                         const double* __restrict__ part,
+                                                         double* __restrict__ C, int ldc,
+                                                         int trans) {
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e >= p * q) return;
+  const int i = e % p, j = e / p;
+  const double* src = part + (int64_t)j * tp + i;
+  const int64_t cs = (int64_t)tp * ((q + 15) / 16) * 16;
+  double s = 0.0;
+  for (int c = lane; c < nchunk; c += 64) s += src[(int64_t)c * cs];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) {
+    if (trans)
+      C[j + (int64_t)i * ldc] = s;
+    else
+      C[i + (int64_t)j * ldc] = s;
+  }
+}
+
+template <typename TA, typename TB, int PI, int QJ>
+static int launch_dot_long_pq(int64_t N, int p, int q, const TA* A, int64_t lda, const TB* B,
+                              int64_t ldb, int rc, int nchunk, int64_t cap, double* partial,
+                              hipStream_t s) {
+  constexpr int TPQ = 256 * PI * QJ;
+  if constexpr (PI + QJ >= 3 && std::is_same<TA, TB>::value) {
+    // staged through LDS once at least 40 columns are read (measured: from
+    // there on the direct loads fall well below the staged ones)
+    const bool al = (p + q >= 40) && (((uintptr_t)A | (uintptr_t)B) % (2 * sizeof(TA)) == 0) &&
+                    (lda % 2 == 0) && (ldb % 2 == 0);
+    int64_t G = cap / TPQ;
+    if (G > 2048) G = 2048;
+    if (al && G >= 256) {
+      hipLaunchKernelGGL((k_dot_lds<TA, PI, QJ>), dim3((unsigned)G), dim3(256), 0, s, N, p, q, A,
+                         lda, B, ldb, partial);
+      return (int)G;
+    }
+  }
+  if ((int64_t)nchunk * TPQ > cap) return -1;
+  constexpr int S = (PI + QJ <= 2) ? 3 : ((PI + QJ <= 3) ? 2 : 1);
+  hipLaunchKernelGGL((k_dot_long<TA, TB, PI, QJ, S>), dim3(nchunk), dim3(256), 0, s, N, p, q, A,
+                     lda, B, ldb, rc, partial);
+  return nchunk;
+}
+
+template <typename TA, typename TB, int QJ>
+static int launch_dot_long_q(int pi, int64_t N, int p, int q, const TA* A, int64_t lda,
+                             const TB* B, int64_t ldb, int rc, int nchunk, int64_t cap,
+                             double* partial, hipStream_t s) {
+  switch (pi) {
+    case 1: return launch_dot_long_pq<TA, TB, 1, QJ>(N, p, q, A, lda, B, ldb, rc, nchunk, cap, partial, s);
+    case 2: return launch_dot_long_pq<TA, TB, 2, QJ>(N, p, q, A, lda, B, ldb, rc, nchunk, cap, partial, s);
+    case 3: return launch_dot_long_pq<TA, TB, 3, QJ>(N, p, q, A, lda, B, ldb, rc, nchunk, cap, partial, s);
+    case 4: return launch_dot_long_pq<TA, TB, 4, QJ>(N, p, q, A, lda, B, ldb, rc, nchunk, cap, partial, s);
+    default: return launch_dot_long_pq<TA, TB, 5, QJ>(N, p, q, A, lda, B, ldb, rc, nchunk, cap, partial, s);
+  }
+}
+
+// C = A^T B on long blocks when one tile holds it (the taller operand is put
+// first: p x q with q <= 32 and p <= 80, or the transpose).  Returns false
+// when the shape does not fit; the caller then runs the general dot.
+template <typename TA, typename TB>
+static bool launch_dot_long(int64_t N, int p, int q, const TA* A, int64_t lda, const TB* B,
+                            int64_t ldb, double* C, int ldc, double* partial, hipStream_t s) {
+  if (N < DOTL_N) return false;
+  const bool trans = q > p;
+  const int P = trans ? q : p, Q = trans ? p : q;
+  if (P > 16 * DOTL_PI || Q > 16 * DOTL_QJ) return false;
+  if (trans && !std::is_same<TA, TB>::value) return false;
+  const int rc = dot_row_chunk(N);
+  const int nchunk = (int)((N + rc - 1) / rc);
+  const int pi = (P + 15) / 16, qj = (Q + 15) / 16;
+  // the partials may take what the general dot's take for this p x q
+  const int64_t cap = dot_scratch_doubles(N, p, q);
+  int nparts;
+  if (trans) {
+    // TA == TB here
+    const TA* Bt = reinterpret_cast<const TA*>(B);
+    const TB* At = reinterpret_cast<const TB*>(A);
+    nparts = qj == 1 ? launch_dot_long_q<TA, TB, 1>(pi, N, P, Q, Bt, ldb, At, lda, rc, nchunk, cap, partial, s)
+                     : launch_dot_long_q<TA, TB, 2>(pi, N, P, Q, Bt, ldb, At, lda, rc, nchunk, cap, partial, s);
+  } else {
+    nparts = qj == 1 ? launch_dot_long_q<TA, TB, 1>(pi, N, P, Q, A, lda, B, ldb, rc, nchunk, cap, partial, s)
+                     : launch_dot_long_q<TA, TB, 2>(pi, N, P, Q, A, lda, B, ldb, rc, nchunk, cap, partial, s);
+  }
+  if (nparts < 0) return false;
+  hipLaunchKernelGGL(k_dot_long_reduce, dim3((unsigned)((P * Q + 3) / 4)), dim3(256), 0, s, P, Q,
+                     16 * pi, nparts, partial, C, ldc, trans ? 1 : 0);
+  return true;
+}
+
 template <typename TA, typename TB>
 hipError_t launch_dot_tn(int64_t N, int p, int q, const TA* A, int64_t lda, const TB* B,
                          int64_t ldb, double* C, int ldc, double* partial, hipStream_t s) {
@@ -187,6 +542,7 @@ hipError_t launch_dot_tn(int64_t N, int p, int q, const TA* A, int64_t lda, cons
     }
     return hipSuccess;
   }
+  if (launch_dot_long<TA, TB>(N, p, q, A, lda, B, ldb, C, ldc, partial, s)) return hipGetLastError();
   const int rc = dot_row_chunk(N);
   const int nchunk = (int)((N + rc - 1) / rc);
   const int tq = (q + DOT_TQ - 1) / DOT_TQ, tp = (p + DOT_TP - 1) / DOT_TP;

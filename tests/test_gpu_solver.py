@@ -13,7 +13,9 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-@pytest.mark.parametrize("N,nq,nx", [(5000, 7, 4), (70000, 40, 8), (1000, 0, 3), (333, 17, 16)])
+@pytest.mark.parametrize("N,nq,nx", [(5000, 7, 4), (70000, 40, 8), (1000, 0, 3), (333, 17, 16),
+                                     (1048576 + 37, 70, 8), (1048576 + 5, 9, 16),
+                                     (1048576, 33, 16)])
 def test_block_orth_matches_oracle(N, nq, nx):
     import torch
     t3 = need_gpu()
