@@ -181,7 +181,9 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   // Q~ = [Q_lock, U] contiguous (U = V s_1..s_nb, plus one column for the
   // residual when a 2 x 2 block straddles the block edge), and A U
   TP3B_HIP(dalloc(Qtb, sizeof(double) * N * (qt_max + 1)));
-  TP3B_HIP(dalloc(AUb, sizeof(double) * N * b));
+  // long blocks form the residuals in one pass over V and A V (A U is not stored)
+  const bool urres_fused = N >= (1 << 20) && m_max + b <= 128 && b <= 16;
+  if (!urres_fused) TP3B_HIP(dalloc(AUb, sizeof(double) * N * b));
   TP3B_HIP(dalloc(AVb, sizeof(double) * N * av_cols));
   // same capacity as A V: the two buffers swap roles after a rotation
   TP3B_HIP(dalloc(TMPb, sizeof(double) * N * av_cols));
@@ -397,9 +399,13 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       std::memcpy(P(r_upT), Tc_.data(), sizeof(double) * nu * nb);
       TP3B_HIP(hipMemcpyAsync(dTb, P(r_upT), sizeof(double) * nu * nb, hipMemcpyHostToDevice, s));
       double* U = Qt + (int64_t)k * N;
-      TP3B_HIP(launch_gemm_nn<double>(N, m, nu, 1.0, V(), N, dS, m, 0.0, U, N, s));
-      TP3B_HIP(launch_gemm_nn<double>(N, m, nb, 1.0, AV(), N, dS, m, 0.0, AU, N, s));
-      TP3B_HIP(launch_gemm_nn_x0<double>(N, nu, nb, -1.0, U, N, dTb, nu, 1.0, AU, N, Rres, N, s));
+      if (urres_fused) {
+        TP3B_HIP(launch_urres_long(N, m, nu, nb, V(), AV(), N, dS, dTb, U, Rres, N, s));
+      } else {
+        TP3B_HIP(launch_gemm_nn<double>(N, m, nu, 1.0, V(), N, dS, m, 0.0, U, N, s));
+        TP3B_HIP(launch_gemm_nn<double>(N, m, nb, 1.0, AV(), N, dS, m, 0.0, AU, N, s));
+        TP3B_HIP(launch_gemm_nn_x0<double>(N, nu, nb, -1.0, U, N, dTb, nu, 1.0, AU, N, Rres, N, s));
+      }
     }
     std::vector<double> Cq((size_t)std::max(k, 1) * nb, 0.0);  // Q^T A U, column-major k x nb
     std::vector<double> c1((size_t)std::max(k, 1) * nb), c2((size_t)std::max(k, 1) * nb);

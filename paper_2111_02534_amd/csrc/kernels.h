@@ -90,6 +90,28 @@ hipError_t launch_gemm_nn_x0(int64_t N, int p, int q, double alpha, const T* A, 
                              const double* C, int ldc, double beta, const T* X0, int64_t ldx0, T* Y,
                              int64_t ldy, hipStream_t s);
 
+// U (N x nu, ldo) = V S and R (N x nb, ldo) = (A V) S[:, :nb] - U T for long
+// blocks (N >= 2^20), V and A V N x m (ld), S m x nu and T nu x nb column-major
+// device matrices; m <= 128, nb <= 16, nu <= nb + 1.  Equals the three
+// products V S, (A V) S[:, :nb], A U - U T bit for bit.  hipErrorInvalidValue
+// outside those limits (the caller then runs the products).
+hipError_t launch_urres_long(int64_t N, int m, int nu, int nb, const double* V, const double* AV,
+                             int64_t ld, const double* S, const double* Tm, double* U, double* R,
+                             int64_t ldo, hipStream_t s);
+
+// Xout = Xin - Q C (Q N x nq, C nq x nx column-major on the device, Xin and
+// Xout N x nx with ld ldx; Xin may equal Xout) fused with the dot on the
+// updated rows: D (ldd) = Q^T Xout (self = 0, nq x nx) or Xout^T Xout
+// (self = 1, nx x nx); `partial` as for launch_dot_tn with that dot's shape.
+// Long FP64 blocks only (N >= 2^20, nq <= 80, nx <= 16, 16-byte aligned
+// operands, even leading dimensions); hipErrorInvalidValue otherwise (the
+// caller then runs the update and the dot); gemm_dot_long_fits tells which.
+bool gemm_dot_long_fits(int64_t N, int nq, int nx, const double* Q, int64_t ldq, const double* Xin,
+                        const double* Xout, int64_t ldx);
+hipError_t launch_gemm_dot_long(int64_t N, int nq, int nx, const double* Q, int64_t ldq,
+                                const double* C, const double* Xin, double* Xout, int64_t ldx,
+                                int self, double* D, int ldd, double* partial, hipStream_t s);
+
 // Batched per-column dots for b independent Krylov bases stored as blocks
 // Vb[i] = V + i*bs (each N x b, ld N):  H[j*hld + i] = sum_r Vb[i][r, j] W[r, j]
 // for i < nb.  `partial` as for the dot.

@@ -530,6 +530,208 @@ static bool launch_dot_long(int64_t N, int p, int q, const TA* A, int64_t lda, c
   return true;
 }
 
+// A Gram-Schmidt update fused with the dot that follows it (long blocks,
+// FP64): per row, Xout = Xin - Q C (nq x nx, nx <= 16, Q C on the matrix
+// cores), then the partials of the next dot on the updated rows, Q^T Xout
+// (SELF false: the second Gram-Schmidt pass; the same steps, workgroups and
+// product order as k_dot_lds, so it equals launch_dot_tn on the stored Xout)
+// or Xout^T Xout (SELF true: the Gram matrix of the Cholesky-QR).  Rows are
+// staged through LDS in 32-row steps as in k_dot_lds.  Xin may equal Xout
+// (each row is read before it is written, by the same workgroup).
+template <int PQ, int QJ, bool SELF>
+__global__ __launch_bounds__(256) void k_gemm_dot_lds(int64_t N, int nq, int nx,
+                                                      const double* __restrict__ Q, int64_t ldq,
+                                                      const double* __restrict__ C,
+                                                      const double* Xin, double* Xout,
+                                                      int64_t ldx, double* __restrict__ part) {
+  constexpr int RS = DOTS_RS;
+  constexpr int TP = 16 * PQ, TQ = 16 * QJ, NC = TP + TQ;
+  constexpr int LDW = NC + 4;
+  constexpr int SEG = RS / 2, CPR = 256 / SEG, NR = NC / CPR;
+  constexpr int DP = SELF ? QJ : PQ;   // 16-column blocks of the dot's first operand
+  constexpr int TD = 16 * DP;
+  constexpr int AOFF = SELF ? TP : 0;  // where that operand sits in the staged rows
+  static_assert(QJ == 1, "the update forms 16 columns per wave");
+  __shared__ double sm[RS * LDW];
+  __shared__ double red[TD * TQ];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int rp = 2 * (tid % SEG);
+  const double* src[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    const int c = k * CPR + tid / SEG;
+    const bool val = c < TP ? c < nq : c - TP < nx;
+    const int cc = val ? (c < TP ? c : c - TP) : 0;
+    src[k] = (c < TP ? Q + (int64_t)cc * ldq : Xin + (int64_t)cc * ldx) + rp;
+  }
+  const int scol = tid / SEG;
+  d4 acc[DP][QJ];
+#pragma unroll
+  for (int i = 0; i < DP; ++i)
+#pragma unroll
+    for (int j = 0; j < QJ; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  double2 v[NR];
+  auto stage = [&]() {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      sm[rp * LDW + k * CPR + scol] = v[k].x;
+      sm[(rp + 1) * LDW + k * CPR + scol] = v[k].y;
+    }
+  };
+  // The update of the staged rows on the matrix cores: waves 0 and 1 form
+  // D = Q C for rows 16w .. 16w + 15 (A operand from the staged Q rows, the
+  // B operand C[4kk + lk][lr] held in registers) and replace the staged X by
+  // X - D; then every thread copies its share of the updated rows to Xout
+  // (32 consecutive rows of a column per half-wave).
+  double creg[4 * PQ];
+#pragma unroll
+  for (int kk = 0; kk < 4 * PQ; ++kk) {
+    const int i = 4 * kk + lk;
+    creg[kk] = (i < nq && lr < nx) ? C[i + (int64_t)lr * nq] : 0.0;
+  }
+  auto update = [&]() {
+    if (wave < RS / 16) {
+      d4 dq = d4{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4 * PQ; ++kk)
+        dq = __builtin_amdgcn_mfma_f64_16x16x4f64(sm[(wave * 16 + lr) * LDW + 4 * kk + lk], creg[kk],
+                                                  dq, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wave * 16 + Mma<double>::row(lk, r);
+        sm[row * LDW + TP + lr] -= dq[r];
+      }
+    }
+  };
+  auto copy_out = [&](int64_t r0) {
+    const int rr = tid & 31;
+    if (r0 + rr < N) {
+#pragma unroll
+      for (int t = 0; t < TQ / 8; ++t) {
+        const int j = (tid >> 5) + 8 * t;
+        if (j < nx) Xout[r0 + rr + (int64_t)j * ldx] = sm[rr * LDW + TP + j];
+      }
+    }
+  };
+  auto mul = [&]() {
+    if (wave < RS / 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = wave * 16 + 4 * lk + u;
+        double a[DP], bb[QJ];
+#pragma unroll
+        for (int i = 0; i < DP; ++i) a[i] = sm[r * LDW + AOFF + i * 16 + lr];
+#pragma unroll
+        for (int j = 0; j < QJ; ++j) bb[j] = sm[r * LDW + TP + j * 16 + lr];
+#pragma unroll
+        for (int i = 0; i < DP; ++i)
+#pragma unroll
+          for (int j = 0; j < QJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+  const int64_t nfull = N / RS, G = gridDim.x;
+  int64_t st = blockIdx.x;
+  if (st < nfull) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) v[k] = *(const double2*)(src[k] + st * RS);
+  }
+  for (; st < nfull; st += G) {
+    __syncthreads();
+    stage();
+    __syncthreads();
+    if (st + G < nfull) {
+      const int64_t r1 = (st + G) * RS;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) v[k] = *(const double2*)(src[k] + r1);
+    }
+    update();
+    __syncthreads();
+    copy_out(st * RS);
+    mul();
+  }
+  if (nfull * RS < N && blockIdx.x == nfull % G) {
+    // the last, partial step: zero past the last row (the update then
+    // stores only the rows inside)
+    const int64_t r0 = nfull * RS;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      v[k].x = (r0 + rp < N) ? src[k][r0] : 0.0;
+      v[k].y = (r0 + rp + 1 < N) ? src[k][r0 + 1] : 0.0;
+    }
+    __syncthreads();
+    stage();
+    __syncthreads();
+    update();
+    __syncthreads();
+    copy_out(r0);
+    mul();
+  }
+  for (int wv = 0; wv < 4; ++wv) {
+    if (wave == wv) {
+#pragma unroll
+      for (int i = 0; i < DP; ++i)
+#pragma unroll
+        for (int j = 0; j < QJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int idx = (j * 16 + lr) * TD + i * 16 + Mma<double>::row(lk, r);
+            red[idx] = (wv == 0) ? acc[i][j][r] : red[idx] + acc[i][j][r];
+          }
+    }
+    __syncthreads();
+  }
+  const int pd = SELF ? nx : nq;
+  double* out = part + (int64_t)blockIdx.x * (TD * TQ);
+  for (int e = tid; e < TD * TQ; e += 256)
+    if (e % TD < pd && e / TD < nx) out[e] = red[e];
+}
+
+template <int PQ, bool SELF>
+static void launch_gemm_dot_pq(unsigned G, int64_t N, int nq, int nx, const double* Q, int64_t ldq,
+                               const double* C, const double* Xin, double* Xout, int64_t ldx,
+                               double* part, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm_dot_lds<PQ, 1, SELF>), dim3(G), dim3(256), 0, s, N, nq, nx, Q, ldq, C,
+                     Xin, Xout, ldx, part);
+}
+
+bool gemm_dot_long_fits(int64_t N, int nq, int nx, const double* Q, int64_t ldq, const double* Xin,
+                        const double* Xout, int64_t ldx) {
+  return N >= DOTL_N && nq >= 1 && nq <= 16 * DOTL_PI && nx >= 1 && nx <= 16 &&
+         (((uintptr_t)Q | (uintptr_t)Xin | (uintptr_t)Xout) % 16) == 0 && ldq % 2 == 0 &&
+         ldx % 2 == 0 && dot_scratch_doubles(N, nx, nx) / 256 >= 256;
+}
+
+hipError_t launch_gemm_dot_long(int64_t N, int nq, int nx, const double* Q, int64_t ldq,
+                                const double* C, const double* Xin, double* Xout, int64_t ldx,
+                                int self, double* D, int ldd, double* partial, hipStream_t s) {
+  if (!gemm_dot_long_fits(N, nq, nx, Q, ldq, Xin, Xout, ldx)) return hipErrorInvalidValue;
+  const int pq = (nq + 15) / 16;
+  const int pd = self ? nx : nq;
+  const int td = self ? 16 : 16 * pq;
+  int64_t G = dot_scratch_doubles(N, pd, nx) / (td * 16);
+  if (G > 2048) G = 2048;
+  if (G < 256) return hipErrorInvalidValue;
+  const unsigned g = (unsigned)G;
+  switch (pq) {
+    case 1: self ? launch_gemm_dot_pq<1, true>(g, N, nq, nx, Q, ldq, C, Xin, Xout, ldx, partial, s)
+                 : launch_gemm_dot_pq<1, false>(g, N, nq, nx, Q, ldq, C, Xin, Xout, ldx, partial, s); break;
+    case 2: self ? launch_gemm_dot_pq<2, true>(g, N, nq, nx, Q, ldq, C, Xin, Xout, ldx, partial, s)
+                 : launch_gemm_dot_pq<2, false>(g, N, nq, nx, Q, ldq, C, Xin, Xout, ldx, partial, s); break;
+    case 3: self ? launch_gemm_dot_pq<3, true>(g, N, nq, nx, Q, ldq, C, Xin, Xout, ldx, partial, s)
+                 : launch_gemm_dot_pq<3, false>(g, N, nq, nx, Q, ldq, C, Xin, Xout, ldx, partial, s); break;
+    case 4: self ? launch_gemm_dot_pq<4, true>(g, N, nq, nx, Q, ldq, C, Xin, Xout, ldx, partial, s)
+                 : launch_gemm_dot_pq<4, false>(g, N, nq, nx, Q, ldq, C, Xin, Xout, ldx, partial, s); break;
+    default: self ? launch_gemm_dot_pq<5, true>(g, N, nq, nx, Q, ldq, C, Xin, Xout, ldx, partial, s)
+                  : launch_gemm_dot_pq<5, false>(g, N, nq, nx, Q, ldq, C, Xin, Xout, ldx, partial, s); break;
+  }
+  hipLaunchKernelGGL(k_dot_long_reduce, dim3((unsigned)((pd * nx + 3) / 4)), dim3(256), 0, s, pd, nx,
+                     td, (int)G, partial, D, ldd, 0);
+  return hipGetLastError();
+}
+
 template <typename TA, typename TB>
 hipError_t launch_dot_tn(int64_t N, int p, int q, const TA* A, int64_t lda, const TB* B,
                          int64_t ldb, double* C, int ldc, double* partial, hipStream_t s) {
@@ -624,6 +826,85 @@ __global__ __launch_bounds__(256) void k_gemm_nn_long(int64_t N, int p, int q, d
       }
     }
   }
+}
+
+// The leading Schur vectors and their residuals in one pass over the basis
+// (long blocks): per row, u = V S[:, :nu] and a = (A V) S[:, :nb], then
+// R = a - u T[:nu, :nb].  Each sum is taken in the order k_gemm_nn_long takes
+// it, so U and R equal those of the three products U = V S, A U = (A V) S,
+// R = A U - U T bit for bit; A U itself is never stored.
+template <int QB>
+__global__ __launch_bounds__(256) void k_urres_long(int64_t N, int m, int nu, int nb,
+                                                    const double* __restrict__ V,
+                                                    const double* __restrict__ AV, int64_t ld,
+                                                    const double* __restrict__ S,
+                                                    const double* __restrict__ Tm,
+                                                    double* __restrict__ U,
+                                                    double* __restrict__ R, int64_t ldo) {
+  __shared__ double Ss[GEMM_PB][QB + 1];
+  __shared__ double Ts[QB + 1][QB];
+  for (int e = threadIdx.x; e < GEMM_PB * (QB + 1); e += 256) {
+    const int i = e / (QB + 1), j = e % (QB + 1);
+    Ss[i][j] = (i < m && j < nu) ? S[i + (int64_t)j * m] : 0.0;
+  }
+  for (int e = threadIdx.x; e < (QB + 1) * QB; e += 256) {
+    const int l = e / QB, j = e % QB;
+    Ts[l][j] = (l < nu && j < nb) ? Tm[l + (int64_t)j * nu] : 0.0;
+  }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += stride) {
+    double u[QB + 1], a[QB];
+#pragma unroll
+    for (int j = 0; j <= QB; ++j) u[j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < QB; ++j) a[j] = 0.0;
+    for (int i0 = 0; i0 < m; i0 += 8) {
+      double vv[8], av[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        vv[t] = (i0 + t < m) ? V[r + (int64_t)(i0 + t) * ld] : 0.0;
+        av[t] = (i0 + t < m) ? AV[r + (int64_t)(i0 + t) * ld] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (i0 + t < m) {
+#pragma unroll
+          for (int j = 0; j <= QB; ++j) u[j] += vv[t] * Ss[i0 + t][j];
+#pragma unroll
+          for (int j = 0; j < QB; ++j) a[j] += av[t] * Ss[i0 + t][j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j <= QB; ++j)
+      if (j < nu) U[r + (int64_t)j * ldo] = u[j];
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      if (j < nb) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l <= QB; ++l)
+          if (l < nu) acc += u[l] * Ts[l][j];
+        R[r + (int64_t)j * ldo] = a[j] - acc;
+      }
+    }
+  }
+}
+
+hipError_t launch_urres_long(int64_t N, int m, int nu, int nb, const double* V, const double* AV,
+                             int64_t ld, const double* S, const double* Tm, double* U, double* R,
+                             int64_t ldo, hipStream_t s) {
+  if (N < GEMM_LONG_N || m > GEMM_PB || nb > 16 || nu > nb + 1 || nb < 1 || m < 1)
+    return hipErrorInvalidValue;
+  const int64_t rb = (N + 255) / 256;
+  const unsigned gx = (unsigned)(rb < GEMM_LONG_WG ? rb : GEMM_LONG_WG);
+  if (nb <= 8)
+    hipLaunchKernelGGL((k_urres_long<8>), dim3(gx), dim3(256), 0, s, N, m, nu, nb, V, AV, ld, S, Tm,
+                       U, R, ldo);
+  else
+    hipLaunchKernelGGL((k_urres_long<16>), dim3(gx), dim3(256), 0, s, N, m, nu, nb, V, AV, ld, S,
+                       Tm, U, R, ldo);
+  return hipGetLastError();
 }
 
 template <typename T>

@@ -668,14 +668,24 @@ tp3b_status block_orth_queue(int64_t N, int nq, const double* Q, int64_t ldq, in
   // the dependence test reads the input norms on the device
   TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, Xin, ldx, Xin, ldx, G, nx, part, s));
   TP3B_HIP(launch_gram_diag(nx, G, n0, nonfin, s));
+  bool gram_done = false;
   if (nq > 0) {
     // the first pass reads the input and writes X = Xin - Q C1
     TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, Xin, ldx, C1, nq, part, s));
-    TP3B_HIP(launch_gemm_nn_x0<double>(N, nq, nx, -1.0, Q, ldq, C1, nq, 1.0, Xin, ldx, X, ldx, s));
-    TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, X, ldx, C2, nq, part, s));
-    TP3B_HIP(launch_gemm_nn<double>(N, nq, nx, -1.0, Q, ldq, C2, nq, 1.0, X, ldx, s));
+    // long blocks: each update also forms the next dot on the rows it has just
+    // written (the second pass's coefficients, then the Gram matrix), so Q and
+    // X are not read again for them
+    if (gemm_dot_long_fits(N, nq, nx, Q, ldq, Xin, X, ldx)) {
+      TP3B_HIP(launch_gemm_dot_long(N, nq, nx, Q, ldq, C1, Xin, X, ldx, 0, C2, nq, part, s));
+      TP3B_HIP(launch_gemm_dot_long(N, nq, nx, Q, ldq, C2, X, X, ldx, 1, G, nx, part, s));
+      gram_done = true;
+    } else {
+      TP3B_HIP(launch_gemm_nn_x0<double>(N, nq, nx, -1.0, Q, ldq, C1, nq, 1.0, Xin, ldx, X, ldx, s));
+      TP3B_HIP(launch_dot_tn<double, double>(N, nq, nx, Q, ldq, X, ldx, C2, nq, part, s));
+      TP3B_HIP(launch_gemm_nn<double>(N, nq, nx, -1.0, Q, ldq, C2, nq, 1.0, X, ldx, s));
+    }
   }
-  TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
+  if (!gram_done) TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
   TP3B_HIP(launch_chol_small(nx, G, n0, kDropTol, R1, fl1, s));
   TP3B_HIP(launch_trsm_right(N, nx, R1, X, ldx, s));
   TP3B_HIP(launch_dot_tn<double, double>(N, nx, nx, X, ldx, X, ldx, G, nx, part, s));
