@@ -377,8 +377,13 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       std::vector<double> Sc = colmajor(S, m, 0, 0, m, q);
       std::memcpy(P(r_upS), Sc.data(), sizeof(double) * m * q);
       TP3B_HIP(hipMemcpyAsync(dS, P(r_upS), sizeof(double) * m * q, hipMemcpyHostToDevice, s));
-      TP3B_HIP(launch_gemm_nn<double>(N, m, q, 1.0, V(), N, dS, m, 0.0, TMP, N, s));
-      TP3B_HIP(hipMemcpyAsync(V(), TMP, sizeof(double) * N * q, hipMemcpyDeviceToDevice, s));
+      if (N >= (1 << 20) && m <= 128 && q <= 64) {
+        // long blocks: in place, row by row (no copy back)
+        TP3B_HIP(launch_gemm_nn_rows_inplace(N, m, q, V(), N, dS, m, s));
+      } else {
+        TP3B_HIP(launch_gemm_nn<double>(N, m, q, 1.0, V(), N, dS, m, 0.0, TMP, N, s));
+        TP3B_HIP(hipMemcpyAsync(V(), TMP, sizeof(double) * N * q, hipMemcpyDeviceToDevice, s));
+      }
       TP3B_HIP(launch_gemm_nn<double>(N, m, q, 1.0, AV(), N, dS, m, 0.0, TMP, N, s));
       // the rotated A V stays where it was written (no copy back)
       std::swap(AVbase, TMP);

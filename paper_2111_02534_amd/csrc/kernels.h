@@ -112,6 +112,13 @@ hipError_t launch_gemm_dot_long(int64_t N, int nq, int nx, const double* Q, int6
                                 const double* C, const double* Xin, double* Xout, int64_t ldx,
                                 int self, double* D, int ldd, double* partial, hipStream_t s);
 
+// A[:, :q] = A C in place (A N x p, C p x q column-major on the device, q <= p)
+// for long FP64 blocks: N >= 2^20, p <= 128, q <= 64; each row is read whole
+// by the thread that then writes it.  hipErrorInvalidValue outside those
+// limits.
+hipError_t launch_gemm_nn_rows_inplace(int64_t N, int p, int q, double* A, int64_t lda,
+                                       const double* C, int ldc, hipStream_t s);
+
 // Batched per-column dots for b independent Krylov bases stored as blocks
 // Vb[i] = V + i*bs (each N x b, ld N):  H[j*hld + i] = sum_r Vb[i][r, j] W[r, j]
 // for i < nb.  `partial` as for the dot.

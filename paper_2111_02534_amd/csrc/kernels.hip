@@ -933,6 +933,56 @@ hipError_t launch_gemm_nn_x0(int64_t N, int p, int q, double alpha, const T* A, 
                      ldx0, Y, ldy);
   return hipGetLastError();
 }
+// A[:, :q] = A C in place, one row per thread over all of A's p columns (the
+// row is read whole before any of it is written; no restrict on A).
+template <int QB>
+__global__ __launch_bounds__(256) void k_gemm_rows_inplace(int64_t N, int p, int q, double* A,
+                                                           int64_t lda,
+                                                           const double* __restrict__ C, int ldc) {
+  __shared__ double Cs[GEMM_PB][QB];
+  for (int e = threadIdx.x; e < GEMM_PB * QB; e += 256) {
+    const int i = e / QB, j = e % QB;
+    Cs[i][j] = (i < p && j < q) ? C[i + (int64_t)j * ldc] : 0.0;
+  }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += stride) {
+    double acc[QB];
+#pragma unroll
+    for (int j = 0; j < QB; ++j) acc[j] = 0.0;
+    for (int i0 = 0; i0 < p; i0 += 8) {
+      double av[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) av[u] = (i0 + u < p) ? A[r + (int64_t)(i0 + u) * lda] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < p) {
+#pragma unroll
+          for (int j = 0; j < QB; ++j) acc[j] += av[u] * Cs[i0 + u][j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < QB; ++j)
+      if (j < q) A[r + (int64_t)j * lda] = acc[j];
+  }
+}
+
+hipError_t launch_gemm_nn_rows_inplace(int64_t N, int p, int q, double* A, int64_t lda,
+                                       const double* C, int ldc, hipStream_t s) {
+  if (N < GEMM_LONG_N || p > GEMM_PB || q > p || q < 1) return hipErrorInvalidValue;
+  const int64_t rb = (N + 255) / 256;
+  const unsigned gx = (unsigned)(rb < GEMM_LONG_WG ? rb : GEMM_LONG_WG);
+  if (q <= 16)
+    hipLaunchKernelGGL((k_gemm_rows_inplace<16>), dim3(gx), dim3(256), 0, s, N, p, q, A, lda, C, ldc);
+  else if (q <= 32)
+    hipLaunchKernelGGL((k_gemm_rows_inplace<32>), dim3(gx), dim3(256), 0, s, N, p, q, A, lda, C, ldc);
+  else if (q <= 64)
+    hipLaunchKernelGGL((k_gemm_rows_inplace<64>), dim3(gx), dim3(256), 0, s, N, p, q, A, lda, C, ldc);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 template hipError_t launch_gemm_nn_x0<double>(int64_t, int, int, double, const double*, int64_t,
                                               const double*, int, double, const double*, int64_t,
                                               double*, int64_t, hipStream_t);
