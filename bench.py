@@ -430,6 +430,39 @@ def counters(args):
     print(f"copy: {n * 4} bytes read, {n * 4} bytes written", flush=True)
 
 
+def orth_timing(args):
+    """Block orthogonalisation alone (tp3b_block_orth without factors: the
+    queued CGS2 + Cholesky-QR sequence JDQR runs on its expansion block) on an
+    N x nq block Q and an N x nx block X, --reps calls, each on a fresh copy of
+    X.  Prints the time per call (HIP events around the call; the call itself
+    synchronises) and the algorithmic bytes of the sequence's kernels."""
+    import torch
+
+    import paper_2111_02534_amd as t3
+    N, nq, nx = args.orth
+    g = torch.Generator(device="cuda").manual_seed(7)
+    Q = torch.randn((nq, N), dtype=torch.float64, device="cuda", generator=g)
+    X0 = torch.randn((nx, N), dtype=torch.float64, device="cuda", generator=g)
+    X = X0.clone()
+    times = []
+    for rep in range(args.reps + 2):
+        X.copy_(X0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, _, rank = t3.block_orth(Q, X, want_factors=False)
+        e1.record()
+        torch.cuda.synchronize()
+        if rep >= 2:
+            times.append(e0.elapsed_time(e1) * 1e3)
+    us = sum(times) / len(times)
+    # Gram of the input, Q^T X, two fused update+dot passes, two triangular
+    # solves and the second Gram matrix: 8 N (3 nq + 11 nx) bytes
+    nbytes = 8 * N * (3 * nq + 11 * nx)
+    print(json.dumps({"orth": {"N": N, "nq": nq, "nx": nx, "rank": rank, "us_per_call": us,
+                               "algorithmic_bytes": nbytes, "TBps": nbytes / (us * 1e-6) / 1e12}}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -452,6 +485,8 @@ def main():
     ap.add_argument("--prec", nargs="*", default=None)
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-mb", type=int, default=256)
+    ap.add_argument("--orth", nargs=3, type=int, default=None, metavar=("N", "NQ", "NX"),
+                    help="time the block orthogonalisation alone at this shape")
     ap.add_argument("--leg", default=None, choices=["c2", "c3", "c4", "c5r"],
                     help="run one of the extra legs alone and print its JSON (for profiling)")
     args = ap.parse_args()
@@ -463,6 +498,8 @@ def main():
         return apply_sweep(args)
     if args.counters:
         return counters(args)
+    if args.orth:
+        return orth_timing(args)
 
     import torch
 
