@@ -31,6 +31,7 @@ struct DevOps {
   T* ST[4] = {nullptr, nullptr, nullptr, nullptr};   // S_k^T         (right operand)
   T* lam[4] = {nullptr, nullptr, nullptr, nullptr};
   T* lamItem = nullptr;  // 2D: lam_x1[i1] + lam_x2[i2] per (x1, x2) plane
+  T* lamItemY = nullptr;  // 2D: lam_y1[j1] + lam_y2[j2] per flattened y index
   T* work = nullptr;  // preconditioner intermediate, work_vecs vectors
   // 2D operators with every mode size <= P2_MAXN: MFMA fragments (plane2d.hip)
   // of K_k, S_k and S_k^{-1} per mode, and the separable factors of a Gaussian

@@ -224,13 +224,16 @@ namespace tp3b {
 // J = 16 / sizeof(T) such matrices in LDS and applies a short program of mode
 // products to each of them with the constant n x n factors read in MFMA
 // fragment order (see plane2d_fragments), so that a whole 2D apply is two
-// passes over HBM and the 2D kinetic preconditioner four.
+// passes over HBM and the 2D kinetic preconditioner three or four.
 //   P2_SUM        Out = A W + W B^T
 //   P2_SUM_V_ACC  Out = A W + W B^T + (V - shift_v) o W + Y   (Y read in place)
 //   P2_SEQ2       Out = (A W) B^T
 //   P2_SEQ2_DIV   Out = [(A W) B^T] / (lamM[m] + lamR[r] + lamC[c] - sigma)
-// Matrices that are x slabs (interleaved layout) take P2_SUM and P2_SEQ2.
-enum Plane2DProg { P2_SUM = 0, P2_SUM_V_ACC = 1, P2_SEQ2 = 2, P2_SEQ2_DIV = 3 };
+//   P2_SEQ4_DIV   Out = C ([(A W) A^T] / (lamM[m] + lamR[r] + lamC[c] - sigma)) C^T
+//                 with A = FA1 and C = FA2 (x slabs with equal x modes, FP64)
+// Matrices that are x slabs (interleaved layout) take P2_SUM, P2_SEQ2 and
+// P2_SEQ4_DIV.
+enum Plane2DProg { P2_SUM = 0, P2_SUM_V_ACC = 1, P2_SEQ2 = 2, P2_SEQ2_DIV = 3, P2_SEQ4_DIV = 4 };
 constexpr int P2_MAXN = 64;
 
 template <typename T>
@@ -247,6 +250,7 @@ struct Plane2D {
   T* Y;
   const T* FA1;     // fragments of A and B (P2_FRAG elements each)
   const T* FB1;
+  const T* FA2;     // P2_SEQ4_DIV: fragments of the second factor (both sides)
   int same_ab;      // A and B are the same matrix (equal modes): one LDS copy serves both
   // P2_SUM_V_ACC: the potential from a table in vector layout (V), or, when G is
   // set, from separable Gaussian factors:

@@ -561,7 +561,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[b] = Mma<double>::mma(af, p2x_at(w, mat, 4 * kk + lk, b * 16 + lr), acc[b]);
     }
-    if (PROG == P2_SEQ2) {
+    if (PROG == P2_SEQ2 || PROG == P2_SEQ4_DIV) {
       // A W -> LDS, then (A W) B^T
       __syncthreads();
 #pragma unroll
@@ -579,6 +579,51 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
       const double x = p2x_at(w, mat, bi * 16 + lr, 4 * kk + lk);
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[b] = Mma<double>::mma(x, f[(b * 16 + kk) * 64 + lane], acc[b]);
+    }
+    if (PROG == P2_SEQ4_DIV) {
+      // divide in the eigenbasis, then the back transform C Z C^T with the
+      // second factor in LDS (the first is loaded again with the next item)
+      {
+        const int64_t v = item / groups, mm = (item - v * groups) * 4 + mat;
+        const double ly = a.lamM[mm] - a.sigma;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double lc = a.lamC[b * 16 + lr] + ly;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[b][q] = acc[b][q] / (a.lamR[bi * 16 + Mma<double>::row(lk, q)] + lc);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          p2x_at(w, mat, bi * 16 + Mma<double>::row(lk, q), b * 16 + lr) = acc[b][q];
+      for (int e = tid; e < P2_FRAG; e += 1024) f[e] = a.FA2[e];
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = d4{0, 0, 0, 0};
+#pragma unroll 2
+      for (int kk = 0; kk < 16; ++kk) {
+        const double af = f[(bi * 16 + kk) * 64 + lane];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = Mma<double>::mma(af, p2x_at(w, mat, 4 * kk + lk, b * 16 + lr), acc[b]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          p2x_at(w, mat, bi * 16 + Mma<double>::row(lk, q), b * 16 + lr) = acc[b][q];
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = d4{0, 0, 0, 0};
+#pragma unroll 2
+      for (int kk = 0; kk < 16; ++kk) {
+        const double x = p2x_at(w, mat, bi * 16 + lr, 4 * kk + lk);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = Mma<double>::mma(x, f[(b * 16 + kk) * 64 + lane], acc[b]);
+      }
     }
     // results staged through LDS, then stored as 32-byte pieces; the stores
     // are issued after the next item's loads, and the put below waits only
@@ -602,6 +647,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
     }
     __syncthreads();
     if (nxt < total) put();
+    if (PROG == P2_SEQ4_DIV && nxt < total)
+      for (int e = tid; e < P2_FRAG; e += 1024) f[e] = a.FA1[e];
     __syncthreads();
   }
 }
@@ -803,7 +850,9 @@ hipError_t launch_plane2d(const Plane2D<T>& a, hipStream_t s) {
   if (a.interleaved && (a.js != 1 || a.prog == P2_SUM_V_ACC || a.prog == P2_SEQ2_DIV))
     return hipErrorInvalidValue;
   if (!a.interleaved && a.cs != 1) return hipErrorInvalidValue;
-  if (a.prog == P2_SEQ2_DIV && (!a.lamM || !a.lamR || !a.lamC)) return hipErrorInvalidValue;
+  if ((a.prog == P2_SEQ2_DIV || a.prog == P2_SEQ4_DIV) && (!a.lamM || !a.lamR || !a.lamC))
+    return hipErrorInvalidValue;
+  if (a.prog == P2_SEQ4_DIV && !a.FA2) return hipErrorInvalidValue;
   constexpr int J = P2Shape<T>::J;
   const int64_t groups = (a.nmat + J - 1) / J;
   const int64_t items = groups * a.nvec;
@@ -820,17 +869,22 @@ hipError_t launch_plane2d(const Plane2D<T>& a, hipStream_t s) {
   if constexpr (sizeof(T) == 8) {
     // equal x modes: items of four matrices (32-byte pieces)
     const bool x4 = a.interleaved && full && vec && a.same_ab && a.nmat % 4 == 0 && a.ldx % 2 == 0 &&
-                    a.ldy % 2 == 0 && (a.prog == P2_SUM || a.prog == P2_SEQ2);
+                    a.ldy % 2 == 0 &&
+                    (a.prog == P2_SUM || a.prog == P2_SEQ2 || a.prog == P2_SEQ4_DIV);
     if (x4) {
       const int64_t items4 = (a.nmat / 4) * a.nvec;
       const unsigned grid4 = (unsigned)(items4 < P2_GRID ? items4 : P2_GRID);
       if (a.prog == P2_SUM)
         hipLaunchKernelGGL((k_plane2d_x4<P2_SUM>), dim3(grid4), dim3(1024), 0, s, b);
-      else
+      else if (a.prog == P2_SEQ2)
         hipLaunchKernelGGL((k_plane2d_x4<P2_SEQ2>), dim3(grid4), dim3(1024), 0, s, b);
+      else
+        hipLaunchKernelGGL((k_plane2d_x4<P2_SEQ4_DIV>), dim3(grid4), dim3(1024), 0, s, b);
       return hipGetLastError();
     }
   }
+  // the four-product x-slab program exists only in the four-matrix kernel
+  if (a.prog == P2_SEQ4_DIV) return hipErrorInvalidValue;
   // equal y modes: one plane per item, two workgroups per CU
   const bool y1 = !a.interleaved && full && vec && a.same_ab && a.cs == 1 && a.rs == P2_MAXN &&
                   (a.prog == P2_SUM_V_ACC || a.prog == P2_SEQ2 || a.prog == P2_SEQ2_DIV);

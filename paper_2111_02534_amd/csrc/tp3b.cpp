@@ -244,7 +244,7 @@ static void free_ops(tp3b::DevOps<T>& d) {
     for (T* p : fs)
       if (p) (void)hipFree(p);
   }
-  T* ps[] = {d.V, d.lamItem, d.work, d.G};
+  T* ps[] = {d.V, d.lamItem, d.lamItemY, d.work, d.G};
   for (T* p : ps)
     if (p) (void)hipFree(p);
   d = tp3b::DevOps<T>();
@@ -260,7 +260,8 @@ static std::vector<double> transpose(const std::vector<double>& A, int n) {
 // Host eigen-factors of the kinetic mode operators K_k = S_k diag(lam_k) S_k^{-1}.
 struct PrecFactors {
   std::vector<double> S[4], Si[4], lam[4];
-  std::vector<double> lamItem;  // 2D: lam_0[i1] + lam_1[i2]
+  std::vector<double> lamItem;   // 2D: lam_0[i1] + lam_1[i2]
+  std::vector<double> lamItemY;  // 2D: lam_2[j1] + lam_3[j2]
 };
 
 template <typename T>
@@ -285,7 +286,10 @@ static tp3b_status upload_ops(tp3b_op op, tp3b::DevOps<T>& d, const std::vector<
       }
       TP3B_HIP(upload(&d.lam[k], pf.lam[k]));
     }
-    if (op->ndim == 2) TP3B_HIP(upload(&d.lamItem, pf.lamItem));
+    if (op->ndim == 2) {
+      TP3B_HIP(upload(&d.lamItem, pf.lamItem));
+      TP3B_HIP(upload(&d.lamItemY, pf.lamItemY));
+    }
     TP3B_HIP(hipMalloc((void**)&d.work, sizeof(T) * op->N * op->work_vecs));
   }
   if (op->plane2d) {
@@ -515,6 +519,36 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
       p.X = Xv; p.Y = Yv;
       p.FA1 = d.frSi[0]; p.FB1 = d.frSi[1];
       p.same_ab = op->x_same_S;
+      if (sizeof(T) == 8 && op->x_same_S && op->y_same_S && nx1 == tp3b::P2_MAXN &&
+          nx2 == tp3b::P2_MAXN && ny1 == tp3b::P2_MAXN && ny2 == tp3b::P2_MAXN) {
+        // equal x modes and equal y modes of 64: the two x-slab transforms and
+        // the divide in one pass between the two y-plane transforms (the mode
+        // transforms commute), so the strided x slabs are read and written once:
+        // y planes S_y1^{-1} W S_y2^{-T}; x slabs S_x (S_x^{-1} W S_x^{-T} / Lambda)
+        // S_x^T; y planes S_y1 W S_y2^T
+        tp3b::Plane2D<T> q{};
+        q.prog = tp3b::P2_SEQ2;
+        q.interleaved = 0;
+        q.M = ny1; q.Nc = ny2;
+        q.rs = ny2; q.cs = 1; q.js = Ny;
+        q.nmat = (int64_t)nx1 * nx2;
+        q.nvec = nv;
+        q.ldx = ldx; q.ldy = ldy;
+        q.X = Xv; q.Y = Yv;
+        q.FA1 = d.frSi[2]; q.FB1 = d.frSi[3];
+        q.same_ab = op->y_same_S;
+        TP3B_HIP(tp3b::launch_plane2d(q, s));
+        p.prog = tp3b::P2_SEQ4_DIV;
+        p.X = Yv; p.ldx = ldy;
+        p.FA2 = d.frS[0];
+        p.lamM = d.lamItemY; p.lamR = d.lam[0]; p.lamC = d.lam[1];
+        p.sigma = op->sigma;
+        TP3B_HIP(tp3b::launch_plane2d(p, s));
+        q.X = Yv; q.ldx = ldy;
+        q.FA1 = d.frS[2]; q.FB1 = d.frS[3];
+        TP3B_HIP(tp3b::launch_plane2d(q, s));
+        continue;
+      }
       TP3B_HIP(tp3b::launch_plane2d(p, s));
       tp3b::Plane2D<T> q{};
       q.prog = tp3b::P2_SEQ2_DIV;
@@ -1031,7 +1065,8 @@ tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* ou
             for (double b : pf.lam[1]) xs.push_back(a + b);
           for (double a : pf.lam[2])
             for (double b : pf.lam[3]) ys.push_back(a + b);
-          pf.lamItem = xs;  // index i1 * n1 + i2
+          pf.lamItem = xs;   // index i1 * n1 + i2
+          pf.lamItemY = ys;  // index j1 * n3 + j2
         }
         std::vector<double> ysort = ys;
         std::sort(ysort.begin(), ysort.end());
