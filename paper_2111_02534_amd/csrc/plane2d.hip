@@ -231,10 +231,16 @@ __device__ __forceinline__ int64_t p2_slot(int g, int G) {
   return (int64_t)((l >> 3) * 64 + x * 8 + (l & 7));
 }
 
-template <typename T>
+template <typename T, bool THIRD = false>
 struct P2Smem {
   P2Buf<T> w;                 // the current work item
   T fa[P2_FRAG], fb[P2_FRAG];  // the two constant factors, fragment order
+};
+template <typename T>
+struct P2Smem<T, true> {
+  P2Buf<T> w;
+  T fa[P2_FRAG], fb[P2_FRAG];
+  T fc[P2_FRAG];  // P2_SEQ4_DIV: the back transform's factor (both sides)
 };
 
 // Persistent workgroups of 1024 threads (sixteen waves, four per SIMD), one
@@ -253,7 +259,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
   typedef P2Shape<T> S;
   constexpr int J = S::J, JW = S::JW, WB = S::WB;
   typedef typename P2Vec<T>::v vec_t;
-  __shared__ P2Smem<T> sm;
+  constexpr bool SEQ4 = PROG == P2_SEQ4_DIV;
+  __shared__ P2Smem<T, SEQ4> sm;
   P2Buf<T>& w = sm.w;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -272,19 +279,21 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
   for (int e = tid; e < P2_FRAG; e += S::NT) {
     sm.fa[e] = a.FA1[e];
     sm.fb[e] = a.FB1[e];
+    if constexpr (SEQ4) sm.fc[e] = a.FA2[e];
   }
   // the divide's row and column eigenvalues of this lane's output elements
   // (the same for every item)
+  constexpr bool DIV = PROG == P2_SEQ2_DIV || SEQ4;
   T lamr[4], lamc[WB];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int r = bi * 16 + Mma<T>::row(lk, q);
-    lamr[q] = (PROG == P2_SEQ2_DIV && r < M) ? a.lamR[r] : T(0);
+    lamr[q] = (DIV && r < M) ? a.lamR[r] : T(0);
   }
 #pragma unroll
   for (int b = 0; b < WB; ++b) {
     const int c = (bj0 + b) * 16 + lr;
-    lamc[b] = (PROG == P2_SEQ2_DIV && c < Nc) ? a.lamC[c] : T(0);
+    lamc[b] = (DIV && c < Nc) ? a.lamC[c] : T(0);
   }
   vec_t pre[S::PER];
   int64_t item = i0;
@@ -346,7 +355,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
     P2Acc<T> acc;
     p2_zero<T>(acc);
     if (active) p2_left<T, FULL>(acc, sm.fa, w, j0, bj0, bi, lane, KA, BN);
-    if (PROG == P2_SEQ2 || PROG == P2_SEQ2_DIV) {
+    if (PROG == P2_SEQ2 || PROG == P2_SEQ2_DIV || SEQ4) {
       // A W -> LDS, then (A W) B^T
       __syncthreads();
       if (active) {
@@ -362,6 +371,54 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
       p2_zero<T>(acc);
     }
     if (active) p2_right<T, FULL>(acc, sm.fb, w, j0, bj0, bi, lane, KB, BN);
+    if constexpr (SEQ4) {
+      // divide in the eigenbasis, then C Z C^T: Z -> LDS, C Z -> LDS, (C Z) C^T
+      // (entries outside the M x Nc matrices or past the last matrix are set
+      // to zero, so they add nothing to the back transform)
+      if (active) {
+#pragma unroll
+        for (int j = 0; j < JW; ++j) {
+          const int64_t m = m0 + j0 + j;
+          const T lm = (m < a.nmat) ? a.lamM[m] - T(a.sigma) : T(0);
+#pragma unroll
+          for (int b = 0; b < WB; ++b) {
+            const int c = (bj0 + b) * 16 + lr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int r = bi * 16 + Mma<T>::row(lk, q);
+              const bool ok = m < a.nmat && (FULL || (r < M && c < Nc));
+              acc[j][b][q] = ok ? acc[j][b][q] / (lm + lamr[q] + lamc[b]) : T(0);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int j = 0; j < JW; ++j)
+#pragma unroll
+          for (int b = 0; b < WB; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              w[j0 + j][bi * 16 + Mma<T>::row(lk, q)][(bj0 + b) * 16 + lr] = acc[j][b][q];
+      }
+      __syncthreads();
+      p2_zero<T>(acc);
+      if (active) p2_left<T, FULL>(acc, sm.fc, w, j0, bj0, bi, lane, KA, BN);
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int j = 0; j < JW; ++j)
+#pragma unroll
+          for (int b = 0; b < WB; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              w[j0 + j][bi * 16 + Mma<T>::row(lk, q)][(bj0 + b) * 16 + lr] = acc[j][b][q];
+      }
+      __syncthreads();
+      p2_zero<T>(acc);
+      if (active) p2_right<T, FULL>(acc, sm.fc, w, j0, bj0, bi, lane, KB, BN);
+    }
 
     // Results are formed in registers; the next item is put into LDS before
     // they are stored, so that waiting for its loads does not also wait for
@@ -883,8 +940,14 @@ hipError_t launch_plane2d(const Plane2D<T>& a, hipStream_t s) {
       return hipGetLastError();
     }
   }
-  // the four-product x-slab program exists only in the four-matrix kernel
-  if (a.prog == P2_SEQ4_DIV) return hipErrorInvalidValue;
+  // the four-product program: x slabs with equal x modes (one factor per half)
+  if (a.prog == P2_SEQ4_DIV) {
+    // FP64 runs it in the four-matrix kernel above (the generic one has no LDS
+    // left for the third factor in FP64)
+    if (sizeof(T) != 4 || !a.interleaved || !a.same_ab) return hipErrorInvalidValue;
+    if constexpr (sizeof(T) == 4) launch_p2<T, P2_SEQ4_DIV, true>(b, full, vec, grid, s);
+    return hipGetLastError();
+  }
   // equal y modes: one plane per item, two workgroups per CU
   const bool y1 = !a.interleaved && full && vec && a.same_ab && a.cs == 1 && a.rs == P2_MAXN &&
                   (a.prog == P2_SUM_V_ACC || a.prog == P2_SEQ2 || a.prog == P2_SEQ2_DIV);

@@ -519,13 +519,18 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
       p.X = Xv; p.Y = Yv;
       p.FA1 = d.frSi[0]; p.FB1 = d.frSi[1];
       p.same_ab = op->x_same_S;
-      if (sizeof(T) == 8 && op->x_same_S && op->y_same_S && nx1 == tp3b::P2_MAXN &&
-          nx2 == tp3b::P2_MAXN && ny1 == tp3b::P2_MAXN && ny2 == tp3b::P2_MAXN) {
-        // equal x modes and equal y modes of 64: the two x-slab transforms and
-        // the divide in one pass between the two y-plane transforms (the mode
-        // transforms commute), so the strided x slabs are read and written once:
-        // y planes S_y1^{-1} W S_y2^{-T}; x slabs S_x (S_x^{-1} W S_x^{-T} / Lambda)
-        // S_x^T; y planes S_y1 W S_y2^T
+      // equal x modes (FP64: both 64 wide, the y groups in fours and 16-byte
+      // aligned vectors, for the four-matrix kernel)
+      const bool seq4 =
+          op->x_same_S &&
+          (sizeof(T) == 4 ||
+           (nx1 == tp3b::P2_MAXN && nx2 == tp3b::P2_MAXN && Ny % 4 == 0 && ldx % 2 == 0 &&
+            ldy % 2 == 0 && (uintptr_t)X % 16 == 0 && (uintptr_t)Y % 16 == 0));
+      if (seq4) {
+        // the two x-slab transforms and the divide in one pass between the two
+        // y-plane transforms (the mode transforms commute), so the strided x
+        // slabs are read and written once: y planes S_y1^{-1} W S_y2^{-T}; x
+        // slabs S_x (S_x^{-1} W S_x^{-T} / Lambda) S_x^T; y planes S_y1 W S_y2^T
         tp3b::Plane2D<T> q{};
         q.prog = tp3b::P2_SEQ2;
         q.interleaved = 0;
