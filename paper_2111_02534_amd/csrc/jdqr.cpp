@@ -185,8 +185,11 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
   const bool urres_fused = N >= (1 << 20) && m_max + b <= 128 && b <= 16;
   if (!urres_fused) TP3B_HIP(dalloc(AUb, sizeof(double) * N * b));
   TP3B_HIP(dalloc(AVb, sizeof(double) * N * av_cols));
-  // same capacity as A V: the two buffers swap roles after a rotation
-  TP3B_HIP(dalloc(TMPb, sizeof(double) * N * av_cols));
+  // long blocks rotate V and A V in place (the search space never holds more
+  // than m_max <= 64 columns there); the others through a scratch basis of
+  // A V's capacity, the two swapping roles after a rotation
+  const bool rot_inplace = N >= (1 << 20) && m_max <= 64;
+  if (!rot_inplace) TP3B_HIP(dalloc(TMPb, sizeof(double) * N * av_cols));
   TP3B_HIP(dalloc(Rresb, sizeof(double) * N * b));
   if (use_prec) {
     TP3B_HIP(dalloc(PQb, sizeof(double) * N * qt_max));
@@ -377,13 +380,16 @@ static tp3b_status jdqr_run(tp3b_op op, const tp3b_jdqr_opts& o, const double* X
       std::vector<double> Sc = colmajor(S, m, 0, 0, m, q);
       std::memcpy(P(r_upS), Sc.data(), sizeof(double) * m * q);
       TP3B_HIP(hipMemcpyAsync(dS, P(r_upS), sizeof(double) * m * q, hipMemcpyHostToDevice, s));
-      if (N >= (1 << 20) && m <= 128 && q <= 64) {
-        // long blocks: in place, row by row (no copy back)
+      if (rot_inplace) {
+        // long blocks: both in place, row by row (A V keeps its column offset;
+        // the offset grows only with locking, by at most nev in all, which its
+        // buffer allows for)
         TP3B_HIP(launch_gemm_nn_rows_inplace(N, m, q, V(), N, dS, m, s));
-      } else {
-        TP3B_HIP(launch_gemm_nn<double>(N, m, q, 1.0, V(), N, dS, m, 0.0, TMP, N, s));
-        TP3B_HIP(hipMemcpyAsync(V(), TMP, sizeof(double) * N * q, hipMemcpyDeviceToDevice, s));
+        TP3B_HIP(launch_gemm_nn_rows_inplace(N, m, q, AV(), N, dS, m, s));
+        return TP3B_OK;
       }
+      TP3B_HIP(launch_gemm_nn<double>(N, m, q, 1.0, V(), N, dS, m, 0.0, TMP, N, s));
+      TP3B_HIP(hipMemcpyAsync(V(), TMP, sizeof(double) * N * q, hipMemcpyDeviceToDevice, s));
       TP3B_HIP(launch_gemm_nn<double>(N, m, q, 1.0, AV(), N, dS, m, 0.0, TMP, N, s));
       // the rotated A V stays where it was written (no copy back)
       std::swap(AVbase, TMP);
