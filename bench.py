@@ -43,9 +43,9 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per 8-vector apply of the 2D Hamiltonian at c5 (FP64; the two plane
 # passes, run vector by vector): rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by
 # what the counter reads for a 256 MiB device copy in the same run
-# (profiles/hbm_traffic_c5_plane_passes_fp64.md; 5,671,854 KiB).  Set to None
+# (profiles/hbm_traffic_c5_plane_passes_fp64.md; 5,682,882 KiB).  Set to None
 # when the plane kernels change until the counters are taken again.
-TRAFFIC_BYTES = {"c5": 5671854 * 1024}
+TRAFFIC_BYTES = {"c5": 5682882 * 1024}
 
 
 def apply_flops(ndim, n, kind="H"):
