@@ -316,8 +316,9 @@ static int prec_index(bool f64, bool bf3) { return f64 ? TP3B_FP64 : (bf3 ? TP3B
 // 64 MB and more (a vector and its partial result then stay in the 256 MB
 // Infinity Cache between the passes), the whole block otherwise.
 template <typename T>
-static int plane2d_vec_group(int64_t N, int nvec) {
-  return (sizeof(T) == 8 && N * (int64_t)sizeof(T) >= (int64_t)(64 << 20)) ? 1 : std::max(nvec, 1);
+static int plane2d_vec_group(int64_t N, int nvec, bool prec = false) {
+  if (sizeof(T) == 8 && N * (int64_t)sizeof(T) >= (int64_t)(64 << 20)) return prec ? 4 : 1;
+  return std::max(nvec, 1);
 }
 
 static int tile_for(tp3b_op op, bool f64, bool bf3, int kind, int M, int Nc, int64_t nbatch) {
@@ -501,9 +502,12 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
     // others work in place).
     const int nx1 = op->n[0], nx2 = op->n[1], ny1 = op->n[2], ny2 = op->n[3];
     const int64_t Ny = (int64_t)ny1 * ny2;
-    // one vector at a time for large FP64 vectors (each pass after the first
-    // then works on a vector that is in the Infinity Cache)
-    const int vb = plane2d_vec_group<T>(N, nvec);
+    // large FP64 vectors in groups of four: each pass after the first then
+    // finds part of its input in the Infinity Cache, and each launch has four
+    // vectors over which to spread the fill and drain of its persistent
+    // workgroups (c5, 8 vectors: 2.91 ms against 3.02 ms one at a time and
+    // 2.93 ms for all eight at once)
+    const int vb = plane2d_vec_group<T>(N, nvec, true);
     for (int v0 = 0; v0 < nvec; v0 += vb) {
       const int nv = std::min(vb, nvec - v0);
       const T* Xv = X + (int64_t)v0 * ldx;
