@@ -933,53 +933,90 @@ hipError_t launch_gemm_nn_x0(int64_t N, int p, int q, double alpha, const T* A, 
                      ldx0, Y, ldy);
   return hipGetLastError();
 }
-// A[:, :q] = A C in place, one row per thread over all of A's p columns (the
-// row is read whole before any of it is written; no restrict on A).
-template <int QB>
+// A[:, :q] = A C in place on the matrix cores.  Each wave takes tiles of 16
+// rows: it loads the tile's p columns as the B operand of v_mfma_f64_16x16x4
+// (lane l: row l % 16, column 4 ks + l / 16 of k-step ks), and forms
+// (A C)^T = C^T A^T per 16-column block with C^T as the A operand, staged once
+// per workgroup in LDS in fragment order.  Every load of a tile has been
+// consumed before the tile is written, and tiles do not share rows (no
+// restrict on A).  The output element of lane l, register r, is row l % 16 and
+// column 16 jb + l / 16 + 4 r, so each store instruction writes 16 consecutive
+// rows of four columns.  Loads past N or p read a clamped row or column; the
+// staged C is zero beyond p and q, so those terms add zero.  KS bounds the
+// k-steps (p <= 4 KS) and JB the 16-column blocks (q <= 16 JB).
+template <int KS, int JB>
 __global__ __launch_bounds__(256) void k_gemm_rows_inplace(int64_t N, int p, int q, double* A,
                                                            int64_t lda,
                                                            const double* __restrict__ C, int ldc) {
-  __shared__ double Cs[GEMM_PB][QB];
-  for (int e = threadIdx.x; e < GEMM_PB * QB; e += 256) {
-    const int i = e / QB, j = e % QB;
-    Cs[i][j] = (i < p && j < q) ? C[i + (int64_t)j * ldc] : 0.0;
+  extern __shared__ double Cf[];  // [nks][JB][64]
+  const int nks = (p + 3) / 4;
+  for (int e = threadIdx.x; e < nks * JB * 64; e += 256) {
+    const int ks = e / (JB * 64), jb = (e / 64) % JB, l = e % 64;
+    const int k = 4 * ks + l / 16, j = 16 * jb + l % 16;
+    Cf[e] = (k < p && j < q) ? C[k + (int64_t)j * ldc] : 0.0;
   }
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += stride) {
-    double acc[QB];
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const int64_t ntiles = (N + 15) / 16;
+  const int64_t wstride = (int64_t)gridDim.x * 4;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < ntiles; t += wstride) {
+    const int64_t r0 = t * 16;
+    const int64_t row = r0 + lr < N ? r0 + lr : N - 1;
+    double b[KS];
 #pragma unroll
-    for (int j = 0; j < QB; ++j) acc[j] = 0.0;
-    for (int i0 = 0; i0 < p; i0 += 8) {
-      double av[8];
+    for (int ks = 0; ks < KS; ++ks) {
+      const int c = 4 * ks + lk < p ? 4 * ks + lk : p - 1;
+      b[ks] = ks < nks ? A[row + (int64_t)c * lda] : 0.0;
+    }
+    d4 acc[JB];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) av[u] = (i0 + u < p) ? A[r + (int64_t)(i0 + u) * lda] : 0.0;
+    for (int jb = 0; jb < JB; ++jb) acc[jb] = d4{0, 0, 0, 0};
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (i0 + u < p) {
+    for (int ks = 0; ks < KS; ++ks)
+      if (ks < nks) {
 #pragma unroll
-          for (int j = 0; j < QB; ++j) acc[j] += av[u] * Cs[i0 + u][j];
+        for (int jb = 0; jb < JB; ++jb)
+          acc[jb] = Mma<double>::mma(Cf[(ks * JB + jb) * 64 + lane], b[ks], acc[jb]);
+      }
+    if (r0 + lr < N) {
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = 16 * jb + Mma<double>::row(lk, r);
+          if (col < q) A[r0 + lr + (int64_t)col * lda] = acc[jb][r];
         }
     }
-#pragma unroll
-    for (int j = 0; j < QB; ++j)
-      if (j < q) A[r + (int64_t)j * lda] = acc[j];
   }
+}
+
+template <int KS>
+static void launch_rows_inplace_ks(unsigned gx, int64_t N, int p, int q, double* A, int64_t lda,
+                                   const double* C, int ldc, hipStream_t s) {
+  const int jb = (q + 15) / 16;
+  const size_t lds = (size_t)((p + 3) / 4) * (jb <= 1 ? 1 : jb <= 2 ? 2 : 4) * 64 * sizeof(double);
+  if (jb <= 1)
+    hipLaunchKernelGGL((k_gemm_rows_inplace<KS, 1>), dim3(gx), dim3(256), lds, s, N, p, q, A, lda, C, ldc);
+  else if (jb <= 2)
+    hipLaunchKernelGGL((k_gemm_rows_inplace<KS, 2>), dim3(gx), dim3(256), lds, s, N, p, q, A, lda, C, ldc);
+  else
+    hipLaunchKernelGGL((k_gemm_rows_inplace<KS, 4>), dim3(gx), dim3(256), lds, s, N, p, q, A, lda, C, ldc);
 }
 
 hipError_t launch_gemm_nn_rows_inplace(int64_t N, int p, int q, double* A, int64_t lda,
                                        const double* C, int ldc, hipStream_t s) {
-  if (N < GEMM_LONG_N || p > GEMM_PB || q > p || q < 1) return hipErrorInvalidValue;
-  const int64_t rb = (N + 255) / 256;
-  const unsigned gx = (unsigned)(rb < GEMM_LONG_WG ? rb : GEMM_LONG_WG);
-  if (q <= 16)
-    hipLaunchKernelGGL((k_gemm_rows_inplace<16>), dim3(gx), dim3(256), 0, s, N, p, q, A, lda, C, ldc);
-  else if (q <= 32)
-    hipLaunchKernelGGL((k_gemm_rows_inplace<32>), dim3(gx), dim3(256), 0, s, N, p, q, A, lda, C, ldc);
-  else if (q <= 64)
-    hipLaunchKernelGGL((k_gemm_rows_inplace<64>), dim3(gx), dim3(256), 0, s, N, p, q, A, lda, C, ldc);
+  if (N < GEMM_LONG_N || p > GEMM_PB || q > p || q < 1 || q > 64) return hipErrorInvalidValue;
+  // four waves per workgroup, each over 16-row tiles
+  const int64_t wg = ((N + 15) / 16 + 3) / 4;
+  const unsigned gx = (unsigned)(wg < GEMM_LONG_WG ? wg : GEMM_LONG_WG);
+  if (p <= 32)
+    launch_rows_inplace_ks<8>(gx, N, p, q, A, lda, C, ldc, s);
+  else if (p <= 64)
+    launch_rows_inplace_ks<16>(gx, N, p, q, A, lda, C, ldc, s);
+  else if (p <= 96)
+    launch_rows_inplace_ks<24>(gx, N, p, q, A, lda, C, ldc, s);
   else
-    return hipErrorInvalidValue;
+    launch_rows_inplace_ks<32>(gx, N, p, q, A, lda, C, ldc, s);
   return hipGetLastError();
 }
 
