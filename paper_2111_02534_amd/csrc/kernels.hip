@@ -942,15 +942,15 @@ hipError_t launch_gemm_nn_x0(int64_t N, int p, int q, double alpha, const T* A, 
 // restrict on A).  The output element of lane l, register r, is row l % 16 and
 // column 16 jb + l / 16 + 4 r, so each store instruction writes 16 consecutive
 // rows of four columns.  Loads past N or p read a clamped row or column; the
-// staged C is zero beyond p and q, so those terms add zero.  KS bounds the
-// k-steps (p <= 4 KS) and JB the 16-column blocks (q <= 16 JB).
-template <int KS, int JB>
+// staged C is zero beyond p and q, so those terms add zero.  KS is the number
+// of k-steps (p <= 4 KS, launched with the smallest multiple of 4 that holds
+// p) and JB the number of 16-column blocks (q <= 16 JB).
+template <int KS, int JB, bool FULL>
 __global__ __launch_bounds__(256) void k_gemm_rows_inplace(int64_t N, int p, int q, double* A,
                                                            int64_t lda,
                                                            const double* __restrict__ C, int ldc) {
-  extern __shared__ double Cf[];  // [nks][JB][64]
-  const int nks = (p + 3) / 4;
-  for (int e = threadIdx.x; e < nks * JB * 64; e += 256) {
+  extern __shared__ double Cf[];  // [KS][JB][64]
+  for (int e = threadIdx.x; e < KS * JB * 64; e += 256) {
     const int ks = e / (JB * 64), jb = (e / 64) % JB, l = e % 64;
     const int k = 4 * ks + l / 16, j = 16 * jb + l % 16;
     Cf[e] = (k < p && j < q) ? C[k + (int64_t)j * ldc] : 0.0;
@@ -959,34 +959,51 @@ __global__ __launch_bounds__(256) void k_gemm_rows_inplace(int64_t N, int p, int
   const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
   const int64_t ntiles = (N + 15) / 16;
   const int64_t wstride = (int64_t)gridDim.x * 4;
-  for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < ntiles; t += wstride) {
-    const int64_t r0 = t * 16;
-    const int64_t row = r0 + lr < N ? r0 + lr : N - 1;
-    double b[KS];
+  // this lane's row of tile t (clamped), and its column of k-step ks (clamped)
+  auto load = [&](int64_t t, double* b) {
+    const int64_t row = t * 16 + lr < N ? t * 16 + lr : N - 1;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int c = 4 * ks + lk < p ? 4 * ks + lk : p - 1;
-      b[ks] = ks < nks ? A[row + (int64_t)c * lda] : 0.0;
+      b[ks] = A[row + (int64_t)c * lda];
     }
+  };
+  int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  double b[KS];
+  if (t < ntiles) load(t, b);
+  for (; t < ntiles; t += wstride) {
+    const int64_t r0 = t * 16;
+    // the next tile's loads go out before this tile's products (other rows:
+    // no tile of this wave's is written before it has been read)
+    double bn[KS];
+    load(t + wstride < ntiles ? t + wstride : t, bn);
     d4 acc[JB];
 #pragma unroll
     for (int jb = 0; jb < JB; ++jb) acc[jb] = d4{0, 0, 0, 0};
+    // no branch between the products (a branch would move the accumulators
+    // between register files at every join), and a scheduling barrier every
+    // two k-steps keeps each step's fragment reads next to its products
+    // instead of all of them held in registers
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-      if (ks < nks) {
+    for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
-        for (int jb = 0; jb < JB; ++jb)
-          acc[jb] = Mma<double>::mma(Cf[(ks * JB + jb) * 64 + lane], b[ks], acc[jb]);
-      }
-    if (r0 + lr < N) {
+      for (int jb = 0; jb < JB; ++jb)
+        acc[jb] = Mma<double>::mma(Cf[(ks * JB + jb) * 64 + lane], b[ks], acc[jb]);
+      if (ks % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    // FULL (q = 16 JB, N a multiple of 16): every lane stores every element,
+    // with no masked branch whose join would wait for the prefetch as well
+    if (FULL || r0 + lr < N) {
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int col = 16 * jb + Mma<double>::row(lk, r);
-          if (col < q) A[r0 + lr + (int64_t)col * lda] = acc[jb][r];
+          if (FULL || col < q) A[r0 + lr + (int64_t)col * lda] = acc[jb][r];
         }
     }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) b[ks] = bn[ks];
   }
 }
 
@@ -994,13 +1011,20 @@ template <int KS>
 static void launch_rows_inplace_ks(unsigned gx, int64_t N, int p, int q, double* A, int64_t lda,
                                    const double* C, int ldc, hipStream_t s) {
   const int jb = (q + 15) / 16;
-  const size_t lds = (size_t)((p + 3) / 4) * (jb <= 1 ? 1 : jb <= 2 ? 2 : 4) * 64 * sizeof(double);
-  if (jb <= 1)
-    hipLaunchKernelGGL((k_gemm_rows_inplace<KS, 1>), dim3(gx), dim3(256), lds, s, N, p, q, A, lda, C, ldc);
-  else if (jb <= 2)
-    hipLaunchKernelGGL((k_gemm_rows_inplace<KS, 2>), dim3(gx), dim3(256), lds, s, N, p, q, A, lda, C, ldc);
-  else
-    hipLaunchKernelGGL((k_gemm_rows_inplace<KS, 4>), dim3(gx), dim3(256), lds, s, N, p, q, A, lda, C, ldc);
+  const int JBl = jb <= 1 ? 1 : jb <= 2 ? 2 : 4;
+  const size_t lds = (size_t)KS * JBl * 64 * sizeof(double);
+  const bool full = q == 16 * JBl && N % 16 == 0;
+#define TP3B_ROWS_INPLACE(JBV, FV)                                                                 \
+  hipLaunchKernelGGL((k_gemm_rows_inplace<KS, JBV, FV>), dim3(gx), dim3(256), lds, s, N, p, q, A, \
+                     lda, C, ldc)
+  if (JBl == 1) {
+    if (full) TP3B_ROWS_INPLACE(1, true); else TP3B_ROWS_INPLACE(1, false);
+  } else if (JBl == 2) {
+    if (full) TP3B_ROWS_INPLACE(2, true); else TP3B_ROWS_INPLACE(2, false);
+  } else {
+    if (full) TP3B_ROWS_INPLACE(4, true); else TP3B_ROWS_INPLACE(4, false);
+  }
+#undef TP3B_ROWS_INPLACE
 }
 
 hipError_t launch_gemm_nn_rows_inplace(int64_t N, int p, int q, double* A, int64_t lda,
@@ -1009,14 +1033,16 @@ hipError_t launch_gemm_nn_rows_inplace(int64_t N, int p, int q, double* A, int64
   // four waves per workgroup, each over 16-row tiles
   const int64_t wg = ((N + 15) / 16 + 3) / 4;
   const unsigned gx = (unsigned)(wg < GEMM_LONG_WG ? wg : GEMM_LONG_WG);
-  if (p <= 32)
-    launch_rows_inplace_ks<8>(gx, N, p, q, A, lda, C, ldc, s);
-  else if (p <= 64)
-    launch_rows_inplace_ks<16>(gx, N, p, q, A, lda, C, ldc, s);
-  else if (p <= 96)
-    launch_rows_inplace_ks<24>(gx, N, p, q, A, lda, C, ldc, s);
-  else
-    launch_rows_inplace_ks<32>(gx, N, p, q, A, lda, C, ldc, s);
+  switch ((p + 15) / 16) {  // k-steps: the multiple of 4 that holds p
+    case 1:
+    case 2: launch_rows_inplace_ks<8>(gx, N, p, q, A, lda, C, ldc, s); break;
+    case 3: launch_rows_inplace_ks<12>(gx, N, p, q, A, lda, C, ldc, s); break;
+    case 4: launch_rows_inplace_ks<16>(gx, N, p, q, A, lda, C, ldc, s); break;
+    case 5: launch_rows_inplace_ks<20>(gx, N, p, q, A, lda, C, ldc, s); break;
+    case 6: launch_rows_inplace_ks<24>(gx, N, p, q, A, lda, C, ldc, s); break;
+    case 7: launch_rows_inplace_ks<28>(gx, N, p, q, A, lda, C, ldc, s); break;
+    default: launch_rows_inplace_ks<32>(gx, N, p, q, A, lda, C, ldc, s); break;
+  }
   return hipGetLastError();
 }
 
