@@ -1290,23 +1290,28 @@ __global__ __launch_bounds__(256) void k_bupdate_dot_red(int64_t N, int b, int n
 #pragma unroll
   for (int i = 0; i < NBM; ++i) acc[i] = 0.0;
   T* Wj = W + (int64_t)j * N;
-  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < N; r += (int64_t)gridDim.x * 256) {
-    // the update of bupdate_row (same terms, same order), keeping the basis
-    // values for the dots
-    double v[NBM];
-    double sum = 0.0;
+  // every load is issued (a basis vector past nb reads vector nb - 1, and one
+  // whose coefficient is zero is read too, though neither value is used): no
+  // load sits behind a branch, whose join would wait for all of them
+  auto load = [&](int64_t r, double* v, T& w) {
 #pragma unroll
     for (int i = 0; i < NBM; ++i) {
-      const double h = (i < nb) ? hs[i] : 0.0;
-      v[i] = (i < nb && (h != 0.0 || !self)) ? (double)V[(int64_t)i * bs + (int64_t)j * N + r] : 0.0;
+      const int ic = i < nb ? i : nb - 1;
+      v[i] = (double)V[(int64_t)ic * bs + (int64_t)j * N + r];
     }
+    w = Wj[r];
+  };
+  // the update of bupdate_row (same terms, same order), keeping the basis
+  // values for the dots
+  auto row = [&](int64_t r, const double* v, T w) {
+    double sum = 0.0;
     // ascending i, as bupdate_row adds them
 #pragma unroll
     for (int i = 0; i < NBM; ++i) {
       const double h = (i < nb) ? hs[i] : 0.0;
       if (h != 0.0) sum += v[i] * h;
     }
-    const T wn = (T)((double)Wj[r] + alpha * sum);
+    const T wn = (T)((double)w + alpha * sum);
     Wj[r] = wn;
     const double wd = (double)wn;
     if (self) {
@@ -1316,6 +1321,26 @@ __global__ __launch_bounds__(256) void k_bupdate_dot_red(int64_t N, int b, int n
       for (int i = 0; i < NBM; ++i)
         if (i < nb) acc[i] += v[i] * wd;
     }
+  };
+  // each thread takes its rows in stride order, RU at a time with all of
+  // their loads in flight (fewer for longer bases, whose rows need more
+  // registers), then one at a time (the same order either way)
+  constexpr int RU = NBM <= 4 ? 4 : NBM <= 8 ? 2 : 1;
+  const int64_t S = (int64_t)gridDim.x * 256;
+  int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; r + (RU - 1) * S < N; r += RU * S) {
+    double v[RU][NBM];
+    T w[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) load(r + u * S, v[u], w[u]);
+#pragma unroll
+    for (int u = 0; u < RU; ++u) row(r + u * S, v[u], w[u]);
+  }
+  for (; r < N; r += S) {
+    double v[NBM];
+    T w;
+    load(r, v, w);
+    row(r, v, w);
   }
   const int nd = self ? 1 : nb;
 #pragma unroll
