@@ -1078,6 +1078,58 @@ __global__ __launch_bounds__(256) void k_bdot_diag(int64_t N, int b, int nb, con
   bdot_chunk<T>(N, nb, V, bs, W, rows, chunk, j, part + ((int64_t)chunk * b + j) * BD_MAXNB, sm);
 }
 
+// The same partials as bdot_chunk (the same products added in the same order:
+// per step of four rows, basis block by basis block, row by row) for bases of
+// at most NBM blocks, with every load of a step issued before its products:
+// rows past the chunk read its last row and blocks past nb read block nb - 1,
+// and neither is added, so no load waits behind a branch.
+template <typename T, int NBM>
+__global__ __launch_bounds__(256) void k_bdot_diag_n(int64_t N, int b, int nb, const T* __restrict__ V,
+                                                     int64_t bs, const T* __restrict__ W, int rows,
+                                                     double* __restrict__ part) {
+  __shared__ double red[NBM][4];
+  const int j = blockIdx.y, chunk = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t rbeg = (int64_t)chunk * rows;
+  const int64_t rend = (rbeg + rows < N) ? rbeg + rows : N;
+  double acc[NBM];
+#pragma unroll
+  for (int i = 0; i < NBM; ++i) acc[i] = 0.0;
+  const T* Wj = W + (int64_t)j * N;
+  for (int64_t r = rbeg + tid; r < rend; r += 1024) {
+    int64_t rq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rq[q] = (r + 256 * q < rend) ? r + 256 * q : rend - 1;
+    double w[4], v[NBM][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = (double)Wj[rq[q]];
+#pragma unroll
+    for (int i = 0; i < NBM; ++i) {
+      const T* Vi = V + (int64_t)(i < nb ? i : nb - 1) * bs + (int64_t)j * N;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[i][q] = (double)Vi[rq[q]];
+    }
+#pragma unroll
+    for (int i = 0; i < NBM; ++i)
+      if (i < nb) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (r + 256 * q < rend) acc[i] += v[i][q] * w[q];
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < NBM; ++i) {
+    if (i < nb) {
+      double x = acc[i];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+      if (lane == 0) red[i][wave] = x;
+    }
+  }
+  __syncthreads();
+  if (tid < nb)
+    part[((int64_t)chunk * b + j) * BD_MAXNB + tid] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+}
+
 __global__ __launch_bounds__(256) void k_bdot_reduce(int b, int nb, int nchunk,
                                                      const double* __restrict__ part,
                                                      double* __restrict__ H, int hld) {
@@ -1096,8 +1148,21 @@ hipError_t launch_bdot_diag(int64_t N, int b, int nb, const T* V, int64_t bs, co
   if (nb > BD_MAXNB) return hipErrorInvalidValue;
   const int rows = bdot_rows(N);
   const int nchunk = (int)((N + rows - 1) / rows);
-  hipLaunchKernelGGL((k_bdot_diag<T>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W, rows,
-                     partial);
+  if (nb == 1)
+    hipLaunchKernelGGL((k_bdot_diag_n<T, 1>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W,
+                       rows, partial);
+  else if (nb == 2)
+    hipLaunchKernelGGL((k_bdot_diag_n<T, 2>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W,
+                       rows, partial);
+  else if (nb <= 4)
+    hipLaunchKernelGGL((k_bdot_diag_n<T, 4>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W,
+                       rows, partial);
+  else if (nb <= 8)
+    hipLaunchKernelGGL((k_bdot_diag_n<T, 8>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W,
+                       rows, partial);
+  else
+    hipLaunchKernelGGL((k_bdot_diag<T>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W, rows,
+                       partial);
   hipLaunchKernelGGL(k_bdot_reduce, dim3((b * nb + 3) / 4), dim3(256), 0, s, b, nb, nchunk, partial,
                      H, hld);
   return hipGetLastError();
@@ -1163,8 +1228,21 @@ hipError_t launch_bdot_partials(int64_t N, int b, int nb, const T* V, int64_t bs
   if (nb > BD_MAXNB) return hipErrorInvalidValue;
   const int rows = bdot_rows(N);
   const int nchunk = (int)((N + rows - 1) / rows);
-  hipLaunchKernelGGL((k_bdot_diag<T>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W, rows,
-                     partial);
+  if (nb == 1)
+    hipLaunchKernelGGL((k_bdot_diag_n<T, 1>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W,
+                       rows, partial);
+  else if (nb == 2)
+    hipLaunchKernelGGL((k_bdot_diag_n<T, 2>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W,
+                       rows, partial);
+  else if (nb <= 4)
+    hipLaunchKernelGGL((k_bdot_diag_n<T, 4>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W,
+                       rows, partial);
+  else if (nb <= 8)
+    hipLaunchKernelGGL((k_bdot_diag_n<T, 8>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W,
+                       rows, partial);
+  else
+    hipLaunchKernelGGL((k_bdot_diag<T>), dim3(nchunk, b), dim3(256), 0, s, N, b, nb, V, bs, W, rows,
+                       partial);
   return hipGetLastError();
 }
 template hipError_t launch_bdot_partials<double>(int64_t, int, int, const double*, int64_t,
