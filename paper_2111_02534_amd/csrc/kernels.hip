@@ -1312,10 +1312,26 @@ __global__ __launch_bounds__(256) void k_normalize_cols_red(int64_t N, int b, in
   __shared__ double hs[1];
   bdot_sum_column(b, 1, nchunk, blockIdx.y, part, nullptr, 0, hs);
   const int64_t r0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  // row 0 (N = 0 included) also stores the norm
-  if (r0 == 0 && N == 0) normalize_row_n2<T>(N, hs[0], W, Vout, hout, hld, 0, blockIdx.y);
-  for (int64_t r = r0; r < N; r += (int64_t)gridDim.x * 256)
-    normalize_row_n2<T>(N, hs[0], W, Vout, hout, hld, r, blockIdx.y);
+  const int j = blockIdx.y;
+  // the norm and its reciprocal as normalize_row_n2 forms them; row 0 (N = 0
+  // included) stores the norm
+  const double h = hs[0] > 0.0 ? sqrt(hs[0]) : 0.0;
+  const double inv = h > 0.0 ? 1.0 / h : 0.0;
+  if (r0 == 0 && hout) hout[(int64_t)j * hld] = h;
+  const T* Wj = W + (int64_t)j * N;
+  T* Vj = Vout + (int64_t)j * N;
+  // four rows per thread at a time, their loads all issued first, then the
+  // rows left one at a time
+  const int64_t S = (int64_t)gridDim.x * 256;
+  int64_t r = r0;
+  for (; r + 3 * S < N; r += 4 * S) {
+    T w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = Wj[r + u * S];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) Vj[r + u * S] = (T)((double)w[u] * inv);
+  }
+  for (; r < N; r += S) Vj[r] = (T)((double)Wj[r] * inv);
 }
 
 template <typename T>
