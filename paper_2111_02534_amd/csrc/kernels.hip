@@ -805,11 +805,13 @@ __global__ __launch_bounds__(256) void k_gemm_nn_long(int64_t N, int p, int q, d
     double acc[QB];
 #pragma unroll
     for (int j = 0; j < QB; ++j) acc[j] = 0.0;
-    // eight columns of A per step, fetched before they are used
+    // eight columns of A per step, fetched before they are used; the loads
+    // are unconditional (a column past p reads column p - 1, not added), so
+    // none waits behind a branch
     for (int i0 = 0; i0 < p; i0 += 8) {
       double av[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) av[u] = (i0 + u < p) ? (double)A[r + (int64_t)(i0 + u) * lda] : 0.0;
+      for (int u = 0; u < 8; ++u) av[u] = (double)A[r + (int64_t)(i0 + u < p ? i0 + u : p - 1) * lda];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
         if (i0 + u < p) {
@@ -817,14 +819,21 @@ __global__ __launch_bounds__(256) void k_gemm_nn_long(int64_t N, int p, int q, d
           for (int j = 0; j < QB; ++j) acc[j] += av[u] * Cs[i0 + u][j];
         }
     }
+    // the old values of all output columns are fetched before any is stored
+    double old[QB];
+    if (beta != 0.0) {
 #pragma unroll
-    for (int j = 0; j < QB; ++j) {
-      if (j < nq) {
-        T* y = Y + r + (int64_t)(q0 + j) * ldy;
-        const double old = (beta != 0.0) ? (double)(X0 ? X0[r + (int64_t)(q0 + j) * ldx0] : *y) : 0.0;
-        *y = (T)(beta * old + alpha * acc[j]);
+      for (int j = 0; j < QB; ++j) {
+        const int64_t jc = q0 + (j < nq ? j : nq - 1);
+        old[j] = (double)(X0 ? X0[r + jc * ldx0] : Y[r + jc * ldy]);
       }
+    } else {
+#pragma unroll
+      for (int j = 0; j < QB; ++j) old[j] = 0.0;
     }
+#pragma unroll
+    for (int j = 0; j < QB; ++j)
+      if (j < nq) Y[r + (int64_t)(q0 + j) * ldy] = (T)(beta * old[j] + alpha * acc[j]);
   }
 }
 
