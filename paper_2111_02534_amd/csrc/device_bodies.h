@@ -329,6 +329,18 @@ __device__ __forceinline__ void modeprod_bf3_tile(const ModeProd<float>& a, int6
   const int nchunks = nL + nR;
   float ra[OA][8], rb[OB][8];
 
+  // constant operands split once (a.Lhl, a.Rhl: hi block then lo block of
+  // raw bf16 bits) are read as 16 bytes of hi and 16 of lo per octet into the
+  // same registers and staged without a split; rows or columns past the
+  // matrix read its last one and are staged as zeros
+  const uint16_t* Lhl = a.L ? a.Lhl : nullptr;
+  const uint16_t* Rhl = a.R ? a.Rhl : nullptr;
+  auto load_hl = [&](const uint16_t* base, int64_t nn, int64_t off, float* out) {
+    const f4 h = *(const f4*)(base + off);
+    const f4 l = *(const f4*)(base + nn + off);
+    out[0] = h[0]; out[1] = h[1]; out[2] = h[2]; out[3] = h[3];
+    out[4] = l[0]; out[5] = l[1]; out[6] = l[2]; out[7] = l[3];
+  };
   auto load = [&](int c) {
     const bool left = c < nL;
     const int k0 = (left ? c : c - nL) * KC;
@@ -339,7 +351,9 @@ __device__ __forceinline__ void modeprod_bf3_tile(const ModeProd<float>& a, int6
       const int o = tid + s * 256, m = o / KG, g = o % KG;
       const int gi = i0 + m, gk = k0 + 8 * g;
       const int valid = (gi < M) ? min(8, K - gk) : 0;
-      if (left)
+      if (left && Lhl)
+        load_hl(Lhl, (int64_t)M * M, (int64_t)(gi < M ? gi : M - 1) * M + gk, ra[s]);
+      else if (left)
         load8_row(a.L + (int64_t)gi * M + gk, valid, alL, ra[s]);
       else
         load8_row(X + (int64_t)gi * rs + gk, valid, alX, ra[s]);
@@ -351,20 +365,34 @@ __device__ __forceinline__ void modeprod_bf3_tile(const ModeProd<float>& a, int6
       const int o = tid + s * 256, n = o % TN, g = o / TN;
       const int gj = j0 + n, gk = k0 + 8 * g;
       const bool cv = gj < Nc;
+      if (!left && Rhl) {
+        load_hl(Rhl, (int64_t)Nc * Nc, (int64_t)(cv ? gj : Nc - 1) * Nc + gk, rb[s]);
+      } else {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int kk = gk + u;
-        const bool v = cv && kk < K;
-        rb[s][u] = v ? (left ? X[(int64_t)kk * rs + gj] : a.R[(int64_t)kk * Nc + gj]) : 0.f;
+        for (int u = 0; u < 8; ++u) {
+          const int kk = gk + u;
+          const bool v = cv && kk < K;
+          rb[s][u] = v ? (left ? X[(int64_t)kk * rs + gj] : a.R[(int64_t)kk * Nc + gj]) : 0.f;
+        }
       }
     }
   };
-  auto store = [&]() {
+  // stage the chunk loaded for chunk c
+  auto store = [&](int c) {
+    const bool left = c < nL;
 #pragma unroll
     for (int s = 0; s < OA; ++s) {
       const int o = tid + s * 256, m = o / KG, g = o % KG;
       bf8 hi, lo;
-      split8(ra[s], hi, lo);
+      if (left && Lhl) {
+        const bool in = i0 + m < M;
+        const f4 h = {ra[s][0], ra[s][1], ra[s][2], ra[s][3]};
+        const f4 l = {ra[s][4], ra[s][5], ra[s][6], ra[s][7]};
+        hi = in ? __builtin_bit_cast(bf8, h) : bf8{};
+        lo = in ? __builtin_bit_cast(bf8, l) : bf8{};
+      } else {
+        split8(ra[s], hi, lo);
+      }
       *(bf8*)&Ah[m][8 * g] = hi;
       *(bf8*)&Al[m][8 * g] = lo;
     }
@@ -372,7 +400,15 @@ __device__ __forceinline__ void modeprod_bf3_tile(const ModeProd<float>& a, int6
     for (int s = 0; s < OB; ++s) {
       const int o = tid + s * 256, n = o % TN, g = o / TN;
       bf8 hi, lo;
-      split8(rb[s], hi, lo);
+      if (!left && Rhl) {
+        const bool in = j0 + n < Nc;
+        const f4 h = {rb[s][0], rb[s][1], rb[s][2], rb[s][3]};
+        const f4 l = {rb[s][4], rb[s][5], rb[s][6], rb[s][7]};
+        hi = in ? __builtin_bit_cast(bf8, h) : bf8{};
+        lo = in ? __builtin_bit_cast(bf8, l) : bf8{};
+      } else {
+        split8(rb[s], hi, lo);
+      }
       *(bf8*)&Bh[n][8 * g] = hi;
       *(bf8*)&Bl[n][8 * g] = lo;
     }
@@ -380,7 +416,7 @@ __device__ __forceinline__ void modeprod_bf3_tile(const ModeProd<float>& a, int6
 
   if (nchunks > 0) {
     load(0);
-    store();
+    store(0);
   }
   __syncthreads();
   const int lr = lane & 15, lk = lane >> 4;
@@ -410,7 +446,7 @@ __device__ __forceinline__ void modeprod_bf3_tile(const ModeProd<float>& a, int6
     }
     __syncthreads();
     if (c + 1 < nchunks) {
-      store();
+      store(c + 1);
       __syncthreads();
     }
   }

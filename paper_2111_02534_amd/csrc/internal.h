@@ -113,6 +113,15 @@ struct tp3b_op_s {
   // else heuristic
   int tile_override = -1;
   int tuned[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
+  // FP32 mode operators split into bf16 hi and lo once for the BF16x3 products
+  // (device, 2 n^2 values each): left operands in their own layout, right
+  // operands transposed
+  struct Bf3Split {
+    const float* src;
+    int n;
+    unsigned short* hl;
+  };
+  std::vector<Bf3Split> bf3L, bf3R;
 };
 
 namespace tp3b {

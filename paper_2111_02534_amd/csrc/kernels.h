@@ -34,6 +34,12 @@ struct ModeProd {
   double sigma;
   int epi;
   int acc;
+  // BF16x3 only (optional): the constant operands split into bf16 hi and lo
+  // once (raw bits, the n x n hi block followed by the lo block): L in its own
+  // layout and R transposed (k contiguous), as launch_bf3_split writes them.
+  // NULL: the operand is split while it is staged.
+  const unsigned short* Lhl;
+  const unsigned short* Rhl;
 };
 
 // Tile configurations (output tile TM x TN per 256-thread workgroup; the
@@ -68,6 +74,11 @@ hipError_t launch_modeprod(const ModeProd<T>& a, int tile, hipStream_t s);
 // The same product on FP32 data with BF16x3 split products on the bf16 matrix
 // cores (FP32 accumulation); tiles TILE_32 and TILE_32W8 run as TILE_64.
 hipError_t launch_modeprod_bf3(const ModeProd<float>& a, int tile, hipStream_t s);
+// Splits the n x n FP32 matrix A (row-major) into bf16 hi and lo, each element
+// as the BF16x3 kernels split it while staging (hi = bf16(a), lo = bf16(a - hi)):
+// out[0, n^2) = hi, out[n^2, 2 n^2) = lo, element (i, k) at i n + k, with
+// (i, k) of A itself or, with transpose, of A^T.
+hipError_t launch_bf3_split(int n, const float* A, int transpose, unsigned short* out, hipStream_t s);
 
 // C (p x q, column-major, ldc) = A^T B, A: N x p (lda), B: N x q (ldb), FP64
 // accumulation; `partial` is device scratch of at least dot_scratch_doubles().

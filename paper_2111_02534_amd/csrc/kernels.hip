@@ -128,6 +128,29 @@ static void launch_role_bf3(const ModeProd<float>& a, int tile, hipStream_t s, u
   }
 }
 
+// hi / lo of each element with the expressions of split8 (device_bodies.h), so
+// the staged values are the same whichever side splits them
+__global__ __launch_bounds__(256) void k_bf3_split(int n, const float* __restrict__ A, int transpose,
+                                                   unsigned short* __restrict__ out) {
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nn; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / n, k = e - i * n;
+    const float f = transpose ? A[k * n + i] : A[i * n + k];
+    const __bf16 h = (__bf16)f;
+    const __bf16 l = (__bf16)(f - (float)h);
+    out[e] = __builtin_bit_cast(unsigned short, h);
+    out[nn + e] = __builtin_bit_cast(unsigned short, l);
+  }
+}
+
+hipError_t launch_bf3_split(int n, const float* A, int transpose, unsigned short* out, hipStream_t s) {
+  if (n <= 0 || !A || !out) return hipErrorInvalidValue;
+  const int64_t nn = (int64_t)n * n;
+  const unsigned g = (unsigned)std::min<int64_t>((nn + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_bf3_split, dim3(g), dim3(256), 0, s, n, A, transpose, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_modeprod_bf3(const ModeProd<float>& a, int tile, hipStream_t s) {
   if (a.M <= 0 || a.Nc <= 0 || a.nbatch <= 0) return hipSuccess;
   if (tile < 0 || tile >= NUM_TILE_CFGS) return hipErrorInvalidValue;

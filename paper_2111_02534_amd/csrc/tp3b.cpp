@@ -333,11 +333,47 @@ int op_tile(tp3b_op op, bool f64, bool bf3, int kind, int64_t nbatch) {
 }
 
 // One mode-product launch in the requested arithmetic.
-static hipError_t modeprod(const ModeProd<double>& a, int tile, hipStream_t s, bool) {
+static hipError_t modeprod(tp3b_op, const ModeProd<double>& a, int tile, hipStream_t s, bool) {
   return launch_modeprod(a, tile, s);
 }
-static hipError_t modeprod(const ModeProd<float>& a, int tile, hipStream_t s, bool bf3) {
-  return bf3 ? launch_modeprod_bf3(a, tile, s) : launch_modeprod(a, tile, s);
+// The pre-split form of a constant operand (bf3_split_ops), or NULL.
+static const unsigned short* bf3_split_of(const std::vector<tp3b_op_s::Bf3Split>& v, const float* m,
+                                          int n) {
+  for (const auto& e : v)
+    if (e.src == m && e.n == n) return e.hl;
+  return nullptr;
+}
+static hipError_t modeprod(tp3b_op op, const ModeProd<float>& a, int tile, hipStream_t s, bool bf3) {
+  if (!bf3) return launch_modeprod(a, tile, s);
+  ModeProd<float> b = a;
+  b.Lhl = a.L ? bf3_split_of(op->bf3L, a.L, a.M) : nullptr;
+  b.Rhl = a.R ? bf3_split_of(op->bf3R, a.R, a.Nc) : nullptr;
+  return launch_modeprod_bf3(b, tile, s);
+}
+
+// BF16x3 products split their constant operands once: each FP32 mode operator
+// that serves as a left operand (K, S^{-1}, S) in its own layout, each that serves
+// as a right operand (K^T, S^{-T}, S^T) transposed, for modes whose size is a
+// multiple of 32 (the K chunk of the BF16x3 tiles, so every octet a tile reads
+// lies inside the matrix).
+static tp3b_status bf3_split_ops(tp3b_op op) {
+  const tp3b::DevOps<float>& d = op->d32;
+  for (int k = 0; k < op->nmodes; ++k) {
+    const int n = op->n[k];
+    if (n % 32 != 0) continue;
+    const float* lefts[] = {d.K[k], d.Si[k], d.S[k]};
+    const float* rights[] = {d.KT[k], d.SiT[k], d.ST[k]};
+    for (int side = 0; side < 2; ++side)
+      for (const float* m : side == 0 ? lefts : rights) {
+        if (!m) continue;
+        unsigned short* hl = nullptr;
+        TP3B_HIP(hipMalloc(&hl, sizeof(unsigned short) * 2 * (size_t)n * n));
+        (side == 0 ? op->bf3L : op->bf3R).push_back({m, n, hl});
+        TP3B_HIP(tp3b::launch_bf3_split(n, m, side, hl, nullptr));
+      }
+  }
+  TP3B_HIP(hipDeviceSynchronize());
+  return TP3B_OK;
 }
 
 template <>
@@ -371,7 +407,7 @@ tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, in
     a.shifts = shifts;
     a.epi = EPI_V;
     a.acc = 0;
-    TP3B_HIP(modeprod(a, tile_for(op, f64, bf3, 0, a.M, a.Nc, nvec), s, bf3));
+    TP3B_HIP(modeprod(op, a, tile_for(op, f64, bf3, 0, a.M, a.Nc, nvec), s, bf3));
     return TP3B_OK;
   }
   const int nx1 = op->n[0], nx2 = op->n[1], ny1 = op->n[2], ny2 = op->n[3];
@@ -445,7 +481,7 @@ tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, in
     a.epi = EPI_V;
     a.acc = 0;
     int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, a.nbatch, f64);
-    TP3B_HIP(modeprod(a, tile, s, bf3));
+    TP3B_HIP(modeprod(op, a, tile, s, bf3));
   }
   {
     ModeProd<T> a{};
@@ -464,7 +500,7 @@ tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, in
     a.epi = EPI_NONE;
     a.acc = 1;
     int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, a.nbatch, f64);
-    TP3B_HIP(modeprod(a, tile, s, bf3));
+    TP3B_HIP(modeprod(op, a, tile, s, bf3));
   }
   {
     ModeProd<T> a{};
@@ -483,7 +519,7 @@ tp3b_status apply_H_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y, in
     a.epi = EPI_NONE;
     a.acc = 1;
     int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, a.nbatch, f64);
-    TP3B_HIP(modeprod(a, tile, s, bf3));
+    TP3B_HIP(modeprod(op, a, tile, s, bf3));
   }
   return TP3B_OK;
 }
@@ -612,7 +648,7 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
           a.sigma = op->sigma;
         }
         const int tile = op->tile_override >= 0 ? op->tile_override : choose_tile(a.M, a.Nc, a.nbatch, f64);
-        TP3B_HIP(modeprod(a, tile, s, bf3));
+        TP3B_HIP(modeprod(op, a, tile, s, bf3));
         return TP3B_OK;
       };
       T* W = d.work;
@@ -647,19 +683,19 @@ tp3b_status apply_prec_impl(tp3b_op op, int nvec, const T* X, int64_t ldx, T* Y,
     // 1: W = Sx^{-1} B
     a.X = Xc; a.ldx = ldx; a.Y = d.work; a.ldy = N;
     a.L = d.Si[0]; a.R = nullptr; a.epi = EPI_NONE;
-    TP3B_HIP(modeprod(a, tile, s, bf3));
+    TP3B_HIP(modeprod(op, a, tile, s, bf3));
     // 2: Y = (W Sy^{-T}) / (lx_i + ly_j - sigma)
     a.X = d.work; a.ldx = N; a.Y = Yc; a.ldy = ldy;
     a.L = nullptr; a.R = d.SiT[1]; a.epi = EPI_DIV; a.lamL = d.lam[0]; a.lamR = d.lam[1];
-    TP3B_HIP(modeprod(a, tile, s, bf3));
+    TP3B_HIP(modeprod(op, a, tile, s, bf3));
     // 3: W = Sx Y
     a.X = Yc; a.ldx = ldy; a.Y = d.work; a.ldy = N;
     a.L = d.S[0]; a.R = nullptr; a.epi = EPI_NONE;
-    TP3B_HIP(modeprod(a, tile, s, bf3));
+    TP3B_HIP(modeprod(op, a, tile, s, bf3));
     // 4: Y = W Sy^T
     a.X = d.work; a.ldx = N; a.Y = Yc; a.ldy = ldy;
     a.L = nullptr; a.R = d.ST[1]; a.epi = EPI_NONE;
-    TP3B_HIP(modeprod(a, tile, s, bf3));
+    TP3B_HIP(modeprod(op, a, tile, s, bf3));
   }
   return TP3B_OK;
 }
@@ -1121,6 +1157,7 @@ tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* ou
     }
     tp3b_status st = upload_ops<double>(op, op->d64, Kh, pf);
     if (st == TP3B_OK) st = upload_ops<float>(op, op->d32, Kh, pf);
+    if (st == TP3B_OK) st = bf3_split_ops(op);
     if (st != TP3B_OK) {
       std::string msg = g_err;
       tp3b_destroy(op);
@@ -1138,6 +1175,8 @@ tp3b_status tp3b_destroy(tp3b_op op) {
     if (!op) return TP3B_OK;
     free_ops(op->d64);
     free_ops(op->d32);
+    for (const auto* v : {&op->bf3L, &op->bf3R})
+      for (const auto& e : *v) (void)hipFree(e.hl);
     delete op;
     return TP3B_OK;
   } catch (...) {
