@@ -358,14 +358,17 @@ __device__ __forceinline__ void modeprod_bf3_tile(const ModeProd<float>& a, int6
       else
         load8_row(X + (int64_t)gi * rs + gk, valid, alX, ra[s]);
     }
+    // B octets of a pre-split right operand go to lanes as the A octets do
+    // (consecutive lanes, consecutive octets of one row of R^T); split ones
+    // to consecutive columns, read down the column
+    const bool preB = !left && Rhl;
 #pragma unroll
     for (int s = 0; s < OB; ++s) {
-      // B octet: column n, k = k0 + 8g .. +7, read down a column (coalesced
-      // across the lanes, which hold consecutive n)
-      const int o = tid + s * 256, n = o % TN, g = o / TN;
+      // B octet: column n, k = k0 + 8g .. +7
+      const int o = tid + s * 256, n = preB ? o / KG : o % TN, g = preB ? o % KG : o / TN;
       const int gj = j0 + n, gk = k0 + 8 * g;
       const bool cv = gj < Nc;
-      if (!left && Rhl) {
+      if (preB) {
         load_hl(Rhl, (int64_t)Nc * Nc, (int64_t)(cv ? gj : Nc - 1) * Nc + gk, rb[s]);
       } else {
 #pragma unroll
@@ -396,11 +399,12 @@ __device__ __forceinline__ void modeprod_bf3_tile(const ModeProd<float>& a, int6
       *(bf8*)&Ah[m][8 * g] = hi;
       *(bf8*)&Al[m][8 * g] = lo;
     }
+    const bool preB = !left && Rhl;
 #pragma unroll
     for (int s = 0; s < OB; ++s) {
-      const int o = tid + s * 256, n = o % TN, g = o / TN;
+      const int o = tid + s * 256, n = preB ? o / KG : o % TN, g = preB ? o % KG : o / TN;
       bf8 hi, lo;
-      if (!left && Rhl) {
+      if (preB) {
         const bool in = j0 + n < Nc;
         const f4 h = {rb[s][0], rb[s][1], rb[s][2], rb[s][3]};
         const f4 l = {rb[s][4], rb[s][5], rb[s][6], rb[s][7]};
