@@ -107,7 +107,10 @@ typedef struct {
 
 /* Creates an operator: builds the second-derivative matrices, the potential
  * table, the preconditioner's eigen-factors of every mode and uploads them to
- * the current HIP device.  Synchronous.  *out receives the handle. */
+ * the current HIP device (in FP64 and FP32, and for modes whose size is a
+ * multiple of 32 also split into bf16 hi and lo for the BF16x3 products: 4 n^2
+ * bytes for each of the mode's six n x n matrices, 24 n^2 per mode).
+ * Synchronous.  *out receives the handle. */
 tp3b_status tp3b_create(const tp3b_problem_desc* desc, void* stream, tp3b_op* out);
 tp3b_status tp3b_destroy(tp3b_op op);
 
